@@ -1,0 +1,211 @@
+/*
+ * grmhd.h -- C ABI of libgrmhd.so: one Runge-Kutta stage of the 3+1 Valencia
+ * GRMHD finite-volume update on MeshBlocks, on one MI355X (gfx950), FP64.
+ *
+ * Method (arXiv 2409.10384):
+ *   conserved variables D~, S~_i, tau~ from (rho, W v^i, P, B^i)   Sec. II, Eq. 7-8
+ *   fluxes                                                         Sec. II, Eq. 9
+ *   metric source terms                                            Sec. II, Eq. 10
+ *   reconstruction (donor cell, WENOZ) of rho, W v^i, P; HLLE/LLF   Sec. III-B
+ *   upwind constrained transport of the face field B~               Sec. III-B
+ *   atmosphere floors, FOFC, FOFC+DMP (relaxed maximum principle)   Sec. III-C, Eq. 11-12
+ *   conservative-to-primitive inversion (Kastaun et al. master
+ *   function in mu = 1/(hW)), ideal gas and hybrid piecewise
+ *   polytrope EOS                                                   Sec. III-D
+ *
+ * Conventions for every entry point:
+ *   - Memory: every array pointer is DEVICE memory owned by the caller (for
+ *     instance a torch tensor).  The library never allocates on these paths;
+ *     it borrows the pointers for the duration of the enqueued work.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Every call is asynchronous with respect to the host.
+ *   - Errors: 0 on success; a negative GRMHD_E* code for a synchronous
+ *     argument or launch error (nothing is enqueued after an argument error).
+ *     Per-cell physics failures are never errors: they follow the atmosphere
+ *     policy of Sec. III-C and are reported in the per-cell flag bits below.
+ *   - Layout: structure of arrays, double precision, index
+ *     ((k * sy + j) * sx + i), i fastest, padded with ng ghost layers:
+ *     sx = nx + 2 ng, sy = ny + 2 ng, sz = nz + 2 ng.  Face arrays of
+ *     direction d carry one more entry along d (face i = lower face of cell i):
+ *     x-faces (sz, sy, sx+1), y-faces (sz, sy+1, sx), z-faces (sz+1, sy, sx).
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRMHD_OK 0
+#define GRMHD_EINVAL (-1)       /* bad argument (size, pointer, option) */
+#define GRMHD_EHIP (-2)         /* a HIP launch or runtime call failed */
+#define GRMHD_EUNSUPPORTED (-3) /* option not implemented */
+
+/* per-cell flag bits (uint16) */
+#define GRMHD_F_C2P_FAIL        (1u << 0)  /* inversion failed -> atmosphere */
+#define GRMHD_F_DFLOOR          (1u << 1)  /* D below f_thr rho_atm -> atmosphere */
+#define GRMHD_F_TAUFLOOR        (1u << 2)  /* tau raised to tau_atm(D, B) */
+#define GRMHD_F_MAGCAP          (1u << 3)  /* D raised to B^2 / M_max */
+#define GRMHD_F_TFLOOR          (1u << 4)  /* T raised to T_atm, rho and W v kept */
+#define GRMHD_F_RHOFLOOR        (1u << 5)  /* rho below threshold after inversion */
+#define GRMHD_F_FOFC            (1u << 6)  /* trial state needed a floor/failed */
+#define GRMHD_F_DMP             (1u << 7)  /* trial D~ or tau~ broke Eq. 12 */
+#define GRMHD_F_BRACKET_FALLBACK (1u << 8) /* learned bracket missed -> full bracket */
+#define GRMHD_F_MAXIT           (1u << 9)  /* root solve hit the iteration cap */
+
+/* Method options (Sec. III-B..III-D). */
+typedef struct grmhd_params {
+  double gamma;       /* ideal-gas adiabatic index, P = (gamma-1) rho eps */
+  double rho_b[3];    /* hybrid EOS: dividing densities of the cold pieces */
+  double K0;          /* hybrid EOS: polytropic constant of the first piece */
+  double Gam[4];      /* hybrid EOS: index of each cold piece */
+  double gamma_th;    /* hybrid EOS: thermal index */
+  double rho_atm;     /* atmosphere density */
+  double T_atm;       /* atmosphere temperature (T = P/rho ideal; P_th/rho hybrid) */
+  double f_thr;       /* density threshold factor of the floors */
+  double M_max;       /* magnetisation cap on B^2/D */
+  double dmp_M;       /* <= 0: plain FOFC; > 0: FOFC+DMP with factor M (Eq. 12) */
+  double c2p_tol;     /* relative bracket tolerance of the root solve */
+  int32_t eos;        /* 0 ideal gas, 1 hybrid piecewise polytrope + thermal */
+  int32_t npieces;    /* hybrid: cold pieces, 1..4 */
+  int32_t recon;      /* 0 donor cell, 2 WENOZ */
+  int32_t riemann;    /* 0 LLF, 1 HLLE */
+  int32_t fofc;       /* 0 off, 1 on */
+  int32_t c2p_maxit;  /* iteration cap of the root solve */
+} grmhd_params;
+
+/* One MeshBlock.  Every pointer is device memory; arrays are padded. */
+typedef struct grmhd_block {
+  int32_t nx, ny, nz, ng;  /* interior cells per axis, ghost layers (ng = 3) */
+  double dx[3];            /* cell size per axis */
+  double *w[5];            /* stage-input primitives rho, W v^x, W v^y, W v^z, P */
+  double *un[5];           /* U^n: D~, S~_x, S~_y, S~_z, tau~ (interior read) */
+  double *us[5];           /* U^(s), the stage input (ghosts read by the DMP) */
+  double *bn[3];           /* B~^n on x-, y-, z-faces */
+  double *bs[3];           /* B~^(s) on faces (stage input) */
+  const double *adm[16];   /* alpha, beta^x..z, gamma_xx xy xz yy yz zz, K_xx..zz */
+  double *uo[5];           /* output U (may alias un) */
+  double *bo[3];           /* output faces (may alias bn) */
+  double *wo[5];           /* output primitives */
+  uint16_t *flags;         /* per-cell flag bits, padded */
+  double *scratch;         /* grmhd_scratch_doubles(...) doubles of workspace */
+  int32_t nbr[27];         /* neighbour block per offset (ox+1)+3(oy+1)+9(oz+1); -1: none */
+  int32_t bc;              /* 0 ghosts frozen (untouched); 1 filled from nbr, outflow if -1 */
+} grmhd_block;
+
+/* Doubles of per-block scratch needed by the stage: the 21 face-flux arrays
+   (7 components D~, S~_xyz, tau~, F(B~^{t1}), F(B~^{t2}) per direction, t1 =
+   (d+1)%3, t2 = (d+2)%3), the cell-centred field B^i = B~_cc/sqrt(gamma)
+   (3 cell arrays), the cell-centre EMF (3 cell arrays) and the corner EMFs
+   (3 arrays of (sx+1)(sy+1)(sz+1)).  Flux d, component c starts at
+   grmhd_flux_offset(...) doubles into scratch. */
+int64_t grmhd_scratch_doubles(int32_t nx, int32_t ny, int32_t nz, int32_t ng);
+int64_t grmhd_flux_offset(int32_t nx, int32_t ny, int32_t nz, int32_t ng, int32_t d, int32_t c);
+
+/*
+ * Every block-list entry point takes the descriptor table twice: blk_h in
+ * host memory (launch geometry and validation) and blk_d, the same table in
+ * device memory (read by the kernels).  nblk >= 1.  The RK coefficients give
+ * U^out = a0 U^n + a1 U^(s) + b dt L(U^(s)); SSP-RK2 in Shu-Osher form is
+ * (0, 1, 1) then (1/2, 1/2, 1/2).  dt is read from the device scalar dt_d
+ * when dt_d != NULL, else the host value dt is used.
+ */
+
+/* Steps a1-a8 of one stage (Sec. III-B..III-D): face fluxes (reconstruction,
+   face metric, floors, Eq. 7-9, HLLE/LLF), FOFC(+DMP) flags with exchange of
+   flags between blocks and donor-cell refluxing, upwind CT of the faces,
+   update with the Eq. 10 sources, C2P with atmosphere floors.  Writes uo,
+   bo, wo, flags.  Ghost cells of the outputs are not filled. */
+int grmhd_stage(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
+                double b, void *stream);
+
+/* Steps a2-a3 alone: high-order face fluxes into each block's scratch. */
+int grmhd_fluxes(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                 const grmhd_params *p, void *stream);
+
+/* Step a4 (Sec. III-C, FOFC and Eq. 12): from the fluxes in scratch, the
+   trial state without sources or CT, the trial inversion, the DMP test, the
+   flag exchange between blocks, and donor-cell refluxing of every face of a
+   flagged cell (all 7 components).  Writes flags and the fluxes in scratch. */
+int fofc_correct(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                 const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
+                 double b, void *stream);
+
+/* Step a5 (Sec. III-B): upwind constrained transport.  Corner EMFs from the
+   face EMFs in scratch and the cell-centre EMF of the stage input, then
+   bo = a0 bn + a1 bs - b dt curl(E) on the interior faces. */
+int ct_update(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+              const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
+              double b, void *stream);
+
+/* Step a6 (Eq. 10): uo = a0 un + a1 us + b dt (-div F + G(w, us, ADM)). */
+int grmhd_update(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                 const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
+                 double b, void *stream);
+
+/* Step a8 on the interior of every block: uo, bo -> wo with the floors;
+   OR-s the inversion flags into flags. */
+int grmhd_stage_c2p(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                    const grmhd_params *p, void *stream);
+
+/* Ghost fill (same-level copy / periodic self-neighbour / outflow) of the
+   arrays in the w (mask 1), us (2), bs (4) and flags (8) slots.  Blocks with
+   bc == 0 keep their ghosts. */
+int grmhd_ghost_fill(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                     int32_t mask, void *stream);
+
+/* Step a9: dt_out[0] = cfl / max over interior cells and directions of
+   |lambda_+-| / dx_d from the w and bs slots (fast magnetosonic speeds).
+   red: device scratch of one double (overwritten). */
+int grmhd_dt(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+             const grmhd_params *p, double cfl, double *red, double *dt_out, void *stream);
+
+/* Baryon mass sum D~ dV over the interiors of the us slot (deterministic
+   order).  partial: device scratch of nblk doubles; out: one device double. */
+int grmhd_mass(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+               double *partial, double *out, void *stream);
+
+/* Eq. 7 over every padded cell of each block: us <- prim2con(w, B~_cc(bs)),
+   B~_cc the face average of the bs slot.  Initialises the conserved state. */
+int grmhd_prim2con_blocks(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                          const grmhd_params *p, void *stream);
+
+/* Eq. 7 at n points (densitized): w (rho, W v^i, P), bt densitized B~^i,
+   gam (gamma_xx xy xz yy yz zz) -> u (D~, S~_i, tau~).  Arrays of n doubles. */
+int prim2con(int64_t n, double *const w[5], double *const bt[3], double *const gam[6],
+             double *u[5], const grmhd_params *p, void *stream);
+
+/* Learned guess and bracket for the inversion (not in the paper): a 5-64-64-64-2
+   MLP with SiLU.  Weights are bf16 (row-major [out][in]) with fp32 biases. */
+typedef struct c2p_mlp {
+  const uint16_t *W[4];   /* bf16 weights: 64x5, 64x64, 64x64, 2x64 */
+  const float *b[4];      /* fp32 biases: 64, 64, 64, 2 */
+  float feat_mean[5], feat_scale[5];  /* feature standardisation */
+  float half_width_min;               /* lower clamp of the relative half-width */
+} c2p_mlp;
+
+/* C2P statistics accumulated by c2p_batch when stats != NULL (device). */
+typedef struct c2p_stats {
+  unsigned long long solves, evaluations, fallbacks, failures;
+} c2p_stats;
+
+/* Step a8 (Sec. III-C, III-D) at n points: u (in/out; rewritten from the
+   final primitives whenever a floor rule fires), bt densitized field, gam ->
+   w, flags.  mlp != NULL: the learned guess and bracket start the same FP64
+   root solve (fallback to the full bracket, bit 8).  mu_out, nev_out may be
+   NULL (root and master-function evaluations per point). */
+int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6], double *w[5],
+              uint16_t *flags, const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
+              double *mu_out, int32_t *nev_out, void *stream);
+
+/* Library version string and the HIP device architecture it was built for. */
+const char *grmhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRMHD_H */

@@ -1,0 +1,1170 @@
+// grmhd.hip -- kernels and C-ABI entry points of libgrmhd.so (gfx950, FP64).
+//
+// One workgroup-grid per step of the stage; every grid spans all blocks
+// (blockIdx.y = block index) so a stage over many MeshBlocks costs a fixed
+// number of launches.  Thread index runs fastest along x so that every
+// stencil load of a wavefront is a contiguous row of the SoA arrays.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "grmhd.h"
+#include "physics.hpp"
+
+using namespace gk;
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------
+// block geometry helpers
+// ---------------------------------------------------------------------------
+struct Geo {
+  int nx, ny, nz, g, sx, sy, sz;
+};
+
+__host__ __device__ __forceinline__ Geo geo_of(const grmhd_block& b) {
+  Geo q;
+  q.nx = b.nx; q.ny = b.ny; q.nz = b.nz; q.g = b.ng;
+  q.sx = b.nx + 2 * b.ng; q.sy = b.ny + 2 * b.ng; q.sz = b.nz + 2 * b.ng;
+  return q;
+}
+__host__ __device__ __forceinline__ int64_t n_cells(const Geo& q) {
+  return (int64_t)q.sx * q.sy * q.sz;
+}
+__host__ __device__ __forceinline__ int64_t n_faces(const Geo& q, int d) {
+  return (int64_t)(q.sx + (d == 0)) * (q.sy + (d == 1)) * (q.sz + (d == 2));
+}
+__host__ __device__ __forceinline__ int64_t n_edges(const Geo& q) {
+  return (int64_t)(q.sx + 1) * (q.sy + 1) * (q.sz + 1);
+}
+__device__ __forceinline__ int64_t cell(const Geo& q, int i, int j, int k) {
+  return ((int64_t)k * q.sy + j) * q.sx + i;
+}
+template <int D>
+__device__ __forceinline__ int64_t face(const Geo& q, int i, int j, int k) {
+  const int ex = q.sx + (D == 0), ey = q.sy + (D == 1);
+  return ((int64_t)k * ey + j) * ex + i;
+}
+__device__ __forceinline__ int64_t face_rt(const Geo& q, int d, int i, int j, int k) {
+  const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
+  return ((int64_t)k * ey + j) * ex + i;
+}
+__device__ __forceinline__ int64_t edge(const Geo& q, int i, int j, int k) {
+  return ((int64_t)k * (q.sy + 1) + j) * (q.sx + 1) + i;
+}
+
+// scratch layout (doubles): flux[d][c] | Bcc[3] | Ecc[3] | Eedge[3]
+__host__ __device__ __forceinline__ int64_t off_flux(const Geo& q, int d, int c) {
+  int64_t o = 0;
+  for (int dd = 0; dd < d; ++dd) o += 7 * n_faces(q, dd);
+  return o + c * n_faces(q, d);
+}
+__host__ __device__ __forceinline__ int64_t off_bcc(const Geo& q) {
+  return off_flux(q, 3, 0);
+}
+__host__ __device__ __forceinline__ int64_t off_ecc(const Geo& q) {
+  return off_bcc(q) + 3 * n_cells(q);
+}
+__host__ __device__ __forceinline__ int64_t off_edge(const Geo& q) {
+  return off_ecc(q) + 3 * n_cells(q);
+}
+__host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
+  return off_edge(q) + 3 * n_edges(q);
+}
+
+// decompose a linear item index over a box [lo, lo+cnt)
+struct Box {
+  int lo[3], cnt[3];
+  __device__ __forceinline__ int64_t size() const { return (int64_t)cnt[0] * cnt[1] * cnt[2]; }
+  __device__ __forceinline__ void at(int64_t t, int& i, int& j, int& k) const {
+    i = lo[0] + (int)(t % cnt[0]);
+    const int64_t r = t / cnt[0];
+    j = lo[1] + (int)(r % cnt[1]);
+    k = lo[2] + (int)(r / cnt[1]);
+  }
+};
+
+// extended face range of direction D: faces [g, g+n_D] along D, cells
+// [g-1, g+n_t] across (one ghost column each side for the corner EMFs)
+template <int D>
+__device__ __forceinline__ Box face_box(const Geo& q) {
+  Box b;
+  const int n[3] = {q.nx, q.ny, q.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == D) { b.lo[a] = q.g; b.cnt[a] = n[a] + 1; }
+    else { b.lo[a] = q.g - 1; b.cnt[a] = n[a] + 2; }
+  }
+  return b;
+}
+__device__ __forceinline__ Box interior_box(const Geo& q) {
+  Box b;
+  b.lo[0] = b.lo[1] = b.lo[2] = q.g;
+  b.cnt[0] = q.nx; b.cnt[1] = q.ny; b.cnt[2] = q.nz;
+  return b;
+}
+
+__device__ __forceinline__ double dt_of(const double* dt_d, double dt) {
+  return dt_d ? *dt_d : dt;
+}
+
+__device__ __forceinline__ void cell_metric(const grmhd_block& b, int64_t c, M3& m) {
+  metric_build(m, b.adm[4][c], b.adm[5][c], b.adm[6][c], b.adm[7][c], b.adm[8][c], b.adm[9][c]);
+}
+
+// densitized cell-centred field from the faces of slot f
+__device__ __forceinline__ void cell_bt(const Geo& q, double* const f[3], int i, int j, int k,
+                                        double Bt[3]) {
+  Bt[0] = 0.5 * (f[0][face<0>(q, i, j, k)] + f[0][face<0>(q, i + 1, j, k)]);
+  Bt[1] = 0.5 * (f[1][face<1>(q, i, j, k)] + f[1][face<1>(q, i, j + 1, k)]);
+  Bt[2] = 0.5 * (f[2][face<2>(q, i, j, k)] + f[2][face<2>(q, i, j, k + 1)]);
+}
+
+// ---------------------------------------------------------------------------
+// a1: cell-centred un-densitized field B^i = B~_cc / sqrt(gamma), all cells
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_bcc(const grmhd_block* __restrict__ blks) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cells(q)) return;
+  const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
+  // face i+1 exists for every cell of the padded block
+  M3 m;
+  cell_metric(b, t, m);
+  double Bt[3];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  double* out = b.scratch + off_bcc(q);
+  const int64_t nc = n_cells(q);
+  const double is = 1.0 / m.sg;
+  out[t] = Bt[0] * is;
+  out[nc + t] = Bt[1] * is;
+  out[2 * nc + t] = Bt[2] * is;
+}
+
+// ---------------------------------------------------------------------------
+// a2 + a3: flux through one face of direction D
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
+                                          const grmhd_block& b, const Geo& q, int i, int j, int k,
+                                          int order, double F[7]) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
+  const int64_t c0 = cell(q, i, j, k);
+  // metric at the face: 4th-order Lagrange (-1, 9, 9, -1)/16
+  double gf[10];
+#pragma unroll
+  for (int n = 0; n < 10; ++n) {
+    const double* a = b.adm[n];
+    gf[n] = (9.0 * (a[c0 - st] + a[c0]) - (a[c0 - 2 * st] + a[c0 + st])) * (1.0 / 16.0);
+  }
+  M3 m;
+  metric_build(m, gf[4], gf[5], gf[6], gf[7], gf[8], gf[9]);
+  const double* bcc = b.scratch + off_bcc(q);
+  const int64_t nc = n_cells(q);
+  const double* bt1 = bcc + T1 * nc;
+  const double* bt2 = bcc + T2 * nc;
+  double qL[7], qR[7];
+  if (order == 0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      qL[v] = b.w[v][c0 - st];
+      qR[v] = b.w[v][c0];
+    }
+    qL[5] = bt1[c0 - st]; qR[5] = bt1[c0];
+    qL[6] = bt2[c0 - st]; qR[6] = bt2[c0];
+  } else {
+    const double* src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const double* a = src[v];
+      const double m3 = a[c0 - 3 * st], m2 = a[c0 - 2 * st], m1 = a[c0 - st];
+      const double p0 = a[c0], p1 = a[c0 + st], p2 = a[c0 + 2 * st];
+      qL[v] = wenoz(m3, m2, m1, p0, p1);
+      qR[v] = wenoz(p2, p1, p0, m1, m2);
+    }
+  }
+  floor_face(e, p, qL);
+  floor_face(e, p, qR);
+  const double Bn = b.bs[D][face<D>(q, i, j, k)] / m.sg;
+  double BL[3], BR[3];
+  BL[D] = Bn; BR[D] = Bn;
+  BL[T1] = qL[5]; BL[T2] = qL[6];
+  BR[T1] = qR[5]; BR[T2] = qR[6];
+  const double beta[3] = {gf[1], gf[2], gf[3]};
+  Side L, R;
+  side_state<D>(e, m, gf[0], beta, qL, BL, L);
+  side_state<D>(e, m, gf[0], beta, qR, BR, R);
+  riemann(p.riemann, L, R, F);
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e,
+                                                   grmhd_params p) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = face_box<D>(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  double F[7];
+  face_flux<D>(e, p, b, q, i, j, k, p.recon, F);
+  const int64_t f = face<D>(q, i, j, k);
+  const int64_t nf = n_faces(q, D);
+  double* out = b.scratch + off_flux(q, D, 0);
+#pragma unroll
+  for (int c = 0; c < 7; ++c) out[c * nf + f] = F[c];
+}
+
+// ---------------------------------------------------------------------------
+// a4: FOFC flags (trial state, trial inversion, relaxed DMP of Eq. 12)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_clear_flags(const grmhd_block* __restrict__ blks) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_cells(q)) b.flags[t] = 0;
+}
+
+__device__ __forceinline__ void dmp_range(double mn, double mx, double M, double& lo, double& hi) {
+  lo = mn >= 0.0 ? mn / M : mn * M;
+  hi = mx >= 0.0 ? mx * M : mx / M;
+}
+
+__device__ __forceinline__ double flux_div(const grmhd_block& b, const Geo& q, int v, int i, int j,
+                                           int k) {
+  const double* fx = b.scratch + off_flux(q, 0, v);
+  const double* fy = b.scratch + off_flux(q, 1, v);
+  const double* fz = b.scratch + off_flux(q, 2, v);
+  return (fx[face<0>(q, i + 1, j, k)] - fx[face<0>(q, i, j, k)]) / b.dx[0] +
+         (fy[face<1>(q, i, j + 1, k)] - fy[face<1>(q, i, j, k)]) / b.dx[1] +
+         (fz[face<2>(q, i, j, k + 1)] - fz[face<2>(q, i, j, k)]) / b.dx[2];
+}
+
+__global__ __launch_bounds__(kThreads) void k_fofc_flags(const grmhd_block* __restrict__ blks,
+                                                         Eos e, grmhd_params p,
+                                                         const double* dt_d, double dt_h,
+                                                         double a0, double a1, double bb) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = interior_box(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  const double dt = dt_of(dt_d, dt_h);
+  const int64_t c = cell(q, i, j, k);
+  double U[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) U[v] = a0 * b.un[v][c] + a1 * b.us[v][c] - bb * dt * flux_div(b, q, v, i, j, k);
+  uint32_t fl = 0;
+  if (p.dmp_M > 0.0) {
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const int v = t2 == 0 ? 0 : 4;
+      const double* a = b.us[v];
+      double mn = a[c], mx = a[c];
+      for (int dk = -1; dk <= 1; ++dk)
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 1; ++di) {
+            const double x = a[cell(q, i + di, j + dj, k + dk)];
+            mn = fmin(mn, x);
+            mx = fmax(mx, x);
+          }
+      double lo, hi;
+      dmp_range(mn, mx, p.dmp_M, lo, hi);
+      if (!(U[v] >= lo && U[v] <= hi)) fl |= GRMHD_F_DMP;
+    }
+  }
+  M3 m;
+  cell_metric(b, c, m);
+  double Bt[3], w[5];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  int nev;
+  double mu;
+  const uint32_t r = c2p_cell(e, p, m, U, Bt, w, false, 0.0, 0.0, nev, mu);
+  if (r & kFloorBits) fl |= GRMHD_F_FOFC;
+  b.flags[c] = (uint16_t)fl;
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e,
+                                                       grmhd_params p) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = face_box<D>(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
+  const int64_t c = cell(q, i, j, k);
+  const uint32_t fl = (uint32_t)b.flags[c] | (uint32_t)b.flags[c - st];
+  if (!(fl & (GRMHD_F_FOFC | GRMHD_F_DMP))) return;
+  double F[7];
+  face_flux<D>(e, p, b, q, i, j, k, 0, F);
+  const int64_t f = face<D>(q, i, j, k);
+  const int64_t nf = n_faces(q, D);
+  double* out = b.scratch + off_flux(q, D, 0);
+#pragma unroll
+  for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
+}
+
+// ---------------------------------------------------------------------------
+// a5: upwind constrained transport
+// ---------------------------------------------------------------------------
+// cell-centre EMF E = -alpha (vhat x B~) on cells [g-1, g+n]
+__global__ __launch_bounds__(kThreads) void k_emf_cc(const grmhd_block* __restrict__ blks) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  Box bx;
+  bx.lo[0] = bx.lo[1] = bx.lo[2] = q.g - 1;
+  bx.cnt[0] = q.nx + 2; bx.cnt[1] = q.ny + 2; bx.cnt[2] = q.nz + 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  const int64_t c = cell(q, i, j, k);
+  M3 m;
+  cell_metric(b, c, m);
+  const double al = b.adm[0][c];
+  const double ux = b.w[1][c], uy = b.w[2][c], uz = b.w[3][c];
+  double lx, ly, lz;
+  lower(m.g, ux, uy, uz, lx, ly, lz);
+  const double iW = 1.0 / sqrt(1.0 + ux * lx + uy * ly + uz * lz);
+  const double ia = 1.0 / al;
+  const double vx = ux * iW - b.adm[1][c] * ia;
+  const double vy = uy * iW - b.adm[2][c] * ia;
+  const double vz = uz * iW - b.adm[3][c] * ia;
+  double Bt[3];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  double* E = b.scratch + off_ecc(q);
+  const int64_t nc = n_cells(q);
+  E[c] = -al * (vy * Bt[2] - vz * Bt[1]);
+  E[nc + c] = -al * (vz * Bt[0] - vx * Bt[2]);
+  E[2 * nc + c] = -al * (vx * Bt[1] - vy * Bt[0]);
+}
+
+__device__ __forceinline__ double upwind(double mflux, double from_neg, double from_pos) {
+  return mflux > 0.0 ? from_neg : (mflux < 0.0 ? from_pos : 0.5 * (from_neg + from_pos));
+}
+
+// EMF component C on a face of direction FD (from the stored transverse-field fluxes)
+template <int FD, int C>
+__device__ __forceinline__ double face_emf(const double* sc, const Geo& q, int64_t f) {
+  constexpr int T1 = (FD + 1) % 3, T2 = (FD + 2) % 3;
+  static_assert(C == T1 || C == T2, "EMF component must be transverse to the face");
+  const int64_t nf = n_faces(q, FD);
+  const double* F = sc + off_flux(q, FD, 0);
+  if (C == T2) return -F[5 * nf + f];
+  return F[6 * nf + f];
+}
+
+// corner EMF of component C on the plane (A, Bx) = ((C+1)%3, (C+2)%3)
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_emf_edge(const grmhd_block* __restrict__ blks) {
+  constexpr int A = (C + 1) % 3, BX = (C + 2) % 3;
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const int n[3] = {q.nx, q.ny, q.nz};
+  Box bx;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bx.lo[a] = q.g;
+    bx.cnt[a] = a == C ? n[a] : n[a] + 1;
+  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int x[3];
+  bx.at(t, x[0], x[1], x[2]);
+  const double* sc = b.scratch;
+  // cells (a,b), (a-1,b), (a,b-1), (a-1,b-1)
+  int p00[3] = {x[0], x[1], x[2]};
+  int p10[3] = {x[0], x[1], x[2]};
+  int p01[3] = {x[0], x[1], x[2]};
+  int p11[3] = {x[0], x[1], x[2]};
+  p10[A] -= 1;
+  p01[BX] -= 1;
+  p11[A] -= 1;
+  p11[BX] -= 1;
+  const int64_t fa_b = face<A>(q, p00[0], p00[1], p00[2]);
+  const int64_t fa_bm = face<A>(q, p01[0], p01[1], p01[2]);
+  const int64_t fb_a = face<BX>(q, p00[0], p00[1], p00[2]);
+  const int64_t fb_am = face<BX>(q, p10[0], p10[1], p10[2]);
+  const double EA_b = face_emf<A, C>(sc, q, fa_b);
+  const double EA_bm = face_emf<A, C>(sc, q, fa_bm);
+  const double EB_a = face_emf<BX, C>(sc, q, fb_a);
+  const double EB_am = face_emf<BX, C>(sc, q, fb_am);
+  const double* mA = sc + off_flux(q, A, 0);
+  const double* mB = sc + off_flux(q, BX, 0);
+  const double mA_b = mA[fa_b], mA_bm = mA[fa_bm], mB_a = mB[fb_a], mB_am = mB[fb_am];
+  const double* Ec = sc + off_ecc(q) + C * n_cells(q);
+  const double E00 = Ec[cell(q, p00[0], p00[1], p00[2])];
+  const double E10 = Ec[cell(q, p10[0], p10[1], p10[2])];
+  const double E01 = Ec[cell(q, p01[0], p01[1], p01[2])];
+  const double E11 = Ec[cell(q, p11[0], p11[1], p11[2])];
+  const double db_hi = upwind(mA_b, E10 - EB_am, E00 - EB_a);
+  const double db_lo = upwind(mA_bm, EB_am - E11, EB_a - E01);
+  const double da_hi = upwind(mB_a, E01 - EA_bm, E00 - EA_b);
+  const double da_lo = upwind(mB_am, EA_bm - E11, EA_b - E10);
+  double* Ee = b.scratch + off_edge(q) + C * n_edges(q);
+  Ee[edge(q, x[0], x[1], x[2])] =
+      0.25 * (EA_b + EA_bm + EB_a + EB_am) + 0.25 * (db_lo - db_hi + da_lo - da_hi);
+}
+
+// bo = a0 bn + a1 bs - b dt (curl E)^D on the interior faces of direction D
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_ct_face(const grmhd_block* __restrict__ blks,
+                                                      const double* dt_d, double dt_h, double a0,
+                                                      double a1, double bb) {
+  constexpr int D1 = (D + 1) % 3, D2 = (D + 2) % 3;
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const int n[3] = {q.nx, q.ny, q.nz};
+  Box bx;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bx.lo[a] = q.g;
+    bx.cnt[a] = a == D ? n[a] + 1 : n[a];
+  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int x[3];
+  bx.at(t, x[0], x[1], x[2]);
+  const double dt = dt_of(dt_d, dt_h);
+  const double* Ee = b.scratch + off_edge(q);
+  const int64_t ne = n_edges(q);
+  int x1[3] = {x[0], x[1], x[2]}, x2[3] = {x[0], x[1], x[2]};
+  x1[D1] += 1;
+  x2[D2] += 1;
+  const int64_t e0 = edge(q, x[0], x[1], x[2]);
+  const double c1 = (Ee[D2 * ne + edge(q, x1[0], x1[1], x1[2])] - Ee[D2 * ne + e0]) / b.dx[D1];
+  const double c2 = (Ee[D1 * ne + edge(q, x2[0], x2[1], x2[2])] - Ee[D1 * ne + e0]) / b.dx[D2];
+  const int64_t f = face<D>(q, x[0], x[1], x[2]);
+  b.bo[D][f] = a0 * b.bn[D][f] + a1 * b.bs[D][f] - bb * dt * (c1 - c2);
+}
+
+// ---------------------------------------------------------------------------
+// a6: update with the Eq. 10 sources of the stage input
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dcen(const double* a, int64_t c, int64_t st, double idx12) {
+  return ((a[c - 2 * st] - a[c + 2 * st]) - 8.0 * (a[c - st] - a[c + st])) * idx12;
+}
+
+__global__ __launch_bounds__(kThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e,
+                                                     const double* dt_d, double dt_h, double a0,
+                                                     double a1, double bb) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = interior_box(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  const double dt = dt_of(dt_d, dt_h);
+  const int64_t c = cell(q, i, j, k);
+  const int64_t strides[3] = {1, (int64_t)q.sx, (int64_t)q.sx * q.sy};
+  M3 m;
+  cell_metric(b, c, m);
+  const double alpha = b.adm[0][c];
+  // primitive-derived quantities of the stage input
+  const double rho = b.w[0][c], P = b.w[4][c];
+  const double u[3] = {b.w[1][c], b.w[2][c], b.w[3][c]};
+  double ul[3];
+  lower(m.g, u[0], u[1], u[2], ul[0], ul[1], ul[2]);
+  const double W = sqrt(1.0 + u[0] * ul[0] + u[1] * ul[1] + u[2] * ul[2]);
+  const double iW = 1.0 / W;
+  const double v[3] = {u[0] * iW, u[1] * iW, u[2] * iW};
+  double Bt[3];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  const double is = 1.0 / m.sg;
+  const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+  double Bl[3];
+  lower(m.g, B[0], B[1], B[2], Bl[0], Bl[1], Bl[2]);
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const double Bv = (B[0] * ul[0] + B[1] * ul[1] + B[2] * ul[2]) * iW;
+  const double eps = eos_eps_from_P(e, rho, P);
+  const double h = 1.0 + eps + P / rho;
+  const double bsq = B2 * iW * iW + Bv * Bv;
+  const double Ptot = P + 0.5 * bsq;
+  const double ew = (rho * h + bsq) * W * W;
+  double bsp[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) bsp[a] = B[a] * iW + W * Bv * v[a];
+  // densitized S~^{ij} (symmetric)
+  double S[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c2 = a; c2 < 3; ++c2)
+      S[sym(a, c2)] = m.sg * (ew * v[a] * v[c2] + Ptot * m.u[sym(a, c2)] - bsp[a] * bsp[c2]);
+  double Us[5];
+#pragma unroll
+  for (int v2 = 0; v2 < 5; ++v2) Us[v2] = b.us[v2][c];
+  const double Su[3] = {m.u[0] * Us[1] + m.u[1] * Us[2] + m.u[2] * Us[3],
+                        m.u[1] * Us[1] + m.u[3] * Us[2] + m.u[4] * Us[3],
+                        m.u[2] * Us[1] + m.u[4] * Us[2] + m.u[5] * Us[3]};
+  const double Et = Us[4] + Us[0];
+  double G[5];
+  G[0] = 0.0;
+  double gt = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t st = strides[d];
+    const double idx12 = 1.0 / (12.0 * b.dx[d]);
+    const double dal = dcen(b.adm[0], c, st, idx12);
+    double t1 = 0.0;
+#pragma unroll
+    for (int s6 = 0; s6 < 6; ++s6) {
+      const double w6 = (s6 == 1 || s6 == 2 || s6 == 4) ? 2.0 : 1.0;
+      t1 += w6 * S[s6] * dcen(b.adm[4 + s6], c, st, idx12);
+    }
+    double t2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t2 += Us[1 + a] * dcen(b.adm[1 + a], c, st, idx12);
+    G[1 + d] = 0.5 * alpha * t1 + t2 - Et * dal;
+    gt -= Su[d] * dal;
+  }
+  double kS = 0.0;
+#pragma unroll
+  for (int s6 = 0; s6 < 6; ++s6) {
+    const double w6 = (s6 == 1 || s6 == 2 || s6 == 4) ? 2.0 : 1.0;
+    kS += w6 * b.adm[10 + s6][c] * S[s6];
+  }
+  G[4] = alpha * kS + gt;
+#pragma unroll
+  for (int v2 = 0; v2 < 5; ++v2)
+    b.uo[v2][c] = a0 * b.un[v2][c] + a1 * Us[v2] + bb * dt * (G[v2] - flux_div(b, q, v2, i, j, k));
+}
+
+// ---------------------------------------------------------------------------
+// a8: inversion of the updated state with the updated field
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e,
+                                                        grmhd_params p) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = interior_box(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bx.size()) return;
+  int i, j, k;
+  bx.at(t, i, j, k);
+  const int64_t c = cell(q, i, j, k);
+  M3 m;
+  cell_metric(b, c, m);
+  double U[5], Bt[3], w[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
+  cell_bt(q, b.bo, i, j, k, Bt);
+  int nev;
+  double mu;
+  const uint32_t r = c2p_cell(e, p, m, U, Bt, w, false, 0.0, 0.0, nev, mu);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    b.uo[v][c] = U[v];
+    b.wo[v][c] = w[v];
+  }
+  b.flags[c] = (uint16_t)(b.flags[c] | r);
+}
+
+// ---------------------------------------------------------------------------
+// ghost fill (same-level copy, periodic self-neighbour, outflow)
+// ---------------------------------------------------------------------------
+// source of ghost entry x[] of block ib; fd = -1 for cells, else the face
+// direction (faces g and g+n along it are interior).  Returns false if x is
+// interior.
+__device__ __forceinline__ bool ghost_src(const grmhd_block* blks, int ib, int fd, int x[3],
+                                          int& sb) {
+  const grmhd_block& b = blks[ib];
+  const int g = b.ng;
+  const int n[3] = {b.nx, b.ny, b.nz};
+  int o[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int hi = a == fd ? g + n[a] : g + n[a] - 1;   // last interior index
+    o[a] = x[a] < g ? -1 : (x[a] > hi ? 1 : 0);
+  }
+  if (!o[0] && !o[1] && !o[2]) return false;
+  // axes with no neighbour: clamp (outflow)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!o[a]) continue;
+    const int idx = (a == 0 ? o[a] + 1 : 1) + 3 * (a == 1 ? o[a] + 1 : 1) + 9 * (a == 2 ? o[a] + 1 : 1);
+    if (b.nbr[idx] < 0) {
+      const int hi = a == fd ? g + n[a] : g + n[a] - 1;
+      x[a] = o[a] < 0 ? g : hi;
+      o[a] = 0;
+    }
+  }
+  sb = ib;
+  if (o[0] || o[1] || o[2]) {
+    const int nb = b.nbr[(o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
+    if (nb < 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (!o[a]) continue;
+        const int hi = a == fd ? g + n[a] : g + n[a] - 1;
+        x[a] = o[a] < 0 ? g : hi;
+      }
+    } else if (nb == ib) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (!o[a]) continue;
+        int r = (x[a] - g) % n[a];
+        if (r < 0) r += n[a];
+        x[a] = g + r;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] -= o[a] * n[a];
+      sb = nb;
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ghost_cells(const grmhd_block* __restrict__ blks,
+                                                          int mask) {
+  const int ib = blockIdx.y;
+  const grmhd_block& b = blks[ib];
+  if (b.bc == 0) return;
+  const Geo q = geo_of(b);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cells(q)) return;
+  int x[3] = {(int)(t % q.sx), (int)((t / q.sx) % q.sy), (int)(t / ((int64_t)q.sx * q.sy))};
+  int sb;
+  if (!ghost_src(blks, ib, -1, x, sb)) return;
+  const grmhd_block& s = blks[sb];
+  const Geo qs = geo_of(s);
+  const int64_t src = cell(qs, x[0], x[1], x[2]);
+  if (mask & 1)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) b.w[v][t] = s.w[v][src];
+  if (mask & 2)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) b.us[v][t] = s.us[v][src];
+  if (mask & 8) b.flags[t] = s.flags[src];
+}
+
+__global__ __launch_bounds__(kThreads) void k_ghost_faces(const grmhd_block* __restrict__ blks,
+                                                          int d) {
+  const int ib = blockIdx.y;
+  const grmhd_block& b = blks[ib];
+  if (b.bc == 0) return;
+  const Geo q = geo_of(b);
+  const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_faces(q, d)) return;
+  int x[3] = {(int)(t % ex), (int)((t / ex) % ey), (int)(t / ((int64_t)ex * ey))};
+  int sb;
+  if (!ghost_src(blks, ib, d, x, sb)) return;
+  const grmhd_block& s = blks[sb];
+  const Geo qs = geo_of(s);
+  b.bs[d][t] = s.bs[d][face_rt(qs, d, x[0], x[1], x[2])];
+}
+
+// ---------------------------------------------------------------------------
+// a9: dt reduction (max of |lambda|/dx; order-independent, exact)
+// ---------------------------------------------------------------------------
+__global__ void k_zero1(double* x) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = 0.0;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e,
+                                                 double* red) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const Box bx = interior_box(q);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (t < bx.size()) {
+    int i, j, k;
+    bx.at(t, i, j, k);
+    const int64_t c = cell(q, i, j, k);
+    M3 m;
+    cell_metric(b, c, m);
+    const double beta[3] = {b.adm[1][c], b.adm[2][c], b.adm[3][c]};
+    double w[5], Bt[3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = b.w[v][c];
+    cell_bt(q, b.bs, i, j, k, Bt);
+    const double is = 1.0 / m.sg;
+    const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+    const double al = b.adm[0][c];
+    Side sd;
+    side_state<0>(e, m, al, beta, w, B, sd);
+    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[0]);
+    side_state<1>(e, m, al, beta, w, B, sd);
+    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[1]);
+    side_state<2>(e, m, al, beta, w, B, sd);
+    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[2]);
+  }
+  s = wave_max(s);
+  __shared__ double part[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = part[0];
+    for (int x = 1; x < kThreads / 64; ++x) r = fmax(r, part[x]);
+    // non-negative doubles order like their bit patterns
+    atomicMax((unsigned long long*)red, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+__global__ void k_dt_final(const double* red, double cfl, double* dt_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dt_out[0] = cfl / red[0];
+}
+
+// ---------------------------------------------------------------------------
+// mass: deterministic two-level sum
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_mass_block(const grmhd_block* __restrict__ blks,
+                                                         double* partial) {
+  const grmhd_block& b = blks[blockIdx.x];
+  const Geo q = geo_of(b);
+  const Box bx = interior_box(q);
+  const int64_t n = bx.size();
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+    int i, j, k;
+    bx.at(t, i, j, k);
+    s += b.us[0][cell(q, i, j, k)];
+  }
+  __shared__ double sh[kThreads];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] * (b.dx[0] * b.dx[1] * b.dx[2]);
+}
+
+__global__ void k_mass_final(const double* partial, int nblk, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int x = 0; x < nblk; ++x) s += partial[x];
+    out[0] = s;
+  }
+}
+
+// Eq. 7 over every padded cell of a block: us <- prim2con(w, B~_cc(bs))
+__global__ __launch_bounds__(kThreads) void k_p2c_block(const grmhd_block* __restrict__ blks, Eos e) {
+  const grmhd_block& b = blks[blockIdx.y];
+  const Geo q = geo_of(b);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cells(q)) return;
+  const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
+  M3 m;
+  cell_metric(b, t, m);
+  double Bt[3], w[5], U[5];
+  cell_bt(q, b.bs, i, j, k, Bt);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[v] = b.w[v][t];
+  prim_to_cons(e, m, w, Bt, U);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) b.us[v][t] = U[v];
+}
+
+// ---------------------------------------------------------------------------
+// pointwise kernels
+// ---------------------------------------------------------------------------
+struct Ptrs5 { double* p[5]; };
+struct Ptrs3 { double* p[3]; };
+struct Ptrs6 { double* p[6]; };
+
+__global__ __launch_bounds__(kThreads) void k_prim2con(int64_t n, Ptrs5 w, Ptrs3 bt, Ptrs6 gm,
+                                                       Ptrs5 u, Eos e) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  M3 m;
+  metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
+  const double ww[5] = {w.p[0][t], w.p[1][t], w.p[2][t], w.p[3][t], w.p[4][t]};
+  const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+  double U[5];
+  prim_to_cons(e, m, ww, B, U);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u.p[v][t] = U[v];
+}
+
+__global__ __launch_bounds__(kThreads) void k_c2p_batch(int64_t n, Ptrs5 u, Ptrs3 bt, Ptrs6 gm,
+                                                        Ptrs5 w, uint16_t* flags, Eos e,
+                                                        grmhd_params p, double* mu_out,
+                                                        int32_t* nev_out, c2p_stats* stats) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  M3 m;
+  metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
+  double U[5] = {u.p[0][t], u.p[1][t], u.p[2][t], u.p[3][t], u.p[4][t]};
+  const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+  double ww[5];
+  int nev;
+  double mu;
+  const uint32_t r = c2p_cell(e, p, m, U, B, ww, false, 0.0, 0.0, nev, mu);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    u.p[v][t] = U[v];
+    w.p[v][t] = ww[v];
+  }
+  flags[t] = (uint16_t)r;
+  if (mu_out) mu_out[t] = mu;
+  if (nev_out) nev_out[t] = nev;
+  if (stats) {
+    atomicAdd(&stats->solves, 1ull);
+    atomicAdd(&stats->evaluations, (unsigned long long)nev);
+    if (r & GRMHD_F_BRACKET_FALLBACK) atomicAdd(&stats->fallbacks, 1ull);
+    if (r & GRMHD_F_C2P_FAIL) atomicAdd(&stats->failures, 1ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+Eos make_eos(const grmhd_params& p) {
+  Eos e;
+  memset(&e, 0, sizeof(e));
+  e.type = p.eos;
+  e.gam = p.gamma;
+  e.gth = p.gamma_th;
+  e.n = p.eos == 1 ? p.npieces : 1;
+  if (p.eos == 1) {
+    for (int i = 0; i < e.n; ++i) e.G[i] = p.Gam[i];
+    e.K[0] = p.K0;
+    e.a[0] = 0.0;
+    for (int i = 1; i < e.n; ++i) {
+      const double r = p.rho_b[i - 1];
+      e.rb[i - 1] = r;
+      // P_cold and eps_cold continuous at r
+      e.K[i] = e.K[i - 1] * pow(r, e.G[i - 1]) / pow(r, e.G[i]);
+      const double pr = e.K[i - 1] * pow(r, e.G[i - 1]);
+      e.a[i] = e.a[i - 1] + pr / (r * (e.G[i - 1] - 1.0)) - pr / (r * (e.G[i] - 1.0));
+    }
+  }
+  return e;
+}
+
+int check_params(const grmhd_params* p) {
+  if (!p) return GRMHD_EINVAL;
+  if (p->eos != 0 && p->eos != 1) return GRMHD_EINVAL;
+  if (p->eos == 1 && (p->npieces < 1 || p->npieces > 4)) return GRMHD_EINVAL;
+  if (p->recon != 0 && p->recon != 2) return GRMHD_EUNSUPPORTED;
+  if (p->riemann != 0 && p->riemann != 1) return GRMHD_EINVAL;
+  if (p->c2p_maxit < 1) return GRMHD_EINVAL;
+  return GRMHD_OK;
+}
+
+int check_blocks(const grmhd_block* h, const grmhd_block* d, int nblk) {
+  if (!h || !d || nblk < 1) return GRMHD_EINVAL;
+  for (int i = 0; i < nblk; ++i) {
+    const grmhd_block& b = h[i];
+    if (b.ng < 3 || b.nx < 1 || b.ny < 1 || b.nz < 1) return GRMHD_EINVAL;
+    if (!b.scratch || !b.flags) return GRMHD_EINVAL;
+    for (int v = 0; v < 5; ++v)
+      if (!b.w[v] || !b.un[v] || !b.us[v] || !b.uo[v] || !b.wo[v]) return GRMHD_EINVAL;
+    for (int v = 0; v < 3; ++v)
+      if (!b.bn[v] || !b.bs[v] || !b.bo[v]) return GRMHD_EINVAL;
+    for (int v = 0; v < 16; ++v)
+      if (!b.adm[v]) return GRMHD_EINVAL;
+    for (int v = 0; v < 27; ++v)
+      if (b.nbr[v] < -1 || b.nbr[v] >= nblk) return GRMHD_EINVAL;
+    if (b.bc == 1) {
+      // a neighbour supplies ng layers: its extent must cover them
+      for (int v = 0; v < 27; ++v) {
+        const int nb = b.nbr[v];
+        if (nb < 0 || nb == i) continue;
+        const grmhd_block& s = h[nb];
+        if (s.nx != b.nx || s.ny != b.ny || s.nz != b.nz || s.ng != b.ng) return GRMHD_EINVAL;
+        if (s.nx < b.ng || s.ny < b.ng || s.nz < b.ng) return GRMHD_EINVAL;
+      }
+    }
+  }
+  return GRMHD_OK;
+}
+
+struct Sizes {
+  int64_t cells, interior, ext_cells, faces[3], ifaces[3], edges[3];
+};
+
+Sizes max_sizes(const grmhd_block* h, int nblk) {
+  Sizes s;
+  memset(&s, 0, sizeof(s));
+  for (int i = 0; i < nblk; ++i) {
+    const Geo q = geo_of(h[i]);
+    const int n[3] = {q.nx, q.ny, q.nz};
+    s.cells = s.cells > n_cells(q) ? s.cells : n_cells(q);
+    const int64_t in = (int64_t)q.nx * q.ny * q.nz;
+    s.interior = s.interior > in ? s.interior : in;
+    const int64_t ec = (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
+    s.ext_cells = s.ext_cells > ec ? s.ext_cells : ec;
+    for (int d = 0; d < 3; ++d) {
+      int64_t f = 1, fi = 1, e = 1;
+      for (int a = 0; a < 3; ++a) {
+        f *= a == d ? n[a] + 1 : n[a] + 2;
+        fi *= a == d ? n[a] + 1 : n[a];
+        e *= a == d ? n[a] : n[a] + 1;
+      }
+      s.faces[d] = s.faces[d] > f ? s.faces[d] : f;
+      s.ifaces[d] = s.ifaces[d] > fi ? s.ifaces[d] : fi;
+      s.edges[d] = s.edges[d] > e ? s.edges[d] : e;
+    }
+  }
+  return s;
+}
+
+dim3 grid_for(int64_t items, int nblk) {
+  return dim3((unsigned)((items + kThreads - 1) / kThreads), (unsigned)nblk, 1);
+}
+
+int last_err() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_EHIP; }
+
+// the steps; validation is done by the public entry points
+void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
+                const Eos& e, hipStream_t s) {
+  const Sizes z = max_sizes(h, nblk);
+  k_bcc<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
+  k_flux<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
+  k_flux<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
+  k_flux<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
+}
+
+void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
+              const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
+              hipStream_t s) {
+  const Sizes z = max_sizes(h, nblk);
+  k_clear_flags<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
+  if (!p.fofc) return;
+  k_fofc_flags<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
+  k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d, 8);
+  k_fofc_fix<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
+  k_fofc_fix<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
+  k_fofc_fix<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
+}
+
+void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
+            double a0, double a1, double b, hipStream_t s) {
+  const Sizes z = max_sizes(h, nblk);
+  k_emf_cc<<<grid_for(z.ext_cells, nblk), kThreads, 0, s>>>(d);
+  k_emf_edge<0><<<grid_for(z.edges[0], nblk), kThreads, 0, s>>>(d);
+  k_emf_edge<1><<<grid_for(z.edges[1], nblk), kThreads, 0, s>>>(d);
+  k_emf_edge<2><<<grid_for(z.edges[2], nblk), kThreads, 0, s>>>(d);
+  k_ct_face<0><<<grid_for(z.ifaces[0], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
+  k_ct_face<1><<<grid_for(z.ifaces[1], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
+  k_ct_face<2><<<grid_for(z.ifaces[2], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
+}
+
+void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos& e,
+                const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
+  const Sizes z = max_sizes(h, nblk);
+  k_update<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, dt_d, dt, a0, a1, b);
+}
+
+void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
+             const Eos& e, hipStream_t s) {
+  const Sizes z = max_sizes(h, nblk);
+  k_stage_c2p<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int64_t grmhd_scratch_doubles(int32_t nx, int32_t ny, int32_t nz, int32_t ng) {
+  if (nx < 1 || ny < 1 || nz < 1 || ng < 0) return -1;
+  Geo q;
+  q.nx = nx; q.ny = ny; q.nz = nz; q.g = ng;
+  q.sx = nx + 2 * ng; q.sy = ny + 2 * ng; q.sz = nz + 2 * ng;
+  return scratch_total(q);
+}
+
+int64_t grmhd_flux_offset(int32_t nx, int32_t ny, int32_t nz, int32_t ng, int32_t d, int32_t c) {
+  if (nx < 1 || ny < 1 || nz < 1 || ng < 0 || d < 0 || d > 2 || c < 0 || c > 6) return -1;
+  Geo q;
+  q.nx = nx; q.ny = ny; q.nz = nz; q.g = ng;
+  q.sx = nx + 2 * ng; q.sy = ny + 2 * ng; q.sz = nz + 2 * ng;
+  return off_flux(q, d, c);
+}
+
+int grmhd_fluxes(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                 const grmhd_params* p, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  run_fluxes(blk_h, blk_d, nblk, *p, make_eos(*p), (hipStream_t)stream);
+  return last_err();
+}
+
+int fofc_correct(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                 const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
+                 double b, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  run_fofc(blk_h, blk_d, nblk, *p, make_eos(*p), dt_d, dt, a0, a1, b, (hipStream_t)stream);
+  return last_err();
+}
+
+int ct_update(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+              const grmhd_params* p, const double* dt_d, double dt, double a0, double a1, double b,
+              void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, (hipStream_t)stream);
+  return last_err();
+}
+
+int grmhd_update(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                 const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
+                 double b, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  run_update(blk_h, blk_d, nblk, make_eos(*p), dt_d, dt, a0, a1, b, (hipStream_t)stream);
+  return last_err();
+}
+
+int grmhd_stage_c2p(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                    const grmhd_params* p, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  run_c2p(blk_h, blk_d, nblk, *p, make_eos(*p), (hipStream_t)stream);
+  return last_err();
+}
+
+int grmhd_stage(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
+                double b, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  const Eos e = make_eos(*p);
+  hipStream_t s = (hipStream_t)stream;
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s);
+  run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s);
+  run_update(blk_h, blk_d, nblk, e, dt_d, dt, a0, a1, b, s);
+  run_c2p(blk_h, blk_d, nblk, *p, e, s);
+  return last_err();
+}
+
+int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                     int32_t mask, void* stream) {
+  if (!blk_h || !blk_d || nblk < 1 || (mask & ~15)) return GRMHD_EINVAL;
+  for (int i = 0; i < nblk; ++i) {
+    const grmhd_block& b = blk_h[i];
+    if (b.ng < 1 || b.nx < 1 || b.ny < 1 || b.nz < 1) return GRMHD_EINVAL;
+    if (b.bc != 1) continue;
+    if (((mask & 1) && !b.w[4]) || ((mask & 2) && !b.us[4]) || ((mask & 4) && !b.bs[2]) ||
+        ((mask & 8) && !b.flags))
+      return GRMHD_EINVAL;
+    for (int v = 0; v < 27; ++v) {
+      const int nb = b.nbr[v];
+      if (nb < -1 || nb >= nblk) return GRMHD_EINVAL;
+      if (nb < 0 || nb == i) continue;
+      const grmhd_block& o = blk_h[nb];
+      if (o.nx != b.nx || o.ny != b.ny || o.nz != b.nz || o.ng != b.ng) return GRMHD_EINVAL;
+      if (b.nx < b.ng || b.ny < b.ng || b.nz < b.ng) return GRMHD_EINVAL;
+    }
+  }
+  const Sizes z = max_sizes(blk_h, nblk);
+  hipStream_t s = (hipStream_t)stream;
+  if (mask & 11) k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(blk_d, mask & 11);
+  if (mask & 4) {
+    int64_t mf[3] = {0, 0, 0};
+    for (int i = 0; i < nblk; ++i)
+      for (int d = 0; d < 3; ++d) {
+        const int64_t f = n_faces(geo_of(blk_h[i]), d);
+        mf[d] = mf[d] > f ? mf[d] : f;
+      }
+    for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_for(mf[d], nblk), kThreads, 0, s>>>(blk_d, d);
+  }
+  return last_err();
+}
+
+int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+             const grmhd_params* p, double cfl, double* red, double* dt_out, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if (!blk_h || !blk_d || nblk < 1 || !red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const Sizes z = max_sizes(blk_h, nblk);
+  k_zero1<<<1, 64, 0, s>>>(red);
+  k_dt<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(blk_d, make_eos(*p), red);
+  k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
+  return last_err();
+}
+
+int grmhd_mass(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk, double* partial,
+               double* out, void* stream) {
+  if (!blk_h || !blk_d || nblk < 1 || !partial || !out) return GRMHD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  k_mass_block<<<nblk, kThreads, 0, s>>>(blk_d, partial);
+  k_mass_final<<<1, 64, 0, s>>>(partial, nblk, out);
+  return last_err();
+}
+
+int prim2con(int64_t n, double* const w[5], double* const bt[3], double* const gam[6], double* u[5],
+             const grmhd_params* p, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if (n < 0 || !w || !bt || !gam || !u) return GRMHD_EINVAL;
+  if (n == 0) return GRMHD_OK;
+  Ptrs5 pw, pu;
+  Ptrs3 pb;
+  Ptrs6 pg;
+  for (int v = 0; v < 5; ++v) { pw.p[v] = w[v]; pu.p[v] = u[v]; if (!w[v] || !u[v]) return GRMHD_EINVAL; }
+  for (int v = 0; v < 3; ++v) { pb.p[v] = bt[v]; if (!bt[v]) return GRMHD_EINVAL; }
+  for (int v = 0; v < 6; ++v) { pg.p[v] = gam[v]; if (!gam[v]) return GRMHD_EINVAL; }
+  k_prim2con<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, (hipStream_t)stream>>>(
+      n, pw, pb, pg, pu, make_eos(*p));
+  return last_err();
+}
+
+int c2p_batch(int64_t n, double* u[5], double* const bt[3], double* const gam[6], double* w[5],
+              uint16_t* flags, const grmhd_params* p, const c2p_mlp* mlp, c2p_stats* stats,
+              double* mu_out, int32_t* nev_out, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if (n < 0 || !u || !bt || !gam || !w || !flags) return GRMHD_EINVAL;
+  if (mlp) return GRMHD_EUNSUPPORTED;
+  if (n == 0) return GRMHD_OK;
+  Ptrs5 pw, pu;
+  Ptrs3 pb;
+  Ptrs6 pg;
+  for (int v = 0; v < 5; ++v) { pw.p[v] = w[v]; pu.p[v] = u[v]; if (!w[v] || !u[v]) return GRMHD_EINVAL; }
+  for (int v = 0; v < 3; ++v) { pb.p[v] = bt[v]; if (!bt[v]) return GRMHD_EINVAL; }
+  for (int v = 0; v < 6; ++v) { pg.p[v] = gam[v]; if (!gam[v]) return GRMHD_EINVAL; }
+  k_c2p_batch<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, (hipStream_t)stream>>>(
+      n, pu, pb, pg, pw, flags, make_eos(*p), *p, mu_out, nev_out, stats);
+  return last_err();
+}
+
+int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                          const grmhd_params* p, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if (!blk_h || !blk_d || nblk < 1) return GRMHD_EINVAL;
+  const Sizes z = max_sizes(blk_h, nblk);
+  k_p2c_block<<<grid_for(z.cells, nblk), kThreads, 0, (hipStream_t)stream>>>(blk_d, make_eos(*p));
+  return last_err();
+}
+
+const char* grmhd_version(void) { return "grmhd 0.1 gfx950 fp64"; }
+
+}  // extern "C"

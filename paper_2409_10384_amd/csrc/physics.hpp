@@ -1,0 +1,497 @@
+// physics.hpp -- device-side physics of one GRMHD stage for gfx950, FP64.
+//
+//   EOS                 ideal gas; hybrid cold piecewise polytrope + thermal
+//                       Gamma_th part (Sec. III-D)
+//   3-metric            determinant, inverse, sqrt(gamma) (Eq. 5)
+//   cell state          Eq. 7 (densitized), Eq. 8 for b^mu, Eq. 9 fluxes,
+//                       fast magnetosonic characteristic speeds
+//   Riemann             HLLE / LLF (Sec. III-B)
+//   WENOZ               Borges et al. 2008 (p = 2, eps = 1e-40)
+//   C2P                 Kastaun et al. master function in mu = 1/(hW),
+//                       bracketed root by Brent's method, atmosphere rules
+//                       of Sec. III-C
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grmhd.h"
+
+namespace gk {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+// ---------------------------------------------------------------------------
+// EOS: derived piece constants are computed once on the host
+// ---------------------------------------------------------------------------
+struct Eos {
+  int type, n;
+  double gam, gth;
+  double rb[3], K[4], G[4], a[4];
+};
+
+__device__ __forceinline__ int eos_piece(const Eos& e, double rho) {
+  int i = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    if (t + 1 < e.n && rho >= e.rb[t]) i = t + 1;
+  return i;
+}
+
+struct Cold { double p, e, g; };   // P_cold, eps_cold, index of the piece
+
+__device__ __forceinline__ Cold eos_cold(const Eos& e, double rho) {
+  Cold c{0.0, 0.0, 1.0};
+  if (e.type == 1) {
+    int i = eos_piece(e, rho);
+    double gi = e.G[i];
+    double pr = e.K[i] * pow(rho, gi);
+    c.p = pr;
+    c.e = e.a[i] + pr / (rho * (gi - 1.0));
+    c.g = gi;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double eos_P_from_eps(const Eos& e, double rho, double eps) {
+  if (e.type == 0) return (e.gam - 1.0) * rho * eps;
+  Cold c = eos_cold(e, rho);
+  return c.p + (e.gth - 1.0) * rho * (eps - c.e);
+}
+__device__ __forceinline__ double eos_eps_from_P(const Eos& e, double rho, double P) {
+  if (e.type == 0) return P / ((e.gam - 1.0) * rho);
+  Cold c = eos_cold(e, rho);
+  return c.e + (P - c.p) / ((e.gth - 1.0) * rho);
+}
+__device__ __forceinline__ double eos_T_from_P(const Eos& e, double rho, double P) {
+  if (e.type == 0) return P / rho;
+  return (P - eos_cold(e, rho).p) / rho;
+}
+__device__ __forceinline__ double eos_P_from_T(const Eos& e, double rho, double T) {
+  if (e.type == 0) return rho * T;
+  return eos_cold(e, rho).p + rho * T;
+}
+__device__ __forceinline__ double eos_eps_from_T(const Eos& e, double rho, double T) {
+  if (e.type == 0) return T / (e.gam - 1.0);
+  return eos_cold(e, rho).e + T / (e.gth - 1.0);
+}
+__device__ __forceinline__ double eos_eps_min(const Eos& e, double rho) {
+  return e.type == 0 ? 0.0 : eos_cold(e, rho).e;
+}
+// c_s^2 h = dP/drho|_eps + (P/rho^2) dP/deps|_rho
+__device__ __forceinline__ double eos_cs2(const Eos& e, double rho, double eps, double P, double h) {
+  if (e.type == 0) return e.gam * P / (rho * h);
+  Cold c = eos_cold(e, rho);
+  double gm1 = e.gth - 1.0;
+  double chi = c.g * c.p / rho + gm1 * (eps - c.e) - gm1 * c.p / rho;
+  return (chi + gm1 * P / rho) / h;
+}
+
+// ---------------------------------------------------------------------------
+// 3-metric (symmetric: xx xy xz yy yz zz)
+// ---------------------------------------------------------------------------
+struct M3 {
+  double g[6];   // lower
+  double u[6];   // inverse
+  double sg;     // sqrt(det)
+};
+
+__device__ __forceinline__ void metric_build(M3& m, double xx, double xy, double xz, double yy,
+                                             double yz, double zz) {
+  m.g[0] = xx; m.g[1] = xy; m.g[2] = xz; m.g[3] = yy; m.g[4] = yz; m.g[5] = zz;
+  double cxx = yy * zz - yz * yz;
+  double cxy = yz * xz - xy * zz;
+  double cxz = xy * yz - yy * xz;
+  double det = xx * cxx + xy * cxy + xz * cxz;
+  double id = 1.0 / det;
+  m.u[0] = cxx * id;
+  m.u[1] = cxy * id;
+  m.u[2] = cxz * id;
+  m.u[3] = (xx * zz - xz * xz) * id;
+  m.u[4] = (xz * xy - xx * yz) * id;
+  m.u[5] = (xx * yy - xy * xy) * id;
+  m.sg = sqrt(det);
+}
+
+__device__ __forceinline__ void lower(const double* g, double ax, double ay, double az, double& lx,
+                                      double& ly, double& lz) {
+  lx = g[0] * ax + g[1] * ay + g[2] * az;
+  ly = g[1] * ax + g[3] * ay + g[4] * az;
+  lz = g[2] * ax + g[4] * ay + g[5] * az;
+}
+
+// component (a, b) of a symmetric 3x3 stored as 6
+__device__ __forceinline__ constexpr int sym(int a, int b) {
+  return a == b ? (a == 0 ? 0 : a == 1 ? 3 : 5) : ((a + b) == 1 ? 1 : (a + b) == 2 ? 2 : 4);
+}
+
+// ---------------------------------------------------------------------------
+// Cell/face state: Eq. 7 (densitized), Eq. 8, Eq. 9 fluxes, wave speeds
+// q = (rho, W v^x, W v^y, W v^z, P); B = Eulerian B^i (un-densitized)
+// U, F: D~, S~_x, S~_y, S~_z, tau~, B~^{t1}, B~^{t2}  (t1 = (D+1)%3, t2 = (D+2)%3)
+// ---------------------------------------------------------------------------
+struct Side {
+  double U[7], F[7];
+  double lm, lp;
+};
+
+// rho h W^2 - P - D without cancellation:
+//   D (W^2 - 1)/(W + 1) + rho eps W^2 + P (W^2 - 1), with W^2 - 1 = u.u
+__device__ __forceinline__ double tau_hydro(double D, double usq, double W, double rho, double eps,
+                                            double P) {
+  return D * usq / (W + 1.0) + rho * eps * (W * W) + P * usq;
+}
+
+template <int DIR>
+__device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alpha, const double beta[3],
+                                           const double q[5], const double B[3], Side& s) {
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  const double rho = q[0], P = q[4];
+  double ul[3];
+  lower(m.g, q[1], q[2], q[3], ul[0], ul[1], ul[2]);
+  const double usq = q[1] * ul[0] + q[2] * ul[1] + q[3] * ul[2];
+  const double W = sqrt(1.0 + usq);
+  const double iW = 1.0 / W;
+  double v[3] = {q[1] * iW, q[2] * iW, q[3] * iW};
+  double vl[3] = {ul[0] * iW, ul[1] * iW, ul[2] * iW};
+  double Bl[3];
+  lower(m.g, B[0], B[1], B[2], Bl[0], Bl[1], Bl[2]);
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const double Bv = B[0] * vl[0] + B[1] * vl[1] + B[2] * vl[2];
+  const double eps = eos_eps_from_P(e, rho, P);
+  const double h = 1.0 + eps + P / rho;
+  const double ia = 1.0 / alpha;
+  const double b0 = W * Bv * ia;
+  const double W2 = W * W;
+  const double bsq = B2 / W2 + Bv * Bv;
+  const double sg = m.sg;
+  const double Ptt = sg * (P + 0.5 * bsq);
+  const double D = rho * W;
+  const double ehw = rho * h * W2 + B2;
+  const double tau = tau_hydro(D, usq, W, rho, eps, P) + B2 - 0.5 * (Bv * Bv + B2 / W2);
+  double vh[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vh[a] = v[a] - beta[a] * ia;
+  const double Btd = sg * B[DIR];
+  s.U[0] = sg * D;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s.U[1 + a] = sg * (ehw * vl[a] - Bv * Bl[a]);
+  s.U[4] = sg * tau;
+  s.U[5] = sg * B[T1];
+  s.U[6] = sg * B[T2];
+  const double avd = alpha * vh[DIR];
+  s.F[0] = avd * s.U[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double bl = Bl[a] * iW + W * Bv * vl[a];     // b_i
+    s.F[1 + a] = avd * s.U[1 + a] - alpha * bl * Btd * iW + (a == DIR ? alpha * Ptt : 0.0);
+  }
+  s.F[4] = avd * s.U[4] - alpha * alpha * b0 * Btd * iW + alpha * Ptt * v[DIR];
+  s.F[5] = alpha * (s.U[5] * vh[DIR] - Btd * vh[T1]);
+  s.F[6] = alpha * (s.U[6] * vh[DIR] - Btd * vh[T2]);
+  // fast magnetosonic estimate c^2 = cs^2 + ca^2 - cs^2 ca^2
+  const double cs2 = eos_cs2(e, rho, eps, P, h);
+  const double ca2 = bsq / (rho * h + bsq);
+  const double c2 = cs2 + ca2 - cs2 * ca2;
+  const double v2 = usq / W2;
+  const double gdd = m.u[sym(DIR, DIR)];
+  const double vd = v[DIR];
+  double disc = c2 * (1.0 - v2) * (gdd * (1.0 - v2 * c2) - vd * vd * (1.0 - c2));
+  disc = disc > 0.0 ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double iden = 1.0 / (1.0 - v2 * c2);
+  const double base = vd * (1.0 - c2);
+  s.lp = alpha * (base + sq) * iden - beta[DIR];
+  s.lm = alpha * (base - sq) * iden - beta[DIR];
+}
+
+__device__ __forceinline__ void riemann(int kind, const Side& L, const Side& R, double F[7]) {
+  if (kind == 0) {
+    double a = fmax(fmax(fabs(L.lm), fabs(L.lp)), fmax(fabs(R.lm), fabs(R.lp)));
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = 0.5 * (L.F[c] + R.F[c]) - 0.5 * a * (R.U[c] - L.U[c]);
+    return;
+  }
+  const double ar = fmax(0.0, fmax(L.lp, R.lp));
+  const double al = fmin(0.0, fmin(L.lm, R.lm));
+  const double den = ar - al;
+  if (den == 0.0) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = 0.5 * (L.F[c] + R.F[c]);
+    return;
+  }
+  const double id = 1.0 / den;
+  const double arl = ar * al;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) F[c] = (ar * L.F[c] - al * R.F[c] + arl * (R.U[c] - L.U[c])) * id;
+}
+
+// WENOZ value at the upper interface of cell c from cells c-2..c+2
+__device__ __forceinline__ double wenoz(double a, double b, double c, double d, double f) {
+  const double s0a = a - 2.0 * b + c, s0b = a - 4.0 * b + 3.0 * c;
+  const double s1a = b - 2.0 * c + d, s1b = b - d;
+  const double s2a = c - 2.0 * d + f, s2b = 3.0 * c - 4.0 * d + f;
+  const double k13 = 13.0 / 12.0;
+  const double be0 = k13 * s0a * s0a + 0.25 * s0b * s0b;
+  const double be1 = k13 * s1a * s1a + 0.25 * s1b * s1b;
+  const double be2 = k13 * s2a * s2a + 0.25 * s2b * s2b;
+  const double t5 = fabs(be0 - be2);
+  const double r0 = t5 / (be0 + 1e-40), r1 = t5 / (be1 + 1e-40), r2 = t5 / (be2 + 1e-40);
+  const double w0 = 0.1 * (1.0 + r0 * r0);
+  const double w1 = 0.6 * (1.0 + r1 * r1);
+  const double w2 = 0.3 * (1.0 + r2 * r2);
+  const double p0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+  const double p1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  const double p2 = (2.0 * c + 5.0 * d - f) * (1.0 / 6.0);
+  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+// atmosphere rules on a reconstructed face state (Sec. III-C)
+__device__ __forceinline__ void floor_face(const Eos& e, const grmhd_params& p, double q[5]) {
+  if (q[0] < p.f_thr * p.rho_atm) {
+    q[0] = p.rho_atm;
+    q[1] = q[2] = q[3] = 0.0;
+    q[4] = eos_P_from_T(e, p.rho_atm, p.T_atm);
+  } else if (eos_T_from_P(e, q[0], q[4]) < p.T_atm) {
+    q[4] = eos_P_from_T(e, q[0], p.T_atm);
+  }
+}
+
+// Eq. 7 at a point (densitized), used by the inversion and prim2con
+__device__ __forceinline__ void prim_to_cons(const Eos& e, const M3& m, const double w[5],
+                                             const double Bt[3], double U[5]) {
+  const double is = 1.0 / m.sg;
+  const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+  double ul[3], Bl[3];
+  lower(m.g, w[1], w[2], w[3], ul[0], ul[1], ul[2]);
+  lower(m.g, B[0], B[1], B[2], Bl[0], Bl[1], Bl[2]);
+  const double usq = w[1] * ul[0] + w[2] * ul[1] + w[3] * ul[2];
+  const double W = sqrt(1.0 + usq);
+  const double iW = 1.0 / W;
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const double Bv = (B[0] * ul[0] + B[1] * ul[1] + B[2] * ul[2]) * iW;
+  const double rho = w[0], P = w[4];
+  const double eps = eos_eps_from_P(e, rho, P);
+  const double h = 1.0 + eps + P / rho;
+  const double D = rho * W;
+  const double ehw = rho * h * W * W + B2;
+  U[0] = m.sg * D;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) U[1 + a] = m.sg * (ehw * ul[a] * iW - Bv * Bl[a]);
+  U[4] = m.sg * (tau_hydro(D, usq, W, rho, eps, P) + B2 - 0.5 * (Bv * Bv + B2 / (W * W)));
+}
+
+// ---------------------------------------------------------------------------
+// C2P: Kastaun master function in mu = 1/(hW)
+// ---------------------------------------------------------------------------
+struct KState {
+  double D, q, r2, b2, s, v0sq;
+};
+
+struct KEval { double chi, rb2, qb, vsq, W, rho, eps, P; };
+
+__device__ __forceinline__ KEval k_eval(const Eos& e, const KState& k, double mu) {
+  KEval o;
+  const double chi = 1.0 / (1.0 + mu * k.b2);
+  const double rb2 = chi * chi * k.r2 + mu * chi * (1.0 + chi) * (k.s * k.s);
+  const double qb = k.q - 0.5 * k.b2 - 0.5 * (mu * mu) * (chi * chi) * (k.b2 * k.r2 - k.s * k.s);
+  const double vsq = fmin(mu * mu * rb2, k.v0sq);
+  const double W = 1.0 / sqrt(1.0 - vsq);
+  const double rho = k.D / W;
+  double eps = W * (qb - mu * rb2) + vsq * (W * W) / (1.0 + W);
+  eps = fmax(eps, eos_eps_min(e, rho));
+  o.chi = chi; o.rb2 = rb2; o.qb = qb; o.vsq = vsq; o.W = W; o.rho = rho; o.eps = eps;
+  o.P = eos_P_from_eps(e, rho, eps);
+  return o;
+}
+
+__device__ __forceinline__ double k_master(const Eos& e, const KState& k, double mu) {
+  const KEval s = k_eval(e, k, mu);
+  const double a = s.P / (s.rho * (1.0 + s.eps));
+  const double nu = fmax((1.0 + a) * (1.0 + s.eps) / s.W, (1.0 + a) * (1.0 + s.qb - mu * s.rb2));
+  return mu - 1.0 / (nu + mu * s.rb2);
+}
+
+__device__ __forceinline__ double k_aux(const KState& k, double mu) {
+  const double chi = 1.0 / (1.0 + mu * k.b2);
+  const double rb2 = chi * chi * k.r2 + mu * chi * (1.0 + chi) * (k.s * k.s);
+  return mu * sqrt(1.0 + rb2) - 1.0;     // minimum enthalpy h0 = 1
+}
+
+// Brent (1973): bracketing root finder; f(a) <= 0 <= f(b) or the reverse.
+// Returns the root; ok = false on the iteration cap or a non-finite value.
+template <class Fn>
+__device__ __forceinline__ double brent_root(Fn f, double a, double b, double fa, double fb,
+                                             double rtol, int maxit, int& nev, bool& ok) {
+  ok = true;
+  if (fa == 0.0) return a;
+  if (fb == 0.0) return b;
+  double c = a, fc = fa, d = b - a, e = d;
+  for (int it = 0; it < maxit; ++it) {
+    if ((fb > 0.0) == (fc > 0.0)) {
+      c = a; fc = fa; d = b - a; e = d;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b; b = c; c = a;
+      fa = fb; fb = fc; fc = fa;
+    }
+    const double tol1 = (2.0 * kEps + 0.5 * rtol) * fabs(b) + 1e-300;
+    const double xm = 0.5 * (c - b);
+    if (fabs(xm) <= tol1 || fb == 0.0) return b;
+    bool bisect = true;
+    if (fabs(e) >= tol1 && fabs(fa) > fabs(fb)) {
+      const double s = fb / fa;
+      double p, q;
+      if (a == c) {
+        p = 2.0 * xm * s;
+        q = 1.0 - s;
+      } else {
+        const double qq = fa / fc, r = fb / fc;
+        p = s * (2.0 * xm * qq * (qq - r) - (b - a) * (r - 1.0));
+        q = (qq - 1.0) * (r - 1.0) * (s - 1.0);
+      }
+      if (p > 0.0) q = -q; else p = -p;
+      if (2.0 * p < fmin(3.0 * xm * q - fabs(tol1 * q), fabs(e * q))) {
+        e = d;
+        d = p / q;
+        bisect = false;
+      }
+    }
+    if (bisect) { d = xm; e = d; }
+    a = b;
+    fa = fb;
+    b += fabs(d) > tol1 ? d : (xm > 0.0 ? tol1 : -tol1);
+    fb = f(b);
+    ++nev;
+    if (!__builtin_isfinite(fb)) { ok = false; return b; }
+  }
+  ok = false;
+  return b;
+}
+
+__device__ __forceinline__ void atmosphere(const Eos& e, const grmhd_params& p, double w[5]) {
+  w[0] = p.rho_atm;
+  w[1] = 0.0; w[2] = 0.0; w[3] = 0.0;
+  w[4] = eos_P_from_T(e, p.rho_atm, p.T_atm);
+}
+
+constexpr uint32_t kFloorBits = GRMHD_F_C2P_FAIL | GRMHD_F_DFLOOR | GRMHD_F_TAUFLOOR |
+                                GRMHD_F_MAGCAP | GRMHD_F_TFLOOR | GRMHD_F_RHOFLOOR | GRMHD_F_MAXIT;
+
+// Inversion of one cell with the atmosphere rules of Sec. III-C.  U
+// (densitized) is rewritten from the final primitives whenever a rule fires.
+// With use_br, [blo, bhi] is tried first (learned bracket).
+__device__ __forceinline__ uint32_t c2p_cell(const Eos& e, const grmhd_params& p, const M3& m,
+                                             double U[5], const double Bt[3], double w[5],
+                                             bool use_br, double blo, double bhi, int& nev,
+                                             double& mu_out) {
+  uint32_t fl = 0;
+  nev = 0;
+  mu_out = 0.0;
+  const double is = 1.0 / m.sg;
+  double D = U[0] * is;
+  const double Sx = U[1] * is, Sy = U[2] * is, Sz = U[3] * is;
+  double tau = U[4] * is;
+  const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+  double Bl[3];
+  lower(m.g, B[0], B[1], B[2], Bl[0], Bl[1], Bl[2]);
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const bool finite = __builtin_isfinite(D) && __builtin_isfinite(Sx) && __builtin_isfinite(Sy) &&
+                      __builtin_isfinite(Sz) && __builtin_isfinite(tau);
+  if (!finite || D < p.f_thr * p.rho_atm) {
+    atmosphere(e, p, w);
+    prim_to_cons(e, m, w, Bt, U);
+    return finite ? GRMHD_F_DFLOOR : GRMHD_F_C2P_FAIL;
+  }
+  if (B2 / D > p.M_max) {
+    D = B2 / p.M_max;
+    fl |= GRMHD_F_MAGCAP;
+  }
+  const double tau_atm = D * eos_eps_from_T(e, D, p.T_atm) + 0.5 * B2;
+  if (tau < tau_atm) {
+    tau = tau_atm;
+    fl |= GRMHD_F_TAUFLOOR;
+  }
+  KState k;
+  k.D = D;
+  const double iD = 1.0 / D;
+  k.q = tau * iD;
+  const double rl[3] = {Sx * iD, Sy * iD, Sz * iD};
+  const double ru[3] = {m.u[0] * rl[0] + m.u[1] * rl[1] + m.u[2] * rl[2],
+                        m.u[1] * rl[0] + m.u[3] * rl[1] + m.u[4] * rl[2],
+                        m.u[2] * rl[0] + m.u[4] * rl[1] + m.u[5] * rl[2]};
+  k.r2 = rl[0] * ru[0] + rl[1] * ru[1] + rl[2] * ru[2];
+  const double isD = 1.0 / sqrt(D);
+  const double bu[3] = {B[0] * isD, B[1] * isD, B[2] * isD};
+  k.b2 = B2 * iD;
+  k.s = rl[0] * bu[0] + rl[1] * bu[1] + rl[2] * bu[2];
+  const double z2 = k.r2;      // z0 = r/h0 with h0 = 1
+  k.v0sq = z2 / (1.0 + z2);
+
+  auto fm = [&](double x) { return k_master(e, k, x); };
+  bool ok = false, have = false;
+  double mu = 0.0;
+  if (use_br) {
+    const double lo = fmax(blo, 0.0), hi = fmin(bhi, 1.0);
+    if (lo < hi && __builtin_isfinite(lo) && __builtin_isfinite(hi)) {
+      const double flo = fm(lo), fhi = fm(hi);
+      nev += 2;
+      if (flo <= 0.0 && fhi >= 0.0) {
+        mu = brent_root(fm, lo, hi, flo, fhi, p.c2p_tol, p.c2p_maxit, nev, ok);
+        have = true;
+      }
+    }
+    if (!have) fl |= GRMHD_F_BRACKET_FALLBACK;
+  }
+  if (!have) {
+    double hi = 1.0;
+    const double flo = fm(0.0);
+    double fhi = fm(hi);
+    nev += 2;
+    if (fhi < 0.0) {
+      // bound from above by the root mu_+ of the auxiliary function
+      auto fa = [&](double x) { return k_aux(k, x); };
+      bool oka;
+      const double mp = brent_root(fa, 0.0, 1.0, fa(0.0), fa(1.0), 1e-15, p.c2p_maxit, nev, oka);
+      hi = fmin(mp * (1.0 + 4.0 * kEps), 1.0);
+      fhi = fm(hi);
+      nev += 1;
+    }
+    if (flo > 0.0 || fhi < 0.0 || !__builtin_isfinite(flo) || !__builtin_isfinite(fhi)) {
+      ok = false;
+    } else {
+      mu = brent_root(fm, 0.0, hi, flo, fhi, p.c2p_tol, p.c2p_maxit, nev, ok);
+    }
+  }
+  mu_out = mu;
+  bool good = ok && __builtin_isfinite(mu);
+  if (good) {
+    const KEval s = k_eval(e, k, mu);
+    const double f1 = mu * s.chi, f2 = mu * k.s;
+    w[0] = s.rho;
+    w[1] = s.W * (f1 * (ru[0] + f2 * bu[0]));
+    w[2] = s.W * (f1 * (ru[1] + f2 * bu[1]));
+    w[3] = s.W * (f1 * (ru[2] + f2 * bu[2]));
+    w[4] = s.P;
+    good = __builtin_isfinite(w[0]) && __builtin_isfinite(w[1]) && __builtin_isfinite(w[2]) &&
+           __builtin_isfinite(w[3]) && __builtin_isfinite(w[4]);
+    if (good) {
+      if (w[0] < p.f_thr * p.rho_atm) {
+        atmosphere(e, p, w);
+        fl |= GRMHD_F_RHOFLOOR;
+      } else if (eos_T_from_P(e, w[0], w[4]) < p.T_atm) {
+        w[4] = eos_P_from_T(e, w[0], p.T_atm);
+        fl |= GRMHD_F_TFLOOR;
+      }
+    }
+  } else {
+    fl |= ok ? 0u : GRMHD_F_MAXIT;
+  }
+  if (!good) {
+    atmosphere(e, p, w);
+    fl |= GRMHD_F_C2P_FAIL;
+  }
+  if (fl & kFloorBits) prim_to_cons(e, m, w, Bt, U);
+  return fl;
+}
+
+}  // namespace gk

@@ -35,6 +35,24 @@ import numpy as np
 
 SEED_BASE = 2409_10384
 
+
+def _sqrt(a):
+    return a.sqrt() if hasattr(a, "sqrt") and not isinstance(a, np.ndarray) else np.sqrt(a)
+
+
+def _maximum(a, b):
+    if isinstance(a, np.ndarray):
+        return np.maximum(a, b)
+    import torch
+    return torch.maximum(a, b)
+
+
+def _maxs(a, s):
+    """elementwise max(a, scalar) for numpy arrays or torch tensors"""
+    if isinstance(a, np.ndarray) or np.isscalar(a):
+        return np.maximum(a, s)
+    return a.clamp(min=s)
+
 # neighbour table order: (ox+1) + 3 (oy+1) + 9 (oz+1)
 def nbr_index(ox: int, oy: int, oz: int) -> int:
     return (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)
@@ -201,61 +219,94 @@ class StarSetup:
     A_b: float = 0.0              # set by calibrate_field
 
     def rho(self, r):
-        return np.maximum(self.rho_c * (1.0 - (r / self.radius) ** 2), self.rho_atm)
+        return _maxs(self.rho_c * (1.0 - (r / self.radius) ** 2), self.rho_atm)
 
     def press(self, r):
         rho = self.rho(r)
-        return np.maximum(self.K * rho ** self.Gamma, rho * self.T_atm)
+        return _maximum(self.K * rho ** self.Gamma, rho * self.T_atm)
 
     def p_max(self):
         return self.K * self.rho_c ** self.Gamma
 
     def potential_scale(self, r):
-        return np.maximum(self.press(r) - self.pcut * self.p_max(), 0.0)
+        return _maxs(self.press(r) - self.pcut * self.p_max(), 0.0)
 
     def metric(self, x, y, z):
-        r = np.sqrt(x * x + y * y + z * z)
-        rt = np.sqrt(r * r + (0.5 * self.radius) ** 2)
+        r2 = x * x + y * y + z * z
+        rt = _sqrt(r2 + (0.5 * self.radius) ** 2)
         q = self.mass / (2.0 * rt)
         psi = 1.0 + q
         alpha = (1.0 - q) / (1.0 + q)
         return alpha, psi ** 4
 
 
-def _star_block_arrays(st: StarSetup, i0, j0, k0, n, ng, h, xmin):
+class _NumpyBackend:
+    def arange(self, n):
+        return np.arange(n, dtype=np.float64)
+
+    def empty(self, shape):
+        return np.empty(shape)
+
+    def contiguous(self, a):
+        return np.ascontiguousarray(a)
+
+
+class _TorchBackend:
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+
+    def arange(self, n):
+        return self.torch.arange(n, dtype=self.torch.float64, device=self.device)
+
+    def empty(self, shape):
+        return self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
+
+    def contiguous(self, a):
+        return a.contiguous()
+
+
+def _star_block_arrays(st: StarSetup, i0, j0, k0, n, ng, h, xmin, backend=None):
     """Padded arrays of a block whose first interior cell has global integer
-    index (i0, j0, k0) on a lattice of spacing h starting at xmin."""
+    index (i0, j0, k0) on a lattice of spacing h starting at xmin.  backend:
+    numpy (default) or torch tensors on a device (same formulas)."""
+    be = backend or _NumpyBackend()
     s = n + 2 * ng
-    gi = np.arange(s) - ng          # local padded -> global cell offset
-    xc = xmin + (i0 + gi + 0.5) * h
-    yc = xmin + (j0 + gi + 0.5) * h
-    zc = xmin + (k0 + gi + 0.5) * h
-    fa = np.arange(s + 1) - ng
-    xf = xmin + (i0 + fa) * h
-    yf = xmin + (j0 + fa) * h
-    zf = xmin + (k0 + fa) * h
-    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
-    R = np.sqrt(X * X + Y * Y + Z * Z)
+    gi = be.arange(s) - ng          # local padded -> global cell offset
+    fa = be.arange(s + 1) - ng
+    # 1-D coordinates, broadcast as [k, j, i]
+    xc = (xmin + (i0 + gi + 0.5) * h)[None, None, :]
+    yc = (xmin + (j0 + gi + 0.5) * h)[None, :, None]
+    zc = (xmin + (k0 + gi + 0.5) * h)[:, None, None]
+    xf = (xmin + (i0 + fa) * h)[None, None, :]
+    yf = (xmin + (j0 + fa) * h)[None, :, None]
+    zf = (xmin + (k0 + fa) * h)[:, None, None]
+    R = _sqrt(xc * xc + yc * yc + zc * zc)
     rho = st.rho(R)
     P = st.press(R)
-    zero = np.zeros_like(rho)
-    alpha, g = st.metric(X, Y, Z)
-    adm = np.stack([alpha, zero, zero, zero, g, zero, zero, g, zero, g] + [zero] * 6)
-    w = np.stack([rho, zero, zero, zero, P])
+    alpha, g = st.metric(xc, yc, zc)
+    adm = be.empty((16, s, s, s))
+    adm[:] = 0.0
+    adm[0] = alpha
+    adm[4] = g
+    adm[7] = g
+    adm[9] = g
+    w = be.empty((5, s, s, s))
+    w[0] = rho
+    w[1:4] = 0.0
+    w[4] = P
     # A = A_b * max(P - pcut Pmax, 0) * (-y, x, 0) on edges; A_z = 0
-    # A_x at (x_c, y_f, z_f), A_y at (x_f, y_c, z_f); shapes padded +1 on face axes
-    Zf, Yf, Xc = np.meshgrid(zf, yf, xc, indexing="ij")
-    Ax = -Yf * st.A_b * st.potential_scale(np.sqrt(Xc ** 2 + Yf ** 2 + Zf ** 2))
-    Zf2, Yc2, Xf2 = np.meshgrid(zf, yc, xf, indexing="ij")
-    Ay = Xf2 * st.A_b * st.potential_scale(np.sqrt(Xf2 ** 2 + Yc2 ** 2 + Zf2 ** 2))
-    # B~x(k,j,i) at (x_f(i), y_c(j), z_c(k)) = dy Az - dz Ay = -(Ay[k+1,j,i] - Ay[k,j,i]) / h
+    # A_x at (x_c, y_f, z_f): shape (s+1, s+1, s); A_y at (x_f, y_c, z_f): (s+1, s, s+1)
+    Ax = -yf * st.A_b * st.potential_scale(_sqrt(xc * xc + yf * yf + zf * zf))
+    Ay = xf * st.A_b * st.potential_scale(_sqrt(xf * xf + yc * yc + zf * zf))
+    # B~x at (x_f, y_c, z_c) = dy Az - dz Ay = -(Ay[k+1] - Ay[k]) / h
     Bx = -(Ay[1:, :, :] - Ay[:-1, :, :]) / h                 # (s, s, s+1)
-    # B~y at (x_c, y_f, z_c) = dz Ax - dx Az = (Ax[k+1,j,i] - Ax[k,j,i]) / h
+    # B~y at (x_c, y_f, z_c) = dz Ax - dx Az = (Ax[k+1] - Ax[k]) / h
     By = (Ax[1:, :, :] - Ax[:-1, :, :]) / h                  # (s, s+1, s)
     # B~z at (x_c, y_c, z_f) = dx Ay - dy Ax
     Bz = (Ay[:, :, 1:] - Ay[:, :, :-1]) / h - (Ax[:, 1:, :] - Ax[:, :-1, :]) / h  # (s+1, s, s)
-    return np.ascontiguousarray(w), [np.ascontiguousarray(Bx), np.ascontiguousarray(By),
-                                     np.ascontiguousarray(Bz)], np.ascontiguousarray(adm)
+    return w, [be.contiguous(Bx), be.contiguous(By), be.contiguous(Bz)], adm
 
 
 def calibrate_field(st: StarSetup, n=64):
@@ -278,18 +329,21 @@ def calibrate_field(st: StarSetup, n=64):
     return st
 
 
-def star_blocks(n_per_side=4, nb=64, ng=3, st: StarSetup | None = None):
+def star_blocks(n_per_side=4, nb=64, ng=3, st: StarSetup | None = None, device=None):
     """The star on a uniform grid of (n_per_side * nb)^3 cells over
     [-box, box]^3, split into n_per_side^3 blocks of nb^3; ghosts are filled
-    by same-level copies between blocks with outflow at the domain edge."""
+    by same-level copies between blocks with outflow at the domain edge.
+    device: None for numpy arrays, else a torch device (arrays built there)."""
     st = st or calibrate_field(StarSetup())
+    backend = _TorchBackend(device) if device is not None else None
     ntot = n_per_side * nb
     h = 2.0 * st.box / ntot
     blocks = []
     for kb in range(n_per_side):
         for jb in range(n_per_side):
             for ib in range(n_per_side):
-                w, bf, adm = _star_block_arrays(st, ib * nb, jb * nb, kb * nb, nb, ng, h, -st.box)
+                w, bf, adm = _star_block_arrays(st, ib * nb, jb * nb, kb * nb, nb, ng, h, -st.box,
+                                                backend)
                 nbr = []
                 for oz in (-1, 0, 1):
                     for oy in (-1, 0, 1):
@@ -303,6 +357,15 @@ def star_blocks(n_per_side=4, nb=64, ng=3, st: StarSetup | None = None):
                                         (-st.box + ib * nb * h, -st.box + jb * nb * h,
                                          -st.box + kb * nb * h)))
     return blocks, st
+
+
+def star_block_numpy(st: StarSetup, ib, jb, kb, n_per_side=4, nb=64, ng=3):
+    """One block (ib, jb, kb) of star_blocks as numpy arrays, ghosts frozen at
+    the analytic data (for CPU samples of the same workload)."""
+    h = 2.0 * st.box / (n_per_side * nb)
+    w, bf, adm = _star_block_arrays(st, ib * nb, jb * nb, kb * nb, nb, ng, h, -st.box)
+    return BlockInit(nb, nb, nb, ng, (h, h, h), w, bf, adm, [-1] * 27, 0, 0,
+                     (-st.box + ib * nb * h, -st.box + jb * nb * h, -st.box + kb * nb * h))
 
 
 def refined_star_blocks(nblocks=1500, nlevels=6, sizes=(16, 24, 32), ng=3, seed_offset=2,

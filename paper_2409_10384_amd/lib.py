@@ -1,0 +1,354 @@
+"""Thin Python binding of libgrmhd.so: argument marshalling only.
+
+Every step of the path runs in the HIP kernels of the library; torch supplies
+device memory and streams.  There is no CPU fallback: importing the binding
+without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrmhd.so")
+_lib = None
+
+# flag bits
+F_C2P_FAIL, F_DFLOOR, F_TAUFLOOR, F_MAGCAP, F_TFLOOR, F_RHOFLOOR, F_FOFC, F_DMP, \
+    F_BRACKET_FALLBACK, F_MAXIT = [1 << b for b in range(10)]
+GF_W, GF_US, GF_BS, GF_FLAGS = 1, 2, 4, 8
+
+
+class GrmhdError(RuntimeError):
+    pass
+
+
+class GrmhdParams(C.Structure):
+    _fields_ = [
+        ("gamma", C.c_double), ("rho_b", C.c_double * 3), ("K0", C.c_double),
+        ("Gam", C.c_double * 4), ("gamma_th", C.c_double), ("rho_atm", C.c_double),
+        ("T_atm", C.c_double), ("f_thr", C.c_double), ("M_max", C.c_double),
+        ("dmp_M", C.c_double), ("c2p_tol", C.c_double),
+        ("eos", C.c_int32), ("npieces", C.c_int32), ("recon", C.c_int32),
+        ("riemann", C.c_int32), ("fofc", C.c_int32), ("c2p_maxit", C.c_int32),
+    ]
+
+
+VP = C.c_void_p
+
+
+class GrmhdBlock(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ng", C.c_int32),
+        ("dx", C.c_double * 3),
+        ("w", VP * 5), ("un", VP * 5), ("us", VP * 5), ("bn", VP * 3), ("bs", VP * 3),
+        ("adm", VP * 16), ("uo", VP * 5), ("bo", VP * 3), ("wo", VP * 5),
+        ("flags", VP), ("scratch", VP), ("nbr", C.c_int32 * 27), ("bc", C.c_int32),
+    ]
+
+
+class C2PStats(C.Structure):
+    _fields_ = [("solves", C.c_uint64), ("evaluations", C.c_uint64), ("fallbacks", C.c_uint64),
+                ("failures", C.c_uint64)]
+
+
+def load():
+    """Load the in-tree libgrmhd.so (built by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GrmhdError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    L.grmhd_scratch_doubles.restype = C.c_int64
+    L.grmhd_scratch_doubles.argtypes = [C.c_int32] * 4
+    L.grmhd_flux_offset.restype = C.c_int64
+    L.grmhd_flux_offset.argtypes = [C.c_int32] * 6
+    L.grmhd_version.restype = C.c_char_p
+    blk = [C.c_void_p, C.c_void_p, C.c_int32]
+    stage = blk + [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
+    for name in ("grmhd_stage", "fofc_correct", "ct_update", "grmhd_update"):
+        getattr(L, name).argtypes = stage
+    L.grmhd_fluxes.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_stage_c2p.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_prim2con_blocks.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_ghost_fill.argtypes = blk + [C.c_int32, C.c_void_p]
+    L.grmhd_dt.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.grmhd_mass.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.prim2con.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_void_p]
+    L.c2p_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    _lib = L
+    return L
+
+
+def check(rc, what):
+    if rc != 0:
+        raise GrmhdError(f"{what} failed with status {rc}")
+
+
+def stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclasses.dataclass
+class MethodParams:
+    """Method options (same meaning as the fields of grmhd_params)."""
+
+    gamma: float = 5.0 / 3.0
+    eos: int = 0
+    npieces: int = 1
+    rho_b: tuple = (0.0, 0.0, 0.0)
+    K0: float = 0.0
+    Gam: tuple = (2.0, 2.0, 2.0, 2.0)
+    gamma_th: float = 1.75
+    rho_atm: float = 1e-10
+    T_atm: float = 1e-12
+    f_thr: float = 1.0
+    M_max: float = 100.0
+    recon: int = 2
+    riemann: int = 1
+    fofc: int = 0
+    dmp_M: float = 0.0
+    c2p_tol: float = 2.220446049250313e-16
+    c2p_maxit: int = 300
+
+    def c(self) -> GrmhdParams:
+        p = GrmhdParams()
+        for f in dataclasses.fields(self):
+            v = getattr(self, f.name)
+            if f.name == "rho_b":
+                p.rho_b = (C.c_double * 3)(*v)
+            elif f.name == "Gam":
+                p.Gam = (C.c_double * 4)(*v)
+            else:
+                setattr(p, f.name, v)
+        return p
+
+
+def _ptr(t: torch.Tensor):
+    return t.data_ptr()
+
+
+def _ptr_array(ts):
+    arr = (C.c_void_p * len(ts))(*[_ptr(t) for t in ts])
+    return arr
+
+
+# ---------------------------------------------------------------------------
+# pointwise entry points
+# ---------------------------------------------------------------------------
+def prim2con(w: torch.Tensor, bt: torch.Tensor, gam: torch.Tensor, params: MethodParams, stream=None):
+    """Eq. 7 on device: w (5,n), bt (3,n), gam (6,n) float64 cuda -> u (5,n)."""
+    L = load()
+    n = w.shape[1]
+    u = torch.empty((5, n), dtype=torch.float64, device=w.device)
+    pw, pb, pg, pu = _ptr_array(list(w)), _ptr_array(list(bt)), _ptr_array(list(gam)), _ptr_array(list(u))
+    check(L.prim2con(n, pw, pb, pg, pu, C.byref(params.c()), stream_ptr(stream)), "prim2con")
+    return u
+
+
+def c2p_batch(u: torch.Tensor, bt: torch.Tensor, gam: torch.Tensor, params: MethodParams,
+              want_mu=False, want_nev=False, stats=False, stream=None):
+    """C2P on device.  u (5,n) is rewritten in place where a floor fires.
+    Returns dict(w, flags[, mu, nev, stats])."""
+    L = load()
+    n = u.shape[1]
+    dev = u.device
+    w = torch.empty((5, n), dtype=torch.float64, device=dev)
+    flags = torch.empty(n, dtype=torch.int16, device=dev)
+    mu = torch.empty(n, dtype=torch.float64, device=dev) if want_mu else None
+    nev = torch.empty(n, dtype=torch.int32, device=dev) if want_nev else None
+    st = torch.zeros(4, dtype=torch.int64, device=dev) if stats else None
+    rc = L.c2p_batch(n, _ptr_array(list(u)), _ptr_array(list(bt)), _ptr_array(list(gam)),
+                     _ptr_array(list(w)), _ptr(flags), C.byref(params.c()), None,
+                     _ptr(st) if st is not None else None, _ptr(mu) if mu is not None else None,
+                     _ptr(nev) if nev is not None else None, stream_ptr(stream))
+    check(rc, "c2p_batch")
+    out = {"w": w, "flags": flags}
+    if mu is not None:
+        out["mu"] = mu
+    if nev is not None:
+        out["nev"] = nev
+    if st is not None:
+        out["stats"] = st
+    return out
+
+
+# ---------------------------------------------------------------------------
+# device mesh of blocks and the RK2 driver
+# ---------------------------------------------------------------------------
+def scratch_doubles(nx, ny, nz, ng):
+    return load().grmhd_scratch_doubles(nx, ny, nz, ng)
+
+
+def flux_offset(nx, ny, nz, ng, d, c):
+    return load().grmhd_flux_offset(nx, ny, nz, ng, d, c)
+
+
+class DeviceMesh:
+    """Blocks resident in HBM with two state sets (A: U^n side, B: stage-1
+    output) for SSP-RK2 in Shu-Osher form, the per-block scratch, and the
+    descriptor tables of both stages (host and device copies)."""
+
+    def __init__(self, blocks, params: MethodParams, device="cuda", stream=None):
+        L = load()
+        self.params = params
+        self.blocks = blocks
+        self.device = torch.device(device)
+        self.stream = stream
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.w0, self.u0, self.b0, self.w1, self.u1, self.b1 = [], [], [], [], [], []
+        self.adm, self.flags, self.scratch = [], [], []
+        def up(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(dev, dtype=torch.float64).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+        for b in blocks:
+            shp = b.shape
+            self.w0.append(up(b.w))
+            self.b0.append([up(x) for x in b.bf])
+            self.adm.append(up(b.adm))
+            self.u0.append(torch.zeros((5,) + shp, **f64))
+            self.w1.append(torch.zeros((5,) + shp, **f64))
+            self.u1.append(torch.zeros((5,) + shp, **f64))
+            self.b1.append([torch.zeros_like(x) for x in self.b0[-1]])
+            self.flags.append(torch.zeros(shp, dtype=torch.int16, device=dev))
+            self.scratch.append(torch.zeros(L.grmhd_scratch_doubles(b.nx, b.ny, b.nz, b.ng), **f64))
+        self.tables = {}
+        for key in ("s1", "s2", "fillA", "fillB"):
+            self.tables[key] = self._make_table(key)
+        # conserved state from the primitives (Eq. 7) on the device, all cells
+        check(L.grmhd_prim2con_blocks(*self._args("fillA"), C.byref(params.c()), self.sp()),
+              "grmhd_prim2con_blocks")
+        self.red = torch.zeros(1, **f64)
+        self.dt_dev = torch.zeros(1, **f64)
+        self.mass_part = torch.zeros(len(blocks), **f64)
+        self.mass_out = torch.zeros(1, **f64)
+
+    def _desc(self, ib, w, un, us, bn, bs, uo, bo, wo):
+        b = self.blocks[ib]
+        d = GrmhdBlock()
+        d.nx, d.ny, d.nz, d.ng = b.nx, b.ny, b.nz, b.ng
+        d.dx = (C.c_double * 3)(*b.dx)
+        d.w = _ptr_array(list(w))
+        d.un = _ptr_array(list(un))
+        d.us = _ptr_array(list(us))
+        d.bn = _ptr_array(bn)
+        d.bs = _ptr_array(bs)
+        d.adm = _ptr_array(list(self.adm[ib]))
+        d.uo = _ptr_array(list(uo))
+        d.bo = _ptr_array(bo)
+        d.wo = _ptr_array(list(wo))
+        d.flags = _ptr(self.flags[ib])
+        d.scratch = _ptr(self.scratch[ib])
+        d.nbr = (C.c_int32 * 27)(*b.nbr)
+        d.bc = b.bc
+        return d
+
+    def _make_table(self, key):
+        n = len(self.blocks)
+        arr = (GrmhdBlock * n)()
+        for ib in range(n):
+            if key == "s1":
+                arr[ib] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
+                                     self.b0[ib], self.u1[ib], self.b1[ib], self.w1[ib])
+            elif key == "s2":
+                arr[ib] = self._desc(ib, self.w1[ib], self.u0[ib], self.u1[ib], self.b0[ib],
+                                     self.b1[ib], self.u0[ib], self.b0[ib], self.w0[ib])
+            elif key == "fillA":
+                arr[ib] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
+                                     self.b0[ib], self.u0[ib], self.b0[ib], self.w0[ib])
+            else:
+                arr[ib] = self._desc(ib, self.w1[ib], self.u1[ib], self.u1[ib], self.b1[ib],
+                                     self.b1[ib], self.u1[ib], self.b1[ib], self.w1[ib])
+        raw = bytes(memoryview(arr).cast("B"))
+        dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        return arr, dev
+
+    def _args(self, key):
+        arr, dev = self.tables[key]
+        return C.cast(arr, C.c_void_p), C.c_void_p(dev.data_ptr()), len(self.blocks)
+
+    def sp(self):
+        return stream_ptr(self.stream)
+
+    # --- steps --------------------------------------------------------------
+    def stage(self, stage, dt=None, dt_dev=None):
+        L = load()
+        a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
+        key = "s1" if stage == 1 else "s2"
+        dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
+        rc = L.grmhd_stage(*self._args(key), C.byref(self.params.c()), dptr,
+                           float(dt) if dt is not None else 0.0, a0, a1, b, self.sp())
+        check(rc, "grmhd_stage")
+
+    def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
+        key = "fillA" if which == 0 else "fillB"
+        check(load().grmhd_ghost_fill(*self._args(key), mask, self.sp()), "grmhd_ghost_fill")
+
+    def compute_dt(self, cfl):
+        """dt on device (kept in self.dt_dev)."""
+        rc = load().grmhd_dt(*self._args("fillA"), C.byref(self.params.c()), cfl,
+                             C.c_void_p(self.red.data_ptr()), C.c_void_p(self.dt_dev.data_ptr()),
+                             self.sp())
+        check(rc, "grmhd_dt")
+        return self.dt_dev
+
+    def rk2_step(self, dt=None, cfl=0.25):
+        """One SSP-RK2 step; dt from the device CFL reduction when dt is None."""
+        if dt is None:
+            self.compute_dt(cfl)
+            self.stage(1, dt_dev=self.dt_dev)
+            self.ghost_fill(1)
+            self.stage(2, dt_dev=self.dt_dev)
+        else:
+            self.stage(1, dt=dt)
+            self.ghost_fill(1)
+            self.stage(2, dt=dt)
+        self.ghost_fill(0)
+
+    def mass(self):
+        check(load().grmhd_mass(*self._args("fillA"), C.c_void_p(self.mass_part.data_ptr()),
+                                C.c_void_p(self.mass_out.data_ptr()), self.sp()), "grmhd_mass")
+        return self.mass_out
+
+    # --- granular steps (for tests) ------------------------------------------
+    def run_steps(self, stage, dt, mode):
+        """mode bits: 1 fluxes, 2 FOFC, 4 CT, 8 update, 16 C2P (host dt)."""
+        L = load()
+        a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
+        args = self._args("s1" if stage == 1 else "s2")
+        pc = C.byref(self.params.c())
+        if mode & 1:
+            check(L.grmhd_fluxes(*args, pc, self.sp()), "grmhd_fluxes")
+        if mode & 2:
+            check(L.fofc_correct(*args, pc, None, dt, a0, a1, b, self.sp()), "fofc_correct")
+        if mode & 4:
+            check(L.ct_update(*args, pc, None, dt, a0, a1, b, self.sp()), "ct_update")
+        if mode & 8:
+            check(L.grmhd_update(*args, pc, None, dt, a0, a1, b, self.sp()), "grmhd_update")
+        if mode & 16:
+            check(L.grmhd_stage_c2p(*args, pc, self.sp()), "grmhd_stage_c2p")
+
+    def flux_view(self, ib, d, c):
+        """face array of flux component c in direction d from block ib's scratch"""
+        b = self.blocks[ib]
+        sz, sy, sx = b.shape
+        shape = [(sz, sy, sx + 1), (sz, sy + 1, sx), (sz + 1, sy, sx)][d]
+        off = flux_offset(b.nx, b.ny, b.nz, b.ng, d, c)
+        n = shape[0] * shape[1] * shape[2]
+        return self.scratch[ib][off:off + n].view(shape)
+
+    def interior(self, t, ib):
+        b = self.blocks[ib]
+        g = b.ng
+        return t[..., g:g + b.nz, g:g + b.ny, g:g + b.nx]
