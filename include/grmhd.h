@@ -179,13 +179,21 @@ int grmhd_prim2con_blocks(const grmhd_block *blk_h, const grmhd_block *blk_d, in
 int prim2con(int64_t n, double *const w[5], double *const bt[3], double *const gam[6],
              double *u[5], const grmhd_params *p, void *stream);
 
-/* Learned guess and bracket for the inversion (not in the paper): a 5-64-64-64-2
-   MLP with SiLU.  Weights are bf16 (row-major [out][in]) with fp32 biases. */
+/* Learned guess and bracket for the inversion (not in the paper): a
+   5-64-64-64-2 perceptron with SiLU on standardised invariants of the scaled
+   state (log10 D, log10(1+q), r/(1+q), b^2/(1+q), s^2/(r^2 b^2)).  Output y0
+   estimates logit(mu), y1 the log of the expected |logit error|; the bracket
+   is logistic(y0 -+ (width_k exp(y1) + width_min)).  Parameters are one flat
+   vector of C2P_MLP_NPARAM values, row-major [out][in] per layer:
+   W1[64][5] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2].
+   Weights are read from the bf16 copy (MFMA operands, fp32 accumulation),
+   biases from the fp32 copy.  Both are device memory. */
+#define C2P_MLP_NPARAM 8834
 typedef struct c2p_mlp {
-  const uint16_t *W[4];   /* bf16 weights: 64x5, 64x64, 64x64, 2x64 */
-  const float *b[4];      /* fp32 biases: 64, 64, 64, 2 */
-  float feat_mean[5], feat_scale[5];  /* feature standardisation */
-  float half_width_min;               /* lower clamp of the relative half-width */
+  const uint16_t *w_bf16;             /* bf16 parameter vector */
+  const float *w_f32;                 /* fp32 parameter vector */
+  float feat_mean[5], feat_scale[5];  /* standardisation: (x - mean) * scale */
+  float width_k, width_min;           /* bracket half-width in logit space */
 } c2p_mlp;
 
 /* C2P statistics accumulated by c2p_batch when stats != NULL (device). */
@@ -202,8 +210,36 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
               uint16_t *flags, const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
               double *mu_out, int32_t *nev_out, void *stream);
 
+/* Learned-bracket training support (device memory throughout).
+   c2p_mlp_features: standardised features [5][n] (fp32) of the conserved
+   states u after the conserved-floor rules and, when w_true != NULL, the
+   targets logit(1/(h W)) [n] of the primitives that generated them.
+   c2p_mlp_forward: y [2][n] from standardised features [5][n].
+   c2p_mlp_to_bf16: theta (fp32) -> theta_bf16.
+   c2p_mlp_train_step: forward + loss + backward over nbatch samples (a
+   multiple of 64) on the MFMA units, one 64-sample partial gradient per
+   workgroup in partial[(nbatch/64) * C2P_MLP_NPARAM], reduced in a fixed
+   order (deterministic); if step >= 1, one Adam step (lr, beta1 0.9, beta2
+   0.999, eps 1e-8, bias correction for `step`) on theta with moments adam_m,
+   adam_v, and theta_bf16 refreshed.  grad_out (C2P_MLP_NPARAM), loss_part
+   (nbatch/64) and loss_out (1) may be NULL.  Loss per sample:
+   0.5 (y0 - t)^2 + 0.5 (y1 - log(|y0 - t| + 1e-4))^2, batch mean. */
+int c2p_mlp_features(int64_t n, double *const u[5], double *const bt[3], double *const gam[6],
+                     double *const w_true[5], const grmhd_params *p, const float mean[5],
+                     const float scale[5], float *feats, float *target, void *stream);
+int c2p_mlp_forward(const c2p_mlp *mlp, int64_t n, const float *feats, float *y, void *stream);
+int c2p_mlp_to_bf16(const float *theta, uint16_t *theta_bf16, void *stream);
+int c2p_mlp_train_step(float *theta, float *adam_m, float *adam_v, uint16_t *theta_bf16,
+                       const float *feats, const float *target, int64_t nbatch, float lr,
+                       int32_t step, float *partial, float *loss_part, float *loss_out,
+                       float *grad_out, void *stream);
+
 /* Library version string and the HIP device architecture it was built for. */
 const char *grmhd_version(void);
+
+/* sizeof of the ABI structs (0 grmhd_params, 1 grmhd_block, 2 c2p_mlp,
+   3 c2p_stats; -1 otherwise), so bindings can check their layouts. */
+int32_t grmhd_struct_size(int32_t which);
 
 #ifdef __cplusplus
 }

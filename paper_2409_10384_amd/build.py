@@ -6,8 +6,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgrmhd.so")
-SOURCES = [os.path.join(HERE, "csrc", "grmhd.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "physics.hpp"), os.path.join(ROOT, "include", "grmhd.h")]
+SOURCES = [os.path.join(HERE, "csrc", "grmhd.hip"), os.path.join(HERE, "csrc", "learned.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "physics.hpp"), os.path.join(HERE, "csrc", "mlp.hpp"),
+           os.path.join(ROOT, "include", "grmhd.h")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -978,6 +978,16 @@ void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_p
 
 }  // namespace
 
+namespace gk {
+Eos make_eos_host(const grmhd_params& p) { return make_eos(p); }
+int check_params_host(const grmhd_params* p) { return check_params(p); }
+}  // namespace gk
+
+extern "C" int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], double* const gam[6],
+                                 double* w[5], uint16_t* flags, const grmhd_params* p,
+                                 const c2p_mlp* mlp, c2p_stats* stats, double* mu_out,
+                                 int32_t* nev_out, void* stream);
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1142,7 +1152,7 @@ int c2p_batch(int64_t n, double* u[5], double* const bt[3], double* const gam[6]
   int r = check_params(p);
   if (r) return r;
   if (n < 0 || !u || !bt || !gam || !w || !flags) return GRMHD_EINVAL;
-  if (mlp) return GRMHD_EUNSUPPORTED;
+  if (mlp) return c2p_batch_learned(n, u, bt, gam, w, flags, p, mlp, stats, mu_out, nev_out, stream);
   if (n == 0) return GRMHD_OK;
   Ptrs5 pw, pu;
   Ptrs3 pb;
@@ -1166,5 +1176,15 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
 }
 
 const char* grmhd_version(void) { return "grmhd 0.1 gfx950 fp64"; }
+
+int32_t grmhd_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return (int32_t)sizeof(grmhd_params);
+    case 1: return (int32_t)sizeof(grmhd_block);
+    case 2: return (int32_t)sizeof(c2p_mlp);
+    case 3: return (int32_t)sizeof(c2p_stats);
+    default: return -1;
+  }
+}
 
 }  // extern "C"

@@ -1,0 +1,137 @@
+// mlp.hpp -- device pieces of the learned C2P guess network (not in the paper):
+// a 5-64-64-64-2 perceptron with SiLU, bf16 operands on the MFMA units with
+// fp32 accumulation.
+//
+// Parameter vector (fp32 master copy and bf16 copy share this layout):
+//   W1 [64][5] | b1 [64] | W2 [64][64] | b2 [64] | W3 [64][64] | b3 [64] |
+//   W4 [2][64] | b4 [2]                         (8834 values, row-major [out][in])
+//
+// MFMA v_mfma_f32_16x16x16_bf16 fragments (64 lanes, lane l, e = 0..3):
+//   A (16x16, rows x k):  A[l % 16][4 (l / 16) + e]
+//   B (16x16, k x cols):  B[4 (l / 16) + e][l % 16]
+//   D (16x16, rows x cols): D[4 (l / 16) + e][l % 16]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gk {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kOffW1 = 0, kOffB1 = 320, kOffW2 = 384, kOffB2 = 4480, kOffW3 = 4544, kOffB3 = 8640,
+              kOffW4 = 8704, kOffB4 = 8832, kNParam = 8834;
+
+// LDS strides (bf16 elements) chosen to spread rows over the LDS banks
+constexpr int kLdIn = 24;   // input tile / W1: 16 used
+constexpr int kLdH = 72;    // hidden activations / W2, W3, W4: 64 used
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu_f(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// contiguous 4 bf16 (8 bytes) from LDS
+__device__ __forceinline__ bf16x4 ld4(const uint16_t* p) { return *(const bf16x4*)p; }
+// 4 bf16 at stride ld
+__device__ __forceinline__ bf16x4 ld4s(const uint16_t* p, int ld) {
+  bf16x4 r;
+  r[0] = (short)p[0];
+  r[1] = (short)p[ld];
+  r[2] = (short)p[2 * ld];
+  r[3] = (short)p[3 * ld];
+  return r;
+}
+
+// Shared weights of one workgroup in LDS
+struct MlpLds {
+  uint16_t W1[64 * kLdIn];
+  uint16_t W2[64 * kLdH];
+  uint16_t W3[64 * kLdH];
+  uint16_t W4[16 * kLdH];
+  float b1[64], b2[64], b3[64], b4[2];
+};
+
+// cooperative load of the bf16 weights (padded) and fp32 biases into LDS
+__device__ __forceinline__ void mlp_load(MlpLds& s, const uint16_t* wh, const float* wf) {
+  for (int x = threadIdx.x; x < 64 * kLdIn; x += blockDim.x) {
+    const int o = x / kLdIn, i = x % kLdIn;
+    s.W1[x] = i < 5 ? wh[kOffW1 + o * 5 + i] : (uint16_t)0;
+  }
+  for (int x = threadIdx.x; x < 64 * kLdH; x += blockDim.x) {
+    const int o = x / kLdH, i = x % kLdH;
+    s.W2[x] = i < 64 ? wh[kOffW2 + o * 64 + i] : (uint16_t)0;
+    s.W3[x] = i < 64 ? wh[kOffW3 + o * 64 + i] : (uint16_t)0;
+  }
+  for (int x = threadIdx.x; x < 16 * kLdH; x += blockDim.x) {
+    const int o = x / kLdH, i = x % kLdH;
+    s.W4[x] = (o < 2 && i < 64) ? wh[kOffW4 + o * 64 + i] : (uint16_t)0;
+  }
+  for (int x = threadIdx.x; x < 64; x += blockDim.x) {
+    s.b1[x] = wf[kOffB1 + x];
+    s.b2[x] = wf[kOffB2 + x];
+    s.b3[x] = wf[kOffB3 + x];
+  }
+  if (threadIdx.x < 2) s.b4[threadIdx.x] = wf[kOffB4 + threadIdx.x];
+}
+
+// One hidden layer on a 16-row tile: out = SiLU(in W^T + b), in [16][ld_in]
+// with KT k-steps of 16, out [16][kLdH] (64 columns).  Optionally keeps the
+// pre-activation derivative SiLU'(z) (fp32 [16][64]) for the backward pass.
+template <int KT>
+__device__ __forceinline__ void mlp_hidden(const uint16_t* in, int ld_in, const uint16_t* W, int ldw,
+                                           const float* bias, uint16_t* out, float* dz) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, q = l >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      const bf16x4 a = ld4(in + r * ld_in + ks * 16 + 4 * q);
+      const bf16x4 b = ld4(W + (nt * 16 + r) * ldw + ks * 16 + 4 * q);
+      acc = mfma16(a, b, acc);
+    }
+    const int col = nt * 16 + r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 4 * q + e;
+      const float z = acc[e] + bias[col];
+      out[row * kLdH + col] = f2bf(silu_f(z));
+      if (dz) dz[row * 64 + col] = dsilu_f(z);
+    }
+  }
+}
+
+// Output layer on a 16-row tile: y[16][2] (fp32) = in W4^T + b4
+__device__ __forceinline__ void mlp_out(const uint16_t* in, const uint16_t* W4, const float* b4,
+                                        float* y) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, q = l >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const bf16x4 a = ld4(in + r * kLdH + ks * 16 + 4 * q);
+    const bf16x4 b = ld4(W4 + r * kLdH + ks * 16 + 4 * q);
+    acc = mfma16(a, b, acc);
+  }
+  if (r < 2) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[(4 * q + e) * 2 + r] = acc[e] + b4[r];
+  }
+}
+
+}  // namespace gk

@@ -377,16 +377,22 @@ __device__ __forceinline__ void atmosphere(const Eos& e, const grmhd_params& p, 
 constexpr uint32_t kFloorBits = GRMHD_F_C2P_FAIL | GRMHD_F_DFLOOR | GRMHD_F_TAUFLOOR |
                                 GRMHD_F_MAGCAP | GRMHD_F_TFLOOR | GRMHD_F_RHOFLOOR | GRMHD_F_MAXIT;
 
-// Inversion of one cell with the atmosphere rules of Sec. III-C.  U
-// (densitized) is rewritten from the final primitives whenever a rule fires.
-// With use_br, [blo, bhi] is tried first (learned bracket).
-__device__ __forceinline__ uint32_t c2p_cell(const Eos& e, const grmhd_params& p, const M3& m,
-                                             double U[5], const double Bt[3], double w[5],
-                                             bool use_br, double blo, double bhi, int& nev,
-                                             double& mu_out) {
-  uint32_t fl = 0;
-  nev = 0;
-  mu_out = 0.0;
+// Inversion state between the conserved-floor rules and the root solve.
+struct C2PWork {
+  KState k;
+  double ru[3], bu[3];
+  uint32_t fl;
+  bool done;      // an atmosphere rule already produced w and U
+};
+
+// Conserved-variable rules of Sec. III-C (non-finite input, D floor,
+// magnetisation cap, tau floor) and the scaled variables of the master
+// function.  When done is set, w and U are final.
+__device__ __forceinline__ C2PWork c2p_prepare(const Eos& e, const grmhd_params& p, const M3& m,
+                                               double U[5], const double Bt[3], double w[5]) {
+  C2PWork cw;
+  cw.fl = 0;
+  cw.done = false;
   const double is = 1.0 / m.sg;
   double D = U[0] * is;
   const double Sx = U[1] * is, Sy = U[2] * is, Sz = U[3] * is;
@@ -400,34 +406,51 @@ __device__ __forceinline__ uint32_t c2p_cell(const Eos& e, const grmhd_params& p
   if (!finite || D < p.f_thr * p.rho_atm) {
     atmosphere(e, p, w);
     prim_to_cons(e, m, w, Bt, U);
-    return finite ? GRMHD_F_DFLOOR : GRMHD_F_C2P_FAIL;
+    cw.fl = finite ? GRMHD_F_DFLOOR : GRMHD_F_C2P_FAIL;
+    cw.done = true;
+    cw.k.D = 1.0; cw.k.q = 0.0; cw.k.r2 = 0.0; cw.k.b2 = 0.0; cw.k.s = 0.0; cw.k.v0sq = 0.0;
+    return cw;
   }
   if (B2 / D > p.M_max) {
     D = B2 / p.M_max;
-    fl |= GRMHD_F_MAGCAP;
+    cw.fl |= GRMHD_F_MAGCAP;
   }
   const double tau_atm = D * eos_eps_from_T(e, D, p.T_atm) + 0.5 * B2;
   if (tau < tau_atm) {
     tau = tau_atm;
-    fl |= GRMHD_F_TAUFLOOR;
+    cw.fl |= GRMHD_F_TAUFLOOR;
   }
-  KState k;
+  KState& k = cw.k;
   k.D = D;
   const double iD = 1.0 / D;
   k.q = tau * iD;
   const double rl[3] = {Sx * iD, Sy * iD, Sz * iD};
-  const double ru[3] = {m.u[0] * rl[0] + m.u[1] * rl[1] + m.u[2] * rl[2],
-                        m.u[1] * rl[0] + m.u[3] * rl[1] + m.u[4] * rl[2],
-                        m.u[2] * rl[0] + m.u[4] * rl[1] + m.u[5] * rl[2]};
-  k.r2 = rl[0] * ru[0] + rl[1] * ru[1] + rl[2] * ru[2];
+  cw.ru[0] = m.u[0] * rl[0] + m.u[1] * rl[1] + m.u[2] * rl[2];
+  cw.ru[1] = m.u[1] * rl[0] + m.u[3] * rl[1] + m.u[4] * rl[2];
+  cw.ru[2] = m.u[2] * rl[0] + m.u[4] * rl[1] + m.u[5] * rl[2];
+  k.r2 = rl[0] * cw.ru[0] + rl[1] * cw.ru[1] + rl[2] * cw.ru[2];
   const double isD = 1.0 / sqrt(D);
-  const double bu[3] = {B[0] * isD, B[1] * isD, B[2] * isD};
+  cw.bu[0] = B[0] * isD; cw.bu[1] = B[1] * isD; cw.bu[2] = B[2] * isD;
   k.b2 = B2 * iD;
-  k.s = rl[0] * bu[0] + rl[1] * bu[1] + rl[2] * bu[2];
+  k.s = rl[0] * cw.bu[0] + rl[1] * cw.bu[1] + rl[2] * cw.bu[2];
   const double z2 = k.r2;      // z0 = r/h0 with h0 = 1
   k.v0sq = z2 / (1.0 + z2);
+  return cw;
+}
 
+// Root solve, recovery, primitive floors and the failure policy.  With
+// use_br, [blo, bhi] is tried first (learned bracket).
+__device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& p, const M3& m,
+                                              C2PWork& cw, double U[5], const double Bt[3],
+                                              double w[5], bool use_br, double blo, double bhi,
+                                              int& nev, double& mu_out) {
+  uint32_t fl = cw.fl;
+  const KState& k = cw.k;
+  const double* ru = cw.ru;
+  const double* bu = cw.bu;
   auto fm = [&](double x) { return k_master(e, k, x); };
+  nev = 0;
+  mu_out = 0.0;
   bool ok = false, have = false;
   double mu = 0.0;
   if (use_br) {
@@ -492,6 +515,21 @@ __device__ __forceinline__ uint32_t c2p_cell(const Eos& e, const grmhd_params& p
   }
   if (fl & kFloorBits) prim_to_cons(e, m, w, Bt, U);
   return fl;
+}
+
+// Inversion of one cell with the atmosphere rules of Sec. III-C.  U
+// (densitized) is rewritten from the final primitives whenever a rule fires.
+__device__ __forceinline__ uint32_t c2p_cell(const Eos& e, const grmhd_params& p, const M3& m,
+                                             double U[5], const double Bt[3], double w[5],
+                                             bool use_br, double blo, double bhi, int& nev,
+                                             double& mu_out) {
+  C2PWork cw = c2p_prepare(e, p, m, U, Bt, w);
+  if (cw.done) {
+    nev = 0;
+    mu_out = 0.0;
+    return cw.fl;
+  }
+  return c2p_solve(e, p, m, cw, U, Bt, w, use_br, blo, bhi, nev, mu_out);
 }
 
 }  // namespace gk

@@ -83,6 +83,12 @@ def load():
                            C.c_void_p]
     L.c2p_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    vp = C.c_void_p
+    L.c2p_mlp_features.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.c2p_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
+    L.c2p_mlp_to_bf16.argtypes = [vp, vp, vp]
+    L.c2p_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_int32, vp, vp,
+                                     vp, vp, vp]
     _lib = L
     return L
 
@@ -352,3 +358,124 @@ class DeviceMesh:
         b = self.blocks[ib]
         g = b.ng
         return t[..., g:g + b.nz, g:g + b.ny, g:g + b.nx]
+
+
+# ---------------------------------------------------------------------------
+# learned guess and bracket for the inversion
+# ---------------------------------------------------------------------------
+NPARAM = 8834
+
+
+class C2PMlp(C.Structure):
+    _fields_ = [("w_bf16", C.c_void_p), ("w_f32", C.c_void_p), ("feat_mean", C.c_float * 5),
+                ("feat_scale", C.c_float * 5), ("width_k", C.c_float), ("width_min", C.c_float)]
+
+
+class LearnedC2P:
+    """Parameters (fp32 master + bf16 copy), Adam moments and feature
+    standardisation of the guess network, resident on the device."""
+
+    def __init__(self, device="cuda", seed=0, width_k=4.0, width_min=1e-3):
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        theta = torch.zeros(NPARAM, dtype=torch.float32)
+        # He-normal weights, zero biases; layout W1 b1 W2 b2 W3 b3 W4 b4
+        offs = [(0, 64, 5), (384, 64, 64), (4544, 64, 64), (8704, 2, 64)]
+        for off, o, i in offs:
+            theta[off:off + o * i] = torch.randn(o * i, generator=g) * (2.0 / i) ** 0.5
+        self.device = torch.device(device)
+        self.theta = theta.to(self.device)
+        self.theta_h = torch.zeros(NPARAM, dtype=torch.int16, device=self.device)
+        self.m = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.mean = [0.0] * 5
+        self.scale = [1.0] * 5
+        self.width_k, self.width_min = width_k, width_min
+        self.step = 0
+        self.refresh_bf16()
+
+    def refresh_bf16(self, stream=None):
+        check(load().c2p_mlp_to_bf16(_ptr(self.theta), _ptr(self.theta_h), stream_ptr(stream)),
+              "c2p_mlp_to_bf16")
+
+    def c(self):
+        s = C2PMlp()
+        s.w_bf16 = _ptr(self.theta_h)
+        s.w_f32 = _ptr(self.theta)
+        s.feat_mean = (C.c_float * 5)(*self.mean)
+        s.feat_scale = (C.c_float * 5)(*self.scale)
+        s.width_k, s.width_min = self.width_k, self.width_min
+        return s
+
+    def features(self, u, bt, gam, params: MethodParams, w_true=None, standardise=True, stream=None):
+        """features [5][n] (fp32) and targets [n] (when w_true is given)"""
+        n = u.shape[1]
+        feats = torch.empty((5, n), dtype=torch.float32, device=u.device)
+        target = torch.empty(n, dtype=torch.float32, device=u.device) if w_true is not None else None
+        mean = (C.c_float * 5)(*(self.mean if standardise else [0.0] * 5))
+        scale = (C.c_float * 5)(*(self.scale if standardise else [1.0] * 5))
+        rc = load().c2p_mlp_features(n, _ptr_array(list(u)), _ptr_array(list(bt)), _ptr_array(list(gam)),
+                                     _ptr_array(list(w_true)) if w_true is not None else None,
+                                     C.byref(params.c()), C.cast(mean, C.c_void_p),
+                                     C.cast(scale, C.c_void_p), _ptr(feats),
+                                     _ptr(target) if target is not None else None, stream_ptr(stream))
+        check(rc, "c2p_mlp_features")
+        return feats, target
+
+    def fit_standardisation(self, raw_feats):
+        """mean and 1/std of raw features (setup, not the hot path)"""
+        self.mean = [float(x) for x in raw_feats.double().mean(dim=1).cpu()]
+        sd = raw_feats.double().std(dim=1).cpu()
+        self.scale = [float(1.0 / max(x, 1e-12)) for x in sd]
+
+    def forward(self, feats, stream=None):
+        n = feats.shape[1]
+        y = torch.empty((2, n), dtype=torch.float32, device=feats.device)
+        mlp = self.c()
+        check(load().c2p_mlp_forward(C.byref(mlp), n, _ptr(feats), _ptr(y), stream_ptr(stream)),
+              "c2p_mlp_forward")
+        return y
+
+    def train_step(self, feats, target, lr=1e-3, apply=True, stream=None, want_grad=False):
+        """one Adam step on a batch (feats [5][nb], target [nb], nb % 64 == 0)"""
+        nb = feats.shape[1]
+        nwg = nb // 64
+        partial = torch.empty(nwg * NPARAM, dtype=torch.float32, device=feats.device)
+        loss_part = torch.empty(nwg, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        grad = torch.empty(NPARAM, dtype=torch.float32, device=feats.device) if want_grad else None
+        if apply:
+            self.step += 1
+        rc = load().c2p_mlp_train_step(_ptr(self.theta), _ptr(self.m), _ptr(self.v), _ptr(self.theta_h),
+                                       _ptr(feats), _ptr(target), nb, float(lr),
+                                       self.step if apply else 0, _ptr(partial), _ptr(loss_part),
+                                       _ptr(loss), _ptr(grad) if grad is not None else None,
+                                       stream_ptr(stream))
+        check(rc, "c2p_mlp_train_step")
+        return loss, grad
+
+
+def c2p_batch_learned(u, bt, gam, params: MethodParams, net: LearnedC2P, want_mu=False,
+                      want_nev=False, stats=False, stream=None):
+    """c2p_batch with the learned bracket (same outputs as c2p_batch)."""
+    L = load()
+    n = u.shape[1]
+    dev = u.device
+    w = torch.empty((5, n), dtype=torch.float64, device=dev)
+    flags = torch.empty(n, dtype=torch.int16, device=dev)
+    mu = torch.empty(n, dtype=torch.float64, device=dev) if want_mu else None
+    nev = torch.empty(n, dtype=torch.int32, device=dev) if want_nev else None
+    st = torch.zeros(4, dtype=torch.int64, device=dev) if stats else None
+    mlp = net.c()
+    rc = L.c2p_batch(n, _ptr_array(list(u)), _ptr_array(list(bt)), _ptr_array(list(gam)),
+                     _ptr_array(list(w)), _ptr(flags), C.byref(params.c()), C.byref(mlp),
+                     _ptr(st) if st is not None else None, _ptr(mu) if mu is not None else None,
+                     _ptr(nev) if nev is not None else None, stream_ptr(stream))
+    check(rc, "c2p_batch (learned)")
+    out = {"w": w, "flags": flags}
+    if mu is not None:
+        out["mu"] = mu
+    if nev is not None:
+        out["nev"] = nev
+    if st is not None:
+        out["stats"] = st
+    return out

@@ -1,0 +1,158 @@
+"""GPU tests of the learned C2P guess: MFMA forward and backward against the
+FP64 oracle on the same bf16-rounded weights and inputs, training on the GPU,
+and the trained network's gain over the plain bracketed solve at an equal
+final error with no unrecovered failures."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+from paper_2409_10384_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+torch = pytest.importorskip("torch")
+
+OFFS = [(0, 64, 5), (384, 64, 64), (4544, 64, 64), (8704, 2, 64)]
+BOFFS = [320, 4480, 8640, 8832]
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10384_amd import lib
+    lib.load()
+    return lib
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16(x):
+    a = np.asarray(x, dtype=np.float32).astype(np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) & 0xFFFF0000
+    return a.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unflatten(theta, round_w=True):
+    ps = []
+    for (off, o, i), bo in zip(OFFS, BOFFS):
+        W = theta[off:off + o * i].reshape(o, i).astype(np.float64)
+        ps.append([bf16(W) if round_w else W, theta[bo:bo + o].astype(np.float64)])
+    return ps
+
+
+def flat_grads(grads):
+    out = np.zeros(8834)
+    for (off, o, i), bo, (dW, db) in zip(OFFS, BOFFS, grads):
+        out[off:off + o * i] = dW.ravel()
+        out[bo:bo + o] = db
+    return out
+
+
+def cosine(a, b):
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_mfma_forward_matches_oracle(G):
+    say("learned: MFMA forward vs FP64 oracle on bf16-rounded operands")
+    net = G.LearnedC2P(seed=3)
+    # non-zero biases
+    net.theta[320:384] = torch.linspace(-0.5, 0.5, 64, device=net.theta.device)
+    net.theta[8832:8834] = torch.tensor([0.3, -0.2], device=net.theta.device)
+    net.refresh_bf16()
+    rng = np.random.default_rng(7)
+    n = 4096 + 37                              # several tiles and a ragged tail
+    x = rng.normal(size=(5, n)).astype(np.float32)
+    y = net.forward(torch.as_tensor(x).cuda()).cpu().numpy()
+    ps = unflatten(net.theta.cpu().numpy())
+    yref, _ = M.forward(ps, bf16(x.T))
+    for c in range(2):
+        assert cosine(y[c], yref[:, c]) > 0.9999
+        rel = np.linalg.norm(y[c] - yref[:, c]) / np.linalg.norm(yref[:, c])
+        assert rel < 2e-2, rel
+
+
+def test_mfma_gradients_match_oracle(G):
+    say("learned: MFMA backward vs FP64 oracle")
+    net = G.LearnedC2P(seed=4)
+    rng = np.random.default_rng(8)
+    nb = 1024
+    x = rng.normal(size=(5, nb)).astype(np.float32)
+    t = rng.normal(size=nb).astype(np.float32)
+    _, grad = net.train_step(torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda(), apply=False,
+                             want_grad=True)
+    g = grad.cpu().numpy().astype(np.float64)
+    ps = unflatten(net.theta.cpu().numpy())
+    y, cache = M.forward(ps, bf16(x.T))
+    _, dy = M.loss_and_grad_out(y, t.astype(np.float64))
+    gref = flat_grads(M.backward(ps, cache, dy))
+    for (off, o, i), bo in zip(OFFS, BOFFS):
+        for a, b in ((g[off:off + o * i], gref[off:off + o * i]), (g[bo:bo + o], gref[bo:bo + o])):
+            c = cosine(a, b)
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            say(f"  tensor at {off}: cosine {c:.6f} rel {rel:.2e}")
+            assert c > 0.999 and rel < 2e-2, (off, c, rel)
+    # determinism: the same step twice gives bitwise the same gradient
+    _, grad2 = net.train_step(torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda(), apply=False,
+                              want_grad=True)
+    assert torch.equal(grad, grad2)
+
+
+C4P = dict(gamma=5.0 / 3.0, rho_atm=1e-20, T_atm=1e-30, f_thr=1.0, M_max=1e30, c2p_tol=1e-12)
+
+
+def _c4_device(G, n, seed):
+    st = inputs.c2p_states(n, seed_offset=seed)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    w, bt, gam = d(st["w"]), d(st["bt"]), d(st["gam"])
+    u = G.prim2con(w, bt, gam, G.MethodParams(**C4P))
+    return st, w, bt, gam, u
+
+
+def train_network(G, n_train=1 << 18, steps=1500, batch=4096, seed=0):
+    p = G.MethodParams(**C4P)
+    st, w, bt, gam, u = _c4_device(G, n_train, 300)
+    net = G.LearnedC2P(seed=seed)
+    raw, _ = net.features(u, bt, gam, p, standardise=False)
+    net.fit_standardisation(raw)
+    feats, target = net.features(u, bt, gam, p, w_true=w)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    losses = []
+    for it in range(steps):
+        idx = torch.randint(0, n_train, (batch,), device="cuda", generator=gen)
+        lr = 2e-3 if it < steps * 0.7 else 5e-4
+        loss, _ = net.train_step(feats[:, idx].contiguous(), target[idx].contiguous(), lr=lr)
+        if it % 100 == 0 or it == steps - 1:
+            losses.append(float(loss.item()))
+    return net, losses
+
+
+def test_learned_c2p_beats_plain_at_equal_error(G):
+    say("learned: train on prim->cons pairs, compare with the plain solve")
+    net, losses = train_network(G)
+    say(f"  loss trace {['%.3g' % x for x in losses]}")
+    assert losses[-1] < 0.5 * losses[0]
+    p = G.MethodParams(**C4P)
+    st, w, bt, gam, u = _c4_device(G, 1 << 16, 301)
+    plain = G.c2p_batch(u.clone(), bt, gam, p, want_mu=True, want_nev=True, stats=True)
+    learned = G.c2p_batch_learned(u.clone(), bt, gam, p, net, want_mu=True, want_nev=True, stats=True)
+    eps = st["w"][4] / (2.0 / 3.0 * st["w"][0])
+    mus = 1.0 / ((1 + eps + st["w"][4] / st["w"][0]) * st["W"])
+    mu_p = plain["mu"].cpu().numpy()
+    mu_l = learned["mu"].cpu().numpy()
+    assert np.max(np.abs(mu_p - mus) / mus) < 1e-10
+    assert np.max(np.abs(mu_l - mus) / mus) < 1e-10
+    fl = learned["flags"].cpu().numpy().astype(np.uint16)
+    assert not np.any(fl & O.F_C2P_FAIL)
+    n_p = plain["nev"].double().mean().item()
+    n_l = learned["nev"].double().mean().item()
+    fb = float(np.mean((fl & O.F_BRACKET_FALLBACK) != 0))
+    say(f"  mean master evaluations plain {n_p:.2f} learned {n_l:.2f}; fallback rate {fb:.4f}")
+    assert n_l < n_p
+    st_l = learned["stats"].cpu().numpy()
+    assert st_l[0] == u.shape[1] and st_l[3] == 0

