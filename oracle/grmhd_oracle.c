@@ -70,6 +70,13 @@ enum {
 };
 #define F_FLOORS (F_C2P_FAIL | F_DFLOOR | F_TAUFLOOR | F_MAGCAP | F_TFLOOR | F_RHOFLOOR | F_MAXIT)
 
+/* Reading of "a state requires a floor" (Sec. III-C): the tau and T floors
+   fire only when the value lies below the floor by more than a rounding
+   margin.  A cell sitting at the atmosphere values is recovered at
+   T_atm (1 +- a few ulp); without the margin such a cell would randomly
+   count as needing the floor (and be FOFC-flagged) on rounding alone. */
+#define FLOOR_MARGIN 1e-10
+
 /* ------------------------------------------------------------------------- */
 /* equation of state                                                          */
 /* ------------------------------------------------------------------------- */
@@ -381,7 +388,7 @@ static int c2p_point(const eos_t *e, const or_params *p, const met3 *m, double U
   }
   /* rule: tau floor for a fluid at rest at T_atm:  tau_atm = D eps(D,T_atm) + B^2/2 */
   double tau_atm = D * eos_eps_T(e, D, p->T_atm) + 0.5 * B2;
-  if (tau < tau_atm) {
+  if (tau < tau_atm * (1.0 - FLOOR_MARGIN)) {
     tau = tau_atm;
     flags |= F_TAUFLOOR;
   }
@@ -473,7 +480,7 @@ static int c2p_point(const eos_t *e, const or_params *p, const met3 *m, double U
   if (w[0] < p->f_thr * p->rho_atm) {
     atmosphere_prims(e, p, w);
     flags |= F_RHOFLOOR;
-  } else if (eos_T(e, w[0], w[4]) < p->T_atm) {
+  } else if (eos_T(e, w[0], w[4]) < p->T_atm * (1.0 - FLOOR_MARGIN)) {
     w[4] = eos_P_T(e, w[0], p->T_atm);
     flags |= F_TFLOOR;
   }

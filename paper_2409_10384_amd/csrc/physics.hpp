@@ -19,6 +19,9 @@
 namespace gk {
 
 constexpr double kEps = 2.220446049250313e-16;
+// tau and T floors fire only below (1 - margin) x the floor: a state at the
+// atmosphere values, recovered within rounding of T_atm, does not need it
+constexpr double kFloorMargin = 1e-10;
 
 // ---------------------------------------------------------------------------
 // EOS: derived piece constants are computed once on the host
@@ -416,7 +419,7 @@ __device__ __forceinline__ C2PWork c2p_prepare(const Eos& e, const grmhd_params&
     cw.fl |= GRMHD_F_MAGCAP;
   }
   const double tau_atm = D * eos_eps_from_T(e, D, p.T_atm) + 0.5 * B2;
-  if (tau < tau_atm) {
+  if (tau < tau_atm * (1.0 - kFloorMargin)) {
     tau = tau_atm;
     cw.fl |= GRMHD_F_TAUFLOOR;
   }
@@ -501,7 +504,7 @@ __device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& 
       if (w[0] < p.f_thr * p.rho_atm) {
         atmosphere(e, p, w);
         fl |= GRMHD_F_RHOFLOOR;
-      } else if (eos_T_from_P(e, w[0], w[4]) < p.T_atm) {
+      } else if (eos_T_from_P(e, w[0], w[4]) < p.T_atm * (1.0 - kFloorMargin)) {
         w[4] = eos_P_from_T(e, w[0], p.T_atm);
         fl |= GRMHD_F_TFLOOR;
       }

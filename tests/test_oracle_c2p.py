@@ -183,6 +183,18 @@ def test_rule_temperature_floor_keeps_rho_and_velocity():
     np.testing.assert_allclose(u2[:, 0], uref[:, 0], rtol=1e-15)
 
 
+def test_state_at_the_floor_values_does_not_need_the_floor():
+    """a fluid at rest at exactly (rho, T_atm) inverts back within rounding of
+    T_atm and does not count as needing the T or tau floor"""
+    rng = np.random.default_rng(9)
+    for rho in 10 ** rng.uniform(-5, 0, size=50):
+        P = rho * P_ATM.T_atm
+        w, bt, u = one(rho, [0.0, 0.0, 0.0], P, [0.0, 0.0, 0.0])
+        _, w2, fl, _, _ = O.c2p(u, bt, FLAT, P_ATM)
+        assert fl[0] == 0, (rho, fl[0])
+        assert abs(w2[4, 0] - P) <= 1e-12 * P
+
+
 def test_rule_primitive_density_floor_after_inversion():
     # D above f_thr rho_atm, but rho = D/W below it
     W = 3.0
