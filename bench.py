@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the GRMHD Runge-Kutta step on one MI355X.
 
-Workload (default): the synthetic star on a 256^3 grid split into 64
-MeshBlocks of 64^3 cells (3 ghost layers), Gamma = 2 ideal gas, WENOZ + HLLE,
-FOFC + DMP (M = 1.1), atmosphere rho_atm = 1.28e-13, T_atm = 1.28e-11,
-f_thr = 0.1; one step = SSP-RK2 (two stages, ghost exchange after each) with
-dt from the on-device CFL reduction (CFL 0.25).  Inputs are resident in HBM
-before timing starts.
+Workload: the synthetic star on a 256^3 grid split into 64 MeshBlocks of 64^3
+cells (3 ghost layers), Gamma = 2 ideal gas, WENOZ + HLLE, FOFC + DMP
+(M = 1.1), atmosphere rho_atm = 1.28e-13, T_atm = 1.28e-11, f_thr = 0.1.  One
+step = SSP-RK2 (two stages, ghost exchange after each) with dt from the
+on-device CFL reduction (CFL 0.25).  Inputs are resident in HBM before timing
+starts.
 
-Metric: zone-updates/s = interior cells x RK2 steps / second.
-Prints one JSON line.
+Metric: zone-updates/s = interior cells x RK2 steps / second (plain C2P).
+Also reported: C2P solves/s on 2^24 random states at root tolerance 1e-12
+(plain bracket vs learned bracket, network trained in this run on the GPU),
+the roofline of the dominant kernel (HIP events on the launch stream), the
+whole-step roofline, and the FP64 oracle on the host as a CPU baseline.
+Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBS = 8000.0
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -27,15 +34,89 @@ def log(*a):
 
 STAR_PARAMS = dict(gamma=2.0, rho_atm=1.28e-13, T_atm=1.28e-11, f_thr=0.1, M_max=100.0, recon=2,
                    riemann=1, fofc=1, dmp_M=1.1)
+C2P_PARAMS = dict(gamma=5.0 / 3.0, rho_atm=1e-20, T_atm=1e-30, f_thr=1.0, M_max=1e30, c2p_tol=1e-12)
 
 
+# ---------------------------------------------------------------------------
+# algorithmic bytes (minimum HBM traffic of each kernel if every value it
+# needs were read once and every value it produces written once)
+# ---------------------------------------------------------------------------
+def kernel_bytes(family, blocks):
+    tot = 0
+    for b in blocks:
+        n = (b.nx, b.ny, b.nz)
+        g = b.ng
+        cells_in = n[0] * n[1] * n[2]
+        if family.startswith("flux_"):
+            d = "xyz".index(family[-1])
+            box, faces = 1, 1
+            for a in range(3):
+                box *= (n[a] + 2 * g) if a == d else (n[a] + 2)
+                faces *= (n[a] + 1) if a == d else (n[a] + 2)
+            # stencil inputs: rho, W v^i, P, 2 transverse B, 10 metric fields;
+            # per face: normal field in, 7 flux components out
+            tot += 8 * (17 * box + 8 * faces)
+        elif family == "update":
+            # U^n 5, U^(s) 5, w 5, B~ 3, ADM 16, flux divergence 15 in; U 5 out
+            tot += 8 * 54 * cells_in
+        elif family == "fofc_flags":
+            # U^n 5, U^(s) 5, B~ 3, metric 6, fluxes 15 in; flag out
+            tot += 8 * 34 * cells_in + 2 * cells_in
+        elif family == "stage_c2p":
+            # U 5 in/out, B~ 3, metric 6 in, w 5 out, flag in/out
+            tot += 8 * 24 * cells_in + 4 * cells_in
+        elif family == "dt":
+            tot += 8 * 18 * cells_in
+        elif family == "bcc":
+            m = (n[0] + 2 * g) * (n[1] + 2 * g) * (n[2] + 2 * g)
+            tot += 8 * 12 * m
+        else:
+            return None
+    return tot
+
+
+def step_bytes(blocks):
+    """whole RK2 step: per stage, 18 stencil-read fields over the padded block
+    (w 5, B~ 3, alpha, beta 3, gamma 6) plus pointwise K 6 and U^n 5 (stage 2
+    adds U^(s) 5 and B~^n 3), writes U 5, B~ 3, w 5"""
+    tot = 0
+    for b in blocks:
+        m = (b.nx + 2 * b.ng) * (b.ny + 2 * b.ng) * (b.nz + 2 * b.ng)
+        c = b.nx * b.ny * b.nz
+        tot += 8 * (18 * m + 11 * c + 13 * c) + 8 * (18 * m + 19 * c + 13 * c)
+    return tot
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2409_10384_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_2409_10384_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(family, launches_per_step):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    null when the kernel sources changed since the counters were taken"""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(family)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
 def cpu_baseline(st, n_per_side, nb, params_kw, target_s=12.0):
     """The FP64 oracle as it stands, on one block of the same workload (the
     block at the star's centre, ghosts frozen at the analytic data), RK2
     steps until ~target_s seconds of CPU work."""
     from paper_2409_10384_amd import inputs
     import oracle as O
-    threads = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     c = n_per_side // 2
     blk = inputs.star_block_numpy(st, c, c, c, n_per_side, nb)
     m = O.Mesh([blk], O.Params(**params_kw))
@@ -48,9 +129,117 @@ def cpu_baseline(st, n_per_side, nb, params_kw, target_s=12.0):
         if el > target_s or steps >= 50:
             break
     zu = blk.nx * blk.ny * blk.nz * steps / el
-    return {"value": zu, "unit": "zone-updates/s", "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
-            "kind": "oracle",
-            "sample": f"one {blk.nx}^3 block of the star (frozen ghosts), {steps} RK2 steps, {el:.1f} s"}
+    return {"value": zu, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one {blk.nx}^3 block of the star (frozen ghosts), {steps} RK2 steps, "
+                      f"{el:.1f} s, OpenMP over k-slabs"}
+
+
+def star_section(args, torch, inputs, lib):
+    t0 = time.perf_counter()
+    log(f"building inputs: star, {args.blocks_per_side}^3 blocks of {args.block}^3")
+    blocks, st = inputs.star_blocks(n_per_side=args.blocks_per_side, nb=args.block, device="cuda")
+    params = lib.MethodParams(**STAR_PARAMS)
+    mesh = lib.DeviceMesh(blocks, params, device="cuda")
+    torch.cuda.synchronize()
+    log(f"mesh resident in HBM ({time.perf_counter() - t0:.1f} s)")
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    for _ in range(args.warmup):
+        mesh.rk2_step(cfl=0.25)
+    torch.cuda.synchronize()
+    log("warmup done")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    lib.timing(True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        mesh.rk2_step(cfl=0.25)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    fam = lib.timing_read()
+    lib.timing(False)
+    value = ncell * args.steps / (ms * 1e-3)
+    log(f"timed {args.steps} steps: {ms:.2f} ms, {value:.3e} zone-updates/s")
+    breakdown = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1]} for k, v in fam.items()}
+    dom = max(fam.items(), key=lambda kv: kv[1][0])[0]
+    dms = fam[dom][0] / fam[dom][1]
+    nbytes = kernel_bytes(dom, blocks)
+    roof = None
+    if nbytes is not None:
+        ach = nbytes / (dms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": lib.KERNEL_OF_FAMILY.get(dom, dom), "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": pmc_traffic(dom, None), "bytes_per_launch": nbytes,
+                "avg_launch_ms": dms}
+    sb = step_bytes(blocks)
+    path = {"bound": "hbm", "algorithmic_bytes_per_step": sb,
+            "achieved": sb / (ms / args.steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    path["frac"] = path["achieved"] / HBM_PEAK_GBS
+    mass = float(mesh.mass().item())
+    return dict(value=value, ms=ms, ncell=ncell, roofline=roof, path=path, breakdown=breakdown,
+                st=st, mass=mass)
+
+
+def c2p_section(args, torch, inputs, lib):
+    """C2P solves/s on 2^k random states, plain vs learned bracket"""
+    n = 1 << args.c2p_log2
+    p = lib.MethodParams(**C2P_PARAMS)
+    log(f"c2p: {n} states")
+    s = inputs.c2p_states_torch(n, seed_offset=3, device="cuda")
+    u0 = lib.prim2con(s["w"], s["bt"], s["gam"], p)
+    eps = s["w"][4] / ((C2P_PARAMS["gamma"] - 1.0) * s["w"][0])
+    mu_exact = 1.0 / ((1.0 + eps + s["w"][4] / s["w"][0]) * s["W"])
+    # train the guess network on separate states (own forward/backward kernels)
+    t0 = time.perf_counter()
+    tr = inputs.c2p_states_torch(1 << 18, seed_offset=300, device="cuda")
+    ut = lib.prim2con(tr["w"], tr["bt"], tr["gam"], p)
+    net = lib.LearnedC2P(seed=0)
+    raw, _ = net.features(ut, tr["bt"], tr["gam"], p, standardise=False)
+    net.fit_standardisation(raw)
+    feats, target = net.features(ut, tr["bt"], tr["gam"], p, w_true=tr["w"])
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    steps = args.train_steps
+    for it in range(steps):
+        idx = torch.randint(0, feats.shape[1], (4096,), device="cuda", generator=gen)
+        loss, _ = net.train_step(feats[:, idx].contiguous(), target[idx].contiguous(),
+                                 lr=2e-3 if it < 0.7 * steps else 5e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained {steps} steps in {train_s:.1f} s, final loss {float(loss.item()):.3g}")
+    res = {}
+    for kind in ("plain", "learned"):
+        times = []
+        for rep in range(args.c2p_reps + 1):
+            u = u0.clone()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if kind == "plain":
+                out = lib.c2p_batch(u, s["bt"], s["gam"], p, want_mu=True, want_nev=True, stats=True)
+            else:
+                out = lib.c2p_batch_learned(u, s["bt"], s["gam"], p, net, want_mu=True, want_nev=True,
+                                            stats=True)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
+        err = ((out["mu"] - mu_exact).abs() / mu_exact).max().item()
+        stt = out["stats"].cpu().tolist()
+        res[kind] = {"solves_per_s": n / (ms * 1e-3), "ms": ms, "max_mu_rel_err": err,
+                     "mean_master_evals": stt[1] / stt[0], "fallback_rate": stt[2] / stt[0],
+                     "unrecovered_failures": int(stt[3])}
+        log(f"c2p {kind}: {res[kind]['solves_per_s']:.3e} solves/s, err {err:.2e}, "
+            f"evals {res[kind]['mean_master_evals']:.2f}, fallback {res[kind]['fallback_rate']:.4f}")
+    res["states"] = n
+    res["train_steps"] = steps
+    res["train_s"] = train_s
+    res["learned_speedup"] = res["learned"]["solves_per_s"] / res["plain"]["solves_per_s"]
+    res["bytes_per_solve"] = 153
+    return res
 
 
 def main():
@@ -60,7 +249,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--blocks-per-side", type=int, default=4)
     ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--c2p-log2", type=int, default=24)
+    ap.add_argument("--c2p-reps", type=int, default=3)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--no-c2p", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB plain copy first (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -72,52 +267,42 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lib.load()
-    t0 = time.perf_counter()
-    log(f"building inputs: star, {args.blocks_per_side}^3 blocks of {args.block}^3")
-    blocks, st = inputs.star_blocks(n_per_side=args.blocks_per_side, nb=args.block, device="cuda")
-    log(f"inputs built in {time.perf_counter() - t0:.1f} s")
-    params = lib.MethodParams(**STAR_PARAMS)
-    mesh = lib.DeviceMesh(blocks, params, device="cuda")
-    torch.cuda.synchronize()
-    log(f"mesh resident in HBM ({time.perf_counter() - t0:.1f} s)")
-    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
-    for s in range(args.warmup):
-        mesh.rk2_step(cfl=0.25)
-    torch.cuda.synchronize()
-    log("warmup done")
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for s in range(args.steps):
-        mesh.rk2_step(cfl=0.25)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    value = ncell * args.steps / (ms * 1e-3)
-    log(f"timed {args.steps} steps: {ms:.2f} ms, {value:.3e} zone-updates/s")
+    if args.calibrate_copy:
+        # one plain copy of known size, for scaling hardware traffic counters
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        lib.copy(a, b)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+        del a, b
+    star = star_section(args, torch, inputs, lib)
     out = {
         "metric": "zone-updates/s per GPU (GRMHD SSP-RK2 step, plain C2P)",
-        "value": value,
+        "value": star["value"],
         "unit": "zone-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": star["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"star {args.blocks_per_side * args.block}^3 as "
-                               f"{args.blocks_per_side ** 3} MeshBlocks of {args.block}^3, Gamma=2, "
-                               f"WENOZ+HLLE, FOFC+DMP, RK2 CFL 0.25",
-                   "cells": ncell},
+                               f"{args.blocks_per_side ** 3} MeshBlocks of {args.block}^3 (+3 ghosts), "
+                               f"Gamma=2, WENOZ+HLLE, FOFC+DMP M=1.1, SSP-RK2 CFL 0.25",
+                   "cells": star["ncell"]},
+        "roofline": star["roofline"],
+        "path_roofline": star["path"],
+        "kernel_breakdown": star["breakdown"],
     }
+    if not args.no_c2p:
+        out["c2p"] = c2p_section(args, torch, inputs, lib)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(st, args.blocks_per_side, args.block, STAR_PARAMS)
+        out["cpu_baseline"] = cpu_baseline(star["st"], args.blocks_per_side, args.block, STAR_PARAMS)
     print(json.dumps(out), flush=True)
 
 

@@ -237,6 +237,21 @@ int c2p_mlp_train_step(float *theta, float *adam_m, float *adam_v, uint16_t *the
 /* Library version string and the HIP device architecture it was built for. */
 const char *grmhd_version(void);
 
+/* Per-kernel timing for measurement.  grmhd_timing(1) creates an event pool
+   (once) and starts recording HIP events on the launch stream around every
+   launch of each kernel family; grmhd_timing(0) stops.  grmhd_timing_read
+   waits for the recorded events and returns the accumulated milliseconds and
+   launch count of a family since timing was enabled.  Families: 0/1/2
+   face fluxes x/y/z, 3 FOFC flags, 4 FOFC refluxing, 5 CT, 6 update with
+   sources, 7 stage C2P, 8 ghost fill, 9 dt, 10 cell-centred field,
+   11 c2p_batch plain, 12 c2p_batch learned, 13 MLP training. */
+int grmhd_timing(int32_t on);
+int grmhd_timing_read(int32_t family, double *ms, int64_t *launches);
+
+/* Plain streaming copy dst[0..n) = src[0..n) (device memory), used to
+   calibrate hardware traffic counters against a kernel of known bytes. */
+int grmhd_copy(const double *src, double *dst, int64_t n, void *stream);
+
 /* sizeof of the ABI structs (0 grmhd_params, 1 grmhd_block, 2 c2p_mlp,
    3 c2p_stats; -1 otherwise), so bindings can check their layouts. */
 int32_t grmhd_struct_size(int32_t which);

@@ -11,6 +11,7 @@
 
 #include "grmhd.h"
 #include "physics.hpp"
+#include "timing.hpp"
 
 using namespace gk;
 
@@ -933,9 +934,19 @@ int last_err() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_EHIP;
 void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
                 const Eos& e, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
-  k_bcc<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
-  k_flux<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
-  k_flux<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
+  {
+    TIMED(T_BCC, s);
+    k_bcc<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
+  }
+  {
+    TIMED(T_FLUX_X, s);
+    k_flux<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
+  }
+  {
+    TIMED(T_FLUX_Y, s);
+    k_flux<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
+  }
+  TIMED(T_FLUX_Z, s);
   k_flux<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
 }
 
@@ -945,8 +956,15 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   const Sizes z = max_sizes(h, nblk);
   k_clear_flags<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
   if (!p.fofc) return;
-  k_fofc_flags<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
-  k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d, 8);
+  {
+    TIMED(T_FOFC_FLAGS, s);
+    k_fofc_flags<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
+  }
+  {
+    TIMED(T_GHOST, s);
+    k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d, 8);
+  }
+  TIMED(T_FOFC_FIX, s);
   k_fofc_fix<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
   k_fofc_fix<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
   k_fofc_fix<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
@@ -955,6 +973,7 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
 void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
             double a0, double a1, double b, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
+  TIMED(T_CT, s);
   k_emf_cc<<<grid_for(z.ext_cells, nblk), kThreads, 0, s>>>(d);
   k_emf_edge<0><<<grid_for(z.edges[0], nblk), kThreads, 0, s>>>(d);
   k_emf_edge<1><<<grid_for(z.edges[1], nblk), kThreads, 0, s>>>(d);
@@ -967,18 +986,29 @@ void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* 
 void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos& e,
                 const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
+  TIMED(T_UPDATE, s);
   k_update<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, dt_d, dt, a0, a1, b);
 }
 
 void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
              const Eos& e, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
+  TIMED(T_C2P, s);
   k_stage_c2p<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p);
+}
+
+// plain streaming copy (counter calibration)
+__global__ __launch_bounds__(kThreads) void k_copy(const double* __restrict__ a, double* __restrict__ b,
+                                                   int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    b[t] = a[t];
 }
 
 }  // namespace
 
 namespace gk {
+Timing g_tm;
 Eos make_eos_host(const grmhd_params& p) { return make_eos(p); }
 int check_params_host(const grmhd_params* p) { return check_params(p); }
 }  // namespace gk
@@ -1094,6 +1124,7 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
   }
   const Sizes z = max_sizes(blk_h, nblk);
   hipStream_t s = (hipStream_t)stream;
+  TIMED(T_GHOST, s);
   if (mask & 11) k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(blk_d, mask & 11);
   if (mask & 4) {
     int64_t mf[3] = {0, 0, 0};
@@ -1115,7 +1146,10 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
   hipStream_t s = (hipStream_t)stream;
   const Sizes z = max_sizes(blk_h, nblk);
   k_zero1<<<1, 64, 0, s>>>(red);
-  k_dt<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(blk_d, make_eos(*p), red);
+  {
+    TIMED(T_DT, s);
+    k_dt<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(blk_d, make_eos(*p), red);
+  }
   k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
   return last_err();
 }
@@ -1160,6 +1194,7 @@ int c2p_batch(int64_t n, double* u[5], double* const bt[3], double* const gam[6]
   for (int v = 0; v < 5; ++v) { pw.p[v] = w[v]; pu.p[v] = u[v]; if (!w[v] || !u[v]) return GRMHD_EINVAL; }
   for (int v = 0; v < 3; ++v) { pb.p[v] = bt[v]; if (!bt[v]) return GRMHD_EINVAL; }
   for (int v = 0; v < 6; ++v) { pg.p[v] = gam[v]; if (!gam[v]) return GRMHD_EINVAL; }
+  TIMED(T_C2P_BATCH, (hipStream_t)stream);
   k_c2p_batch<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, (hipStream_t)stream>>>(
       n, pu, pb, pg, pw, flags, make_eos(*p), *p, mu_out, nev_out, stats);
   return last_err();
@@ -1176,6 +1211,42 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
 }
 
 const char* grmhd_version(void) { return "grmhd 0.1 gfx950 fp64"; }
+
+int grmhd_timing(int32_t on) {
+  if (on) {
+    if (!g_tm.created) {
+      for (int x = 0; x < kEventPool; ++x)
+        if (hipEventCreate(&g_tm.ev[x]) != hipSuccess) return GRMHD_EHIP;
+      g_tm.created = 1;
+    }
+    g_tm.used = 0;
+    for (int f = 0; f < kFamilies; ++f) { g_tm.ms[f] = 0.0; g_tm.cnt[f] = 0; }
+  }
+  g_tm.on = on ? 1 : 0;
+  return GRMHD_OK;
+}
+
+int grmhd_timing_read(int32_t family, double* ms, int64_t* launches) {
+  if (family < 0 || family >= kFamilies || !ms || !launches) return GRMHD_EINVAL;
+  for (int x = 0; x < g_tm.used; x += 2) {
+    if (hipEventSynchronize(g_tm.ev[x + 1]) != hipSuccess) return GRMHD_EHIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_tm.ev[x], g_tm.ev[x + 1]) != hipSuccess) return GRMHD_EHIP;
+    g_tm.ms[g_tm.fam[x / 2]] += t;
+    g_tm.cnt[g_tm.fam[x / 2]] += 1;
+  }
+  g_tm.used = 0;
+  *ms = g_tm.ms[family];
+  *launches = g_tm.cnt[family];
+  return GRMHD_OK;
+}
+
+int grmhd_copy(const double* src, double* dst, int64_t n, void* stream) {
+  if (!src || !dst || n < 0) return GRMHD_EINVAL;
+  if (n == 0) return GRMHD_OK;
+  k_copy<<<4096, kThreads, 0, (hipStream_t)stream>>>(src, dst, n);
+  return last_err();
+}
 
 int32_t grmhd_struct_size(int32_t which) {
   switch (which) {

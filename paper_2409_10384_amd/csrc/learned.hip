@@ -13,6 +13,7 @@
 #include "grmhd.h"
 #include "mlp.hpp"
 #include "physics.hpp"
+#include "timing.hpp"
 
 using namespace gk;
 
@@ -448,6 +449,7 @@ int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], double* cons
     return GRMHD_EINVAL;
   Feat ft;
   for (int c = 0; c < 5; ++c) { ft.mean[c] = mlp->feat_mean[c]; ft.scale[c] = mlp->feat_scale[c]; }
+  TIMED(T_C2P_LEARNED, (hipStream_t)stream);
   k_c2p_learned<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
       n, pu, pb, pg, pw, flags, make_eos_host(*p), *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,
       mlp->width_min, mu_out, nev_out, stats);
@@ -499,6 +501,7 @@ int c2p_mlp_train_step(float* theta, float* adam_m, float* adam_v, uint16_t* the
   if (apply && (!adam_m || !adam_v)) return GRMHD_EINVAL;
   const int nwg = (int)(nbatch / 64);
   hipStream_t s = (hipStream_t)stream;
+  TIMED(T_MLP_TRAIN, s);
   k_mlp_train<<<nwg, 64, 0, s>>>(nbatch, feats, target, theta_bf16, theta, partial, loss_part);
   const float c1 = apply ? 1.0f - powf(0.9f, (float)step) : 1.f;
   const float c2 = apply ? 1.0f - powf(0.999f, (float)step) : 1.f;

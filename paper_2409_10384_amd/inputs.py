@@ -444,3 +444,47 @@ def c2p_states(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps
     bt = (B * sqrtg[:, None]).T
     return {"w": np.ascontiguousarray(w), "bt": np.ascontiguousarray(bt),
             "gam": np.ascontiguousarray(gam), "eps": eps, "W": W, "bsq": bsq}
+
+
+def c2p_states_torch(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps=(-6.0, 1.0),
+                     W_range=(1.0, 10.0), log_bsq_rho=(-4.0, 1.0), metric_dev=0.1, device="cuda"):
+    """c2p_states with the same distributions, drawn with torch on a device
+    (for workloads too large to build on the host; different random stream)."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(SEED_BASE + seed_offset)
+    f64 = dict(dtype=torch.float64, device=device)
+
+    def U(lo, hi, *shape):
+        return lo + (hi - lo) * torch.rand(*shape, generator=g, **f64)
+
+    rho = 10.0 ** U(*log_rho, n)
+    eps = 10.0 ** U(*log_eps, n)
+    W = U(*W_range, n)
+    bsq = rho * 10.0 ** U(*log_bsq_rho, n)
+    qv = torch.randn(n, 4, generator=g, **f64)
+    qv = qv / qv.norm(dim=1, keepdim=True)
+    a, b, c, d = qv.unbind(1)
+    Q = torch.stack([
+        torch.stack([a * a + b * b - c * c - d * d, 2 * (b * c - a * d), 2 * (b * d + a * c)], -1),
+        torch.stack([2 * (b * c + a * d), a * a - b * b + c * c - d * d, 2 * (c * d - a * b)], -1),
+        torch.stack([2 * (b * d - a * c), 2 * (c * d + a * b), a * a - b * b - c * c + d * d], -1),
+    ], 1)
+    lam = U(1.0 - metric_dev, 1.0 + metric_dev, n, 3)
+    G = (Q * lam[:, None, :]) @ Q.transpose(1, 2)
+    gam = torch.stack([G[:, 0, 0], G[:, 0, 1], G[:, 0, 2], G[:, 1, 1], G[:, 1, 2], G[:, 2, 2]])
+
+    def unit_gamma(vec):
+        nrm = torch.sqrt(torch.einsum("ni,nij,nj->n", vec, G, vec))
+        return vec / nrm[:, None]
+
+    e = unit_gamma(torch.randn(n, 3, generator=g, **f64))
+    v = e * torch.sqrt(1.0 - 1.0 / (W * W))[:, None]
+    nb = unit_gamma(torch.randn(n, 3, generator=g, **f64))
+    nv = torch.einsum("ni,nij,nj->n", nb, G, v)
+    Bmag = torch.sqrt(bsq / (1.0 / (W * W) + nv * nv))
+    B = nb * Bmag[:, None]
+    sqrtg = torch.sqrt(torch.linalg.det(G))
+    P = (gamma - 1.0) * rho * eps
+    w = torch.stack([rho, W * v[:, 0], W * v[:, 1], W * v[:, 2], P]).contiguous()
+    bt = (B * sqrtg[:, None]).T.contiguous()
+    return {"w": w, "bt": bt, "gam": gam.contiguous(), "W": W, "eps": eps}

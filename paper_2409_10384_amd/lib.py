@@ -84,6 +84,9 @@ def load():
     L.c2p_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     vp = C.c_void_p
+    L.grmhd_timing.argtypes = [C.c_int32]
+    L.grmhd_timing_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.grmhd_copy.argtypes = [vp, vp, C.c_int64, vp]
     L.c2p_mlp_features.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.c2p_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
     L.c2p_mlp_to_bf16.argtypes = [vp, vp, vp]
@@ -145,6 +148,38 @@ def _ptr(t: torch.Tensor):
 def _ptr_array(ts):
     arr = (C.c_void_p * len(ts))(*[_ptr(t) for t in ts])
     return arr
+
+
+# ---------------------------------------------------------------------------
+# measurement helpers
+# ---------------------------------------------------------------------------
+FAMILIES = ["flux_x", "flux_y", "flux_z", "fofc_flags", "fofc_fix", "ct", "update", "stage_c2p",
+            "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train"]
+KERNEL_OF_FAMILY = {"flux_x": "k_flux<0>", "flux_y": "k_flux<1>", "flux_z": "k_flux<2>",
+                    "fofc_flags": "k_fofc_flags", "update": "k_update", "stage_c2p": "k_stage_c2p",
+                    "dt": "k_dt", "bcc": "k_bcc", "c2p_batch": "k_c2p_batch",
+                    "c2p_learned": "k_c2p_learned", "mlp_train": "k_mlp_train"}
+
+
+def timing(on: bool):
+    check(load().grmhd_timing(1 if on else 0), "grmhd_timing")
+
+
+def timing_read():
+    """{family: (total ms, launches)} since timing was enabled"""
+    L = load()
+    out = {}
+    for f, name in enumerate(FAMILIES):
+        ms = C.c_double(0.0)
+        cnt = C.c_int64(0)
+        check(L.grmhd_timing_read(f, C.byref(ms), C.byref(cnt)), "grmhd_timing_read")
+        if cnt.value:
+            out[name] = (ms.value, cnt.value)
+    return out
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    check(load().grmhd_copy(_ptr(src), _ptr(dst), src.numel(), stream_ptr(stream)), "grmhd_copy")
 
 
 # ---------------------------------------------------------------------------
