@@ -94,7 +94,18 @@ typedef struct grmhd_block {
   double *scratch;         /* grmhd_scratch_doubles(...) doubles of workspace */
   int32_t nbr[27];         /* neighbour block per offset (ox+1)+3(oy+1)+9(oz+1); -1: none */
   int32_t bc;              /* 0 ghosts frozen (untouched); 1 filled from nbr, outflow if -1 */
+  /* launch layout, filled by grmhd_blocks_prepare (do not set by hand):
+     first 64-item wave of this block in each of the 15 launch shapes, and
+     the number of blocks in the table */
+  int32_t wave0[16];
+  int32_t nblk;
+  int32_t reserved;
 } grmhd_block;
+
+/* Fill the launch-layout fields (wave0, nblk) of a host descriptor table in
+   place.  Call once after the table is built and before it is copied to the
+   device; every block-list entry point checks that the layout is current. */
+int grmhd_blocks_prepare(grmhd_block *blk_h, int32_t nblk);
 
 /* Doubles of per-block scratch needed by the stage: the 21 face-flux arrays
    (7 components D~, S~_xyz, tau~, F(B~^{t1}), F(B~^{t2}) per direction, t1 =
@@ -246,6 +257,10 @@ const char *grmhd_version(void);
    sources, 7 stage C2P, 8 ghost fill, 9 dt, 10 cell-centred field,
    11 c2p_batch plain, 12 c2p_batch learned, 13 MLP training. */
 int grmhd_timing(int32_t on);
+/* Workgroup size (64..512, a multiple of 64) of a kernel family of the stage
+   (families as for grmhd_timing, 0..10); default 256.  Set by the
+   autotuner; applies to subsequent launches in this process. */
+int grmhd_set_threads(int32_t family, int32_t threads);
 int grmhd_timing_read(int32_t family, double *ms, int64_t *launches);
 
 /* Plain streaming copy dst[0..n) = src[0..n) (device memory), used to

@@ -17,7 +17,8 @@ using namespace gk;
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // fixed-size kernels (pointwise, reductions)
+constexpr int kMaxThreads = 512;   // stage kernels: runtime workgroup size up to this
 
 // ---------------------------------------------------------------------------
 // block geometry helpers
@@ -76,6 +77,82 @@ __host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
   return off_edge(q) + 3 * n_edges(q);
 }
 
+// Launch shapes: every kernel runs over one "shape" of items per block,
+// flattened over the whole block list in 64-item waves (a wave never spans
+// two blocks; the host stores each block's first wave per shape in wave0).
+enum {
+  S_CELLS = 0,    // padded cells
+  S_INTERIOR,     // interior cells
+  S_EXT,          // cells [g-1, g+n] (cell-centre EMF)
+  S_XFACE,        // extended face ranges of direction x, y, z (fluxes)
+  S_YFACE,
+  S_ZFACE,
+  S_XEDGE,        // corner-EMF ranges of component x, y, z
+  S_YEDGE,
+  S_ZEDGE,
+  S_XIFACE,       // interior faces of direction x, y, z (CT update)
+  S_YIFACE,
+  S_ZIFACE,
+  S_XPFACE,       // padded faces of direction x, y, z (ghost fill)
+  S_YPFACE,
+  S_ZPFACE,
+  S_COUNT
+};
+
+__host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
+  const int n[3] = {q.nx, q.ny, q.nz};
+  int64_t c = 1;
+  switch (cls) {
+    case S_CELLS: return n_cells(q);
+    case S_INTERIOR: return (int64_t)n[0] * n[1] * n[2];
+    case S_EXT: return (int64_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
+    case S_XFACE: case S_YFACE: case S_ZFACE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XFACE ? n[a] + 1 : n[a] + 2;
+      return c;
+    case S_XEDGE: case S_YEDGE: case S_ZEDGE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XEDGE ? n[a] : n[a] + 1;
+      return c;
+    case S_XIFACE: case S_YIFACE: case S_ZIFACE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XIFACE ? n[a] + 1 : n[a];
+      return c;
+    default: return n_faces(q, cls - S_XPFACE);
+  }
+}
+
+// XCD-aware order.  Workgroups are dealt round-robin to the 8 XCDs by
+// linear id L; each XCD has its own L2.  Renumber so that XCD x owns a
+// contiguous range of tiles (its y/z stencil neighbours then share that L2):
+// L -> start(L % 8) + L / 8, a bijection of [0, N) for any N.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_linear() {
+  const int n = gridDim.x;
+  const int L = blockIdx.x;
+  const int x = L % kXcds, i = L / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+// block and item of this thread for launch shape cls; false when the thread
+// has no item (past the last wave, or in the padding of a block's last wave)
+__device__ __forceinline__ bool locate(const grmhd_block* __restrict__ blks, int cls, int& bi,
+                                       int64_t& t) {
+  const int64_t g = (int64_t)xcd_linear() * blockDim.x + threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane((int)(g >> 6));
+  const int nb = blks[0].nblk;
+  const int last = blks[nb - 1].wave0[cls];
+  // binary search: largest b with wave0[b] <= w
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blks[mid].wave0[cls] <= w) lo = mid; else hi = mid - 1;
+  }
+  bi = lo;
+  const Geo q = geo_of(blks[bi]);
+  if (bi == nb - 1 && w >= last + (int)((shape_items(q, cls) + 63) >> 6)) return false;
+  t = (int64_t)(w - blks[bi].wave0[cls]) * 64 + (threadIdx.x & 63);
+  return t < shape_items(q, cls);
+}
+
 // decompose a linear item index over a box [lo, lo+cnt)
 struct Box {
   int lo[3], cnt[3];
@@ -127,11 +204,12 @@ __device__ __forceinline__ void cell_bt(const Geo& q, double* const f[3], int i,
 // ---------------------------------------------------------------------------
 // a1: cell-centred un-densitized field B^i = B~_cc / sqrt(gamma), all cells
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_bcc(const grmhd_block* __restrict__ blks) {
-  const grmhd_block& b = blks[blockIdx.y];
+__global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restrict__ blks) {
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_CELLS, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_cells(q)) return;
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
   // face i+1 exists for every cell of the padded block
   M3 m;
@@ -204,13 +282,14 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e,
+__global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e,
                                                    grmhd_params p) {
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_XFACE + D, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const Box bx = face_box<D>(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   double F[7];
@@ -225,10 +304,12 @@ __global__ __launch_bounds__(kThreads) void k_flux(const grmhd_block* __restrict
 // ---------------------------------------------------------------------------
 // a4: FOFC flags (trial state, trial inversion, relaxed DMP of Eq. 12)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_clear_flags(const grmhd_block* __restrict__ blks) {
-  const grmhd_block& b = blks[blockIdx.y];
+__global__ __launch_bounds__(kMaxThreads) void k_clear_flags(const grmhd_block* __restrict__ blks) {
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_CELLS, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n_cells(q)) b.flags[t] = 0;
 }
 
@@ -247,15 +328,16 @@ __device__ __forceinline__ double flux_div(const grmhd_block& b, const Geo& q, i
          (fz[face<2>(q, i, j, k + 1)] - fz[face<2>(q, i, j, k)]) / b.dx[2];
 }
 
-__global__ __launch_bounds__(kThreads) void k_fofc_flags(const grmhd_block* __restrict__ blks,
+__global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* __restrict__ blks,
                                                          Eos e, grmhd_params p,
                                                          const double* dt_d, double dt_h,
                                                          double a0, double a1, double bb) {
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const Box bx = interior_box(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   const double dt = dt_of(dt_d, dt_h);
@@ -295,13 +377,14 @@ __global__ __launch_bounds__(kThreads) void k_fofc_flags(const grmhd_block* __re
 }
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e,
+__global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e,
                                                        grmhd_params p) {
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_XFACE + D, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const Box bx = face_box<D>(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
@@ -321,14 +404,15 @@ __global__ __launch_bounds__(kThreads) void k_fofc_fix(const grmhd_block* __rest
 // a5: upwind constrained transport
 // ---------------------------------------------------------------------------
 // cell-centre EMF E = -alpha (vhat x B~) on cells [g-1, g+n]
-__global__ __launch_bounds__(kThreads) void k_emf_cc(const grmhd_block* __restrict__ blks) {
-  const grmhd_block& b = blks[blockIdx.y];
+__global__ __launch_bounds__(kMaxThreads) void k_emf_cc(const grmhd_block* __restrict__ blks) {
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_EXT, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   Box bx;
   bx.lo[0] = bx.lo[1] = bx.lo[2] = q.g - 1;
   bx.cnt[0] = q.nx + 2; bx.cnt[1] = q.ny + 2; bx.cnt[2] = q.nz + 2;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   const int64_t c = cell(q, i, j, k);
@@ -369,9 +453,12 @@ __device__ __forceinline__ double face_emf(const double* sc, const Geo& q, int64
 
 // corner EMF of component C on the plane (A, Bx) = ((C+1)%3, (C+2)%3)
 template <int C>
-__global__ __launch_bounds__(kThreads) void k_emf_edge(const grmhd_block* __restrict__ blks) {
+__global__ __launch_bounds__(kMaxThreads) void k_emf_edge(const grmhd_block* __restrict__ blks) {
   constexpr int A = (C + 1) % 3, BX = (C + 2) % 3;
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_XEDGE + C, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const int n[3] = {q.nx, q.ny, q.nz};
   Box bx;
@@ -380,8 +467,6 @@ __global__ __launch_bounds__(kThreads) void k_emf_edge(const grmhd_block* __rest
     bx.lo[a] = q.g;
     bx.cnt[a] = a == C ? n[a] : n[a] + 1;
   }
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int x[3];
   bx.at(t, x[0], x[1], x[2]);
   const double* sc = b.scratch;
@@ -421,11 +506,14 @@ __global__ __launch_bounds__(kThreads) void k_emf_edge(const grmhd_block* __rest
 
 // bo = a0 bn + a1 bs - b dt (curl E)^D on the interior faces of direction D
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_ct_face(const grmhd_block* __restrict__ blks,
+__global__ __launch_bounds__(kMaxThreads) void k_ct_face(const grmhd_block* __restrict__ blks,
                                                       const double* dt_d, double dt_h, double a0,
                                                       double a1, double bb) {
   constexpr int D1 = (D + 1) % 3, D2 = (D + 2) % 3;
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_XIFACE + D, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const int n[3] = {q.nx, q.ny, q.nz};
   Box bx;
@@ -434,8 +522,6 @@ __global__ __launch_bounds__(kThreads) void k_ct_face(const grmhd_block* __restr
     bx.lo[a] = q.g;
     bx.cnt[a] = a == D ? n[a] + 1 : n[a];
   }
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int x[3];
   bx.at(t, x[0], x[1], x[2]);
   const double dt = dt_of(dt_d, dt_h);
@@ -458,14 +544,15 @@ __device__ __forceinline__ double dcen(const double* a, int64_t c, int64_t st, d
   return ((a[c - 2 * st] - a[c + 2 * st]) - 8.0 * (a[c - st] - a[c + st])) * idx12;
 }
 
-__global__ __launch_bounds__(kThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e,
+__global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e,
                                                      const double* dt_d, double dt_h, double a0,
                                                      double a1, double bb) {
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const Box bx = interior_box(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   const double dt = dt_of(dt_d, dt_h);
@@ -547,13 +634,14 @@ __global__ __launch_bounds__(kThreads) void k_update(const grmhd_block* __restri
 // ---------------------------------------------------------------------------
 // a8: inversion of the updated state with the updated field
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e,
+__global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e,
                                                         grmhd_params p) {
-  const grmhd_block& b = blks[blockIdx.y];
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   const Box bx = interior_box(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= bx.size()) return;
   int i, j, k;
   bx.at(t, i, j, k);
   const int64_t c = cell(q, i, j, k);
@@ -630,14 +718,14 @@ __device__ __forceinline__ bool ghost_src(const grmhd_block* blks, int ib, int f
   return true;
 }
 
-__global__ __launch_bounds__(kThreads) void k_ghost_cells(const grmhd_block* __restrict__ blks,
+__global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* __restrict__ blks,
                                                           int mask) {
-  const int ib = blockIdx.y;
+  int ib;
+  int64_t t;
+  if (!locate(blks, S_CELLS, ib, t)) return;
   const grmhd_block& b = blks[ib];
   if (b.bc == 0) return;
   const Geo q = geo_of(b);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_cells(q)) return;
   int x[3] = {(int)(t % q.sx), (int)((t / q.sx) % q.sy), (int)(t / ((int64_t)q.sx * q.sy))};
   int sb;
   if (!ghost_src(blks, ib, -1, x, sb)) return;
@@ -653,15 +741,15 @@ __global__ __launch_bounds__(kThreads) void k_ghost_cells(const grmhd_block* __r
   if (mask & 8) b.flags[t] = s.flags[src];
 }
 
-__global__ __launch_bounds__(kThreads) void k_ghost_faces(const grmhd_block* __restrict__ blks,
+__global__ __launch_bounds__(kMaxThreads) void k_ghost_faces(const grmhd_block* __restrict__ blks,
                                                           int d) {
-  const int ib = blockIdx.y;
+  int ib;
+  int64_t t;
+  if (!locate(blks, S_XPFACE + d, ib, t)) return;
   const grmhd_block& b = blks[ib];
   if (b.bc == 0) return;
   const Geo q = geo_of(b);
   const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_faces(q, d)) return;
   int x[3] = {(int)(t % ex), (int)((t / ex) % ey), (int)(t / ((int64_t)ex * ey))};
   int sb;
   if (!ghost_src(blks, ib, d, x, sb)) return;
@@ -683,14 +771,16 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e,
+__global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e,
                                                  double* red) {
-  const grmhd_block& b = blks[blockIdx.y];
-  const Geo q = geo_of(b);
-  const Box bx = interior_box(q);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int bi;
+  int64_t t;
+  const bool live = locate(blks, S_INTERIOR, bi, t);   // no early return: barrier below
   double s = 0.0;
-  if (t < bx.size()) {
+  if (live) {
+    const grmhd_block& b = blks[bi];
+    const Geo q = geo_of(b);
+    const Box bx = interior_box(q);
     int i, j, k;
     bx.at(t, i, j, k);
     const int64_t c = cell(q, i, j, k);
@@ -713,12 +803,12 @@ __global__ __launch_bounds__(kThreads) void k_dt(const grmhd_block* __restrict__
     s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[2]);
   }
   s = wave_max(s);
-  __shared__ double part[kThreads / 64];
+  __shared__ double part[kMaxThreads / 64];
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = part[0];
-    for (int x = 1; x < kThreads / 64; ++x) r = fmax(r, part[x]);
+    for (int x = 1; x < (int)(blockDim.x >> 6); ++x) r = fmax(r, part[x]);
     // non-negative doubles order like their bit patterns
     atomicMax((unsigned long long*)red, (unsigned long long)__double_as_longlong(r));
   }
@@ -762,11 +852,12 @@ __global__ void k_mass_final(const double* partial, int nblk, double* out) {
 }
 
 // Eq. 7 over every padded cell of a block: us <- prim2con(w, B~_cc(bs))
-__global__ __launch_bounds__(kThreads) void k_p2c_block(const grmhd_block* __restrict__ blks, Eos e) {
-  const grmhd_block& b = blks[blockIdx.y];
+__global__ __launch_bounds__(kMaxThreads) void k_p2c_block(const grmhd_block* __restrict__ blks, Eos e) {
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_CELLS, bi, t)) return;
+  const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_cells(q)) return;
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
   M3 m;
   cell_metric(b, t, m);
@@ -866,8 +957,11 @@ int check_params(const grmhd_params* p) {
   return GRMHD_OK;
 }
 
+int64_t prepare_layout(grmhd_block* h, int nblk, bool write);
+
 int check_blocks(const grmhd_block* h, const grmhd_block* d, int nblk) {
   if (!h || !d || nblk < 1) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(h), nblk, false) != 0) return GRMHD_EINVAL;
   for (int i = 0; i < nblk; ++i) {
     const grmhd_block& b = h[i];
     if (b.ng < 3 || b.nx < 1 || b.ny < 1 || b.nz < 1) return GRMHD_EINVAL;
@@ -924,6 +1018,34 @@ Sizes max_sizes(const grmhd_block* h, int nblk) {
   return s;
 }
 
+// 1-D grid over all 64-item waves of launch shape cls in the block list
+dim3 grid_cls(const grmhd_block* h, int nblk, int cls, int threads) {
+  const int64_t waves = (int64_t)h[nblk - 1].wave0[cls] + (shape_items(geo_of(h[nblk - 1]), cls) + 63) / 64;
+  return dim3((unsigned)((waves * 64 + threads - 1) / threads), 1, 1);
+}
+
+// workgroup size per kernel family (64..512, multiple of 64), set by the
+// autotuner through grmhd_set_threads
+int g_threads[kFamilies] = {256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256};
+inline int tpb(int fam) { return g_threads[fam]; }
+
+// launch layout of a block table: first wave of each block per shape
+int64_t prepare_layout(grmhd_block* h, int nblk, bool write) {
+  int64_t wave[S_COUNT] = {0};
+  for (int i = 0; i < nblk; ++i) {
+    const Geo q = geo_of(h[i]);
+    for (int c = 0; c < S_COUNT; ++c) {
+      if (write) h[i].wave0[c] = (int32_t)wave[c];
+      else if (h[i].wave0[c] != (int32_t)wave[c]) return -1;
+      wave[c] += (shape_items(q, c) + 63) / 64;
+      if (wave[c] > 0x3fffffff) return -1;
+    }
+    if (write) { h[i].wave0[S_COUNT] = 0; h[i].nblk = nblk; h[i].reserved = 0; }
+    else if (h[i].nblk != nblk) return -1;
+  }
+  return 0;
+}
+
 dim3 grid_for(int64_t items, int nblk) {
   return dim3((unsigned)((items + kThreads - 1) / kThreads), (unsigned)nblk, 1);
 }
@@ -936,65 +1058,65 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
   const Sizes z = max_sizes(h, nblk);
   {
     TIMED(T_BCC, s);
-    k_bcc<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
+    k_bcc<<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d);
   }
   {
     TIMED(T_FLUX_X, s);
-    k_flux<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
+    k_flux<0><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FLUX_X)), tpb(T_FLUX_X), 0, s>>>(d, e, p);
   }
   {
     TIMED(T_FLUX_Y, s);
-    k_flux<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
+    k_flux<1><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FLUX_Y)), tpb(T_FLUX_Y), 0, s>>>(d, e, p);
   }
   TIMED(T_FLUX_Z, s);
-  k_flux<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
+  k_flux<2><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FLUX_Z)), tpb(T_FLUX_Z), 0, s>>>(d, e, p);
 }
 
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
               const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
               hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
-  k_clear_flags<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d);
+  k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
   if (!p.fofc) return;
   {
     TIMED(T_FOFC_FLAGS, s);
-    k_fofc_flags<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
+    k_fofc_flags<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
   }
   {
     TIMED(T_GHOST, s);
-    k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(d, 8);
+    k_ghost_cells<<<grid_cls(h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8);
   }
   TIMED(T_FOFC_FIX, s);
-  k_fofc_fix<0><<<grid_for(z.faces[0], nblk), kThreads, 0, s>>>(d, e, p);
-  k_fofc_fix<1><<<grid_for(z.faces[1], nblk), kThreads, 0, s>>>(d, e, p);
-  k_fofc_fix<2><<<grid_for(z.faces[2], nblk), kThreads, 0, s>>>(d, e, p);
+  k_fofc_fix<0><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+  k_fofc_fix<1><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+  k_fofc_fix<2><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
 }
 
 void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
             double a0, double a1, double b, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_CT, s);
-  k_emf_cc<<<grid_for(z.ext_cells, nblk), kThreads, 0, s>>>(d);
-  k_emf_edge<0><<<grid_for(z.edges[0], nblk), kThreads, 0, s>>>(d);
-  k_emf_edge<1><<<grid_for(z.edges[1], nblk), kThreads, 0, s>>>(d);
-  k_emf_edge<2><<<grid_for(z.edges[2], nblk), kThreads, 0, s>>>(d);
-  k_ct_face<0><<<grid_for(z.ifaces[0], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
-  k_ct_face<1><<<grid_for(z.ifaces[1], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
-  k_ct_face<2><<<grid_for(z.ifaces[2], nblk), kThreads, 0, s>>>(d, dt_d, dt, a0, a1, b);
+  k_emf_cc<<<grid_cls(h, nblk, S_EXT, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
+  k_emf_edge<0><<<grid_cls(h, nblk, S_XEDGE + 0, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
+  k_emf_edge<1><<<grid_cls(h, nblk, S_XEDGE + 1, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
+  k_emf_edge<2><<<grid_cls(h, nblk, S_XEDGE + 2, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
+  k_ct_face<0><<<grid_cls(h, nblk, S_XIFACE + 0, tpb(T_CT)), tpb(T_CT), 0, s>>>(d, dt_d, dt, a0, a1, b);
+  k_ct_face<1><<<grid_cls(h, nblk, S_XIFACE + 1, tpb(T_CT)), tpb(T_CT), 0, s>>>(d, dt_d, dt, a0, a1, b);
+  k_ct_face<2><<<grid_cls(h, nblk, S_XIFACE + 2, tpb(T_CT)), tpb(T_CT), 0, s>>>(d, dt_d, dt, a0, a1, b);
 }
 
 void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos& e,
                 const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_UPDATE, s);
-  k_update<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, dt_d, dt, a0, a1, b);
+  k_update<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(d, e, dt_d, dt, a0, a1, b);
 }
 
 void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
              const Eos& e, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_C2P, s);
-  k_stage_c2p<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(d, e, p);
+  k_stage_c2p<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(d, e, p);
 }
 
 // plain streaming copy (counter calibration)
@@ -1022,6 +1144,13 @@ extern "C" int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], d
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+int grmhd_blocks_prepare(grmhd_block* blk_h, int32_t nblk) {
+  if (!blk_h || nblk < 1) return GRMHD_EINVAL;
+  for (int i = 0; i < nblk; ++i)
+    if (blk_h[i].nx < 1 || blk_h[i].ny < 1 || blk_h[i].nz < 1 || blk_h[i].ng < 0) return GRMHD_EINVAL;
+  return prepare_layout(blk_h, nblk, true) == 0 ? GRMHD_OK : GRMHD_EINVAL;
+}
 
 int64_t grmhd_scratch_doubles(int32_t nx, int32_t ny, int32_t nz, int32_t ng) {
   if (nx < 1 || ny < 1 || nz < 1 || ng < 0) return -1;
@@ -1106,6 +1235,7 @@ int grmhd_stage(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk
 int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
                      int32_t mask, void* stream) {
   if (!blk_h || !blk_d || nblk < 1 || (mask & ~15)) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
   for (int i = 0; i < nblk; ++i) {
     const grmhd_block& b = blk_h[i];
     if (b.ng < 1 || b.nx < 1 || b.ny < 1 || b.nz < 1) return GRMHD_EINVAL;
@@ -1125,7 +1255,7 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
   const Sizes z = max_sizes(blk_h, nblk);
   hipStream_t s = (hipStream_t)stream;
   TIMED(T_GHOST, s);
-  if (mask & 11) k_ghost_cells<<<grid_for(z.cells, nblk), kThreads, 0, s>>>(blk_d, mask & 11);
+  if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11);
   if (mask & 4) {
     int64_t mf[3] = {0, 0, 0};
     for (int i = 0; i < nblk; ++i)
@@ -1133,7 +1263,7 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
         const int64_t f = n_faces(geo_of(blk_h[i]), d);
         mf[d] = mf[d] > f ? mf[d] : f;
       }
-    for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_for(mf[d], nblk), kThreads, 0, s>>>(blk_d, d);
+    for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_cls(blk_h, nblk, S_XPFACE + d, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, d);
   }
   return last_err();
 }
@@ -1143,12 +1273,13 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
   int r = check_params(p);
   if (r) return r;
   if (!blk_h || !blk_d || nblk < 1 || !red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const Sizes z = max_sizes(blk_h, nblk);
   k_zero1<<<1, 64, 0, s>>>(red);
   {
     TIMED(T_DT, s);
-    k_dt<<<grid_for(z.interior, nblk), kThreads, 0, s>>>(blk_d, make_eos(*p), red);
+    k_dt<<<grid_cls(blk_h, nblk, S_INTERIOR, tpb(T_DT)), tpb(T_DT), 0, s>>>(blk_d, make_eos(*p), red);
   }
   k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
   return last_err();
@@ -1205,8 +1336,9 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
   int r = check_params(p);
   if (r) return r;
   if (!blk_h || !blk_d || nblk < 1) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
   const Sizes z = max_sizes(blk_h, nblk);
-  k_p2c_block<<<grid_for(z.cells, nblk), kThreads, 0, (hipStream_t)stream>>>(blk_d, make_eos(*p));
+  k_p2c_block<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, (hipStream_t)stream>>>(blk_d, make_eos(*p));
   return last_err();
 }
 
@@ -1246,6 +1378,13 @@ int grmhd_copy(const double* src, double* dst, int64_t n, void* stream) {
   if (n == 0) return GRMHD_OK;
   k_copy<<<4096, kThreads, 0, (hipStream_t)stream>>>(src, dst, n);
   return last_err();
+}
+
+int grmhd_set_threads(int32_t family, int32_t threads) {
+  if (family < 0 || family >= kFamilies) return GRMHD_EINVAL;
+  if (threads < 64 || threads > kMaxThreads || (threads % 64)) return GRMHD_EINVAL;
+  g_threads[family] = threads;
+  return GRMHD_OK;
 }
 
 int32_t grmhd_struct_size(int32_t which) {

@@ -48,6 +48,7 @@ class GrmhdBlock(C.Structure):
         ("w", VP * 5), ("un", VP * 5), ("us", VP * 5), ("bn", VP * 3), ("bs", VP * 3),
         ("adm", VP * 16), ("uo", VP * 5), ("bo", VP * 3), ("wo", VP * 5),
         ("flags", VP), ("scratch", VP), ("nbr", C.c_int32 * 27), ("bc", C.c_int32),
+        ("wave0", C.c_int32 * 16), ("nblk", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -69,6 +70,7 @@ def load():
     L.grmhd_flux_offset.restype = C.c_int64
     L.grmhd_flux_offset.argtypes = [C.c_int32] * 6
     L.grmhd_version.restype = C.c_char_p
+    L.grmhd_blocks_prepare.argtypes = [C.c_void_p, C.c_int32]
     blk = [C.c_void_p, C.c_void_p, C.c_int32]
     stage = blk + [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
     for name in ("grmhd_stage", "fofc_correct", "ct_update", "grmhd_update"):
@@ -85,6 +87,7 @@ def load():
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     vp = C.c_void_p
     L.grmhd_timing.argtypes = [C.c_int32]
+    L.grmhd_set_threads.argtypes = [C.c_int32, C.c_int32]
     L.grmhd_timing_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.grmhd_copy.argtypes = [vp, vp, C.c_int64, vp]
     L.c2p_mlp_features.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -311,6 +314,7 @@ class DeviceMesh:
             else:
                 arr[ib] = self._desc(ib, self.w1[ib], self.u1[ib], self.u1[ib], self.b1[ib],
                                      self.b1[ib], self.u1[ib], self.b1[ib], self.w1[ib])
+        check(load().grmhd_blocks_prepare(C.cast(arr, C.c_void_p), n), "grmhd_blocks_prepare")
         raw = bytes(memoryview(arr).cast("B"))
         dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
         return arr, dev
