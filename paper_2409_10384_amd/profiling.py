@@ -25,10 +25,16 @@ FAMILY_OF_KERNEL = {"k_flux<0>": "flux_x", "k_flux<1>": "flux_y", "k_flux<2>": "
 
 
 def short(name):
+    """kernel name without namespace, return type and argument list"""
     for k in FAMILY_OF_KERNEL:
         if ("::" + k + "(") in name or name.startswith(k + "("):
             return k
-    return name.split("(")[0][:80]
+    # 'void (anonymous namespace)::k_emf_edge<1>(...)' -> 'k_emf_edge<1>'
+    head = name.replace("(anonymous namespace)", "anon")
+    head = head.split("(")[0]
+    if "::" in head:
+        head = head[head.rindex("::") + 2:]
+    return head.split(" ")[-1][:80]
 
 
 def source_hash():
