@@ -182,6 +182,63 @@ def star_section(args, torch, inputs, lib):
                 st=st, mass=mass)
 
 
+def refined_section(args, torch, inputs, lib):
+    """~1500 independent blocks of 16^3/24^3/32^3 over 6 levels (frozen
+    ghosts): RK2 steps launched block by block, batched (one launch per kernel
+    and stage over the whole list), batched after the autotuner, and the
+    batched step replayed from a captured HIP graph"""
+    from paper_2409_10384_amd import autotune
+    t0 = time.perf_counter()
+    blocks, st = inputs.refined_star_blocks(nblocks=args.refined_blocks, device="cuda")
+    mesh = lib.DeviceMesh(blocks, lib.MethodParams(**STAR_PARAMS), device="cuda")
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    torch.cuda.synchronize()
+    log(f"refined mesh: {len(blocks)} blocks, {ncell} cells ({time.perf_counter() - t0:.1f} s)")
+    dt = float(mesh.compute_dt(0.25).item())
+    K = args.refined_steps
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    res = {"blocks": len(blocks), "cells": ncell, "sizes": sorted({b.nx for b in blocks}),
+           "levels": len({b.level for b in blocks}), "steps": K}
+    ms = timed(lambda: mesh.rk2_step_per_block(dt=dt))
+    res["per_block_launches"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
+    log(f"refined per-block launches: {ms:.2f} ms/step")
+    ms = timed(lambda: mesh.rk2_step(dt=dt))
+    res["batched"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
+    log(f"refined batched: {ms:.2f} ms/step")
+    tune = autotune.autotune(mesh, dt, log=log)
+    ms = timed(lambda: mesh.rk2_step(dt=dt))
+    res["batched_autotuned"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3),
+                                "workgroup_sizes": {k: v["best"] for k, v in tune.items()}}
+    log(f"refined batched + autotuned: {ms:.2f} ms/step")
+    # whole step (device dt, both stages, ghost fills) captured once, replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        mesh.rk2_step(cfl=0.25)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mesh.rk2_step(cfl=0.25)
+    ms = timed(g.replay)
+    res["graph_autotuned"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
+    log(f"refined graph replay: {ms:.2f} ms/step")
+    autotune.reset()
+    del g
+    return res
+
+
 def c2p_section(args, torch, inputs, lib):
     """C2P solves/s on 2^k random states, plain vs learned bracket"""
     n = 1 << args.c2p_log2
@@ -209,7 +266,8 @@ def c2p_section(args, torch, inputs, lib):
     train_s = time.perf_counter() - t0
     log(f"trained {steps} steps in {train_s:.1f} s, final loss {float(loss.item()):.3g}")
     res = {}
-    for kind in ("plain", "learned"):
+    ws = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    for kind in ("plain", "learned", "learned_fused"):
         times = []
         for rep in range(args.c2p_reps + 1):
             u = u0.clone()
@@ -221,7 +279,7 @@ def c2p_section(args, torch, inputs, lib):
                 out = lib.c2p_batch(u, s["bt"], s["gam"], p, want_mu=True, want_nev=True, stats=True)
             else:
                 out = lib.c2p_batch_learned(u, s["bt"], s["gam"], p, net, want_mu=True, want_nev=True,
-                                            stats=True)
+                                            stats=True, split=(kind == "learned"), workspace=ws)
             e1.record()
             torch.cuda.synchronize()
             if rep > 0:
@@ -251,8 +309,13 @@ def main():
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--c2p-log2", type=int, default=24)
     ap.add_argument("--c2p-reps", type=int, default=3)
-    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--no-c2p", action="store_true")
+    ap.add_argument("--c2p-only", action="store_true", help="only the C2P solves/s section")
+    ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--refined-only", action="store_true", help="only the refined-mesh section")
+    ap.add_argument("--refined-blocks", type=int, default=1500)
+    ap.add_argument("--refined-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB plain copy first (for counter scaling)")
@@ -276,6 +339,12 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del a, b
+    if args.c2p_only:
+        print(json.dumps({"c2p": c2p_section(args, torch, inputs, lib)}), flush=True)
+        return
+    if args.refined_only:
+        print(json.dumps({"refined": refined_section(args, torch, inputs, lib)}), flush=True)
+        return
     star = star_section(args, torch, inputs, lib)
     out = {
         "metric": "zone-updates/s per GPU (GRMHD SSP-RK2 step, plain C2P)",
@@ -298,6 +367,8 @@ def main():
         "path_roofline": star["path"],
         "kernel_breakdown": star["breakdown"],
     }
+    if not args.no_refined:
+        out["refined"] = refined_section(args, torch, inputs, lib)
     if not args.no_c2p:
         out["c2p"] = c2p_section(args, torch, inputs, lib)
     if not args.no_cpu_baseline:

@@ -205,6 +205,10 @@ typedef struct c2p_mlp {
   const float *w_f32;                 /* fp32 parameter vector */
   float feat_mean[5], feat_scale[5];  /* standardisation: (x - mean) * scale */
   float width_k, width_min;           /* bracket half-width in logit space */
+  double *bracket_ws;                 /* optional device workspace of 2 n doubles: when set,
+                                         the network runs as its own MFMA kernel writing
+                                         the brackets, then the FP64 root kernel reads them;
+                                         when NULL, one fused kernel does both */
 } c2p_mlp;
 
 /* C2P statistics accumulated by c2p_batch when stats != NULL (device). */

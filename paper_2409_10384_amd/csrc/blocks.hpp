@@ -1,0 +1,197 @@
+// blocks.hpp -- MeshBlock geometry, scratch layout and the flattened launch
+// layout shared by the stage kernels and the learned-bracket kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grmhd.h"
+#include "physics.hpp"
+
+namespace gk {
+
+// ---------------------------------------------------------------------------
+// block geometry helpers
+// ---------------------------------------------------------------------------
+struct Geo {
+  int nx, ny, nz, g, sx, sy, sz;
+};
+
+__host__ __device__ __forceinline__ Geo geo_of(const grmhd_block& b) {
+  Geo q;
+  q.nx = b.nx; q.ny = b.ny; q.nz = b.nz; q.g = b.ng;
+  q.sx = b.nx + 2 * b.ng; q.sy = b.ny + 2 * b.ng; q.sz = b.nz + 2 * b.ng;
+  return q;
+}
+__host__ __device__ __forceinline__ int64_t n_cells(const Geo& q) {
+  return (int64_t)q.sx * q.sy * q.sz;
+}
+__host__ __device__ __forceinline__ int64_t n_faces(const Geo& q, int d) {
+  return (int64_t)(q.sx + (d == 0)) * (q.sy + (d == 1)) * (q.sz + (d == 2));
+}
+__host__ __device__ __forceinline__ int64_t n_edges(const Geo& q) {
+  return (int64_t)(q.sx + 1) * (q.sy + 1) * (q.sz + 1);
+}
+__device__ __forceinline__ int64_t cell(const Geo& q, int i, int j, int k) {
+  return ((int64_t)k * q.sy + j) * q.sx + i;
+}
+template <int D>
+__device__ __forceinline__ int64_t face(const Geo& q, int i, int j, int k) {
+  const int ex = q.sx + (D == 0), ey = q.sy + (D == 1);
+  return ((int64_t)k * ey + j) * ex + i;
+}
+__device__ __forceinline__ int64_t face_rt(const Geo& q, int d, int i, int j, int k) {
+  const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
+  return ((int64_t)k * ey + j) * ex + i;
+}
+__device__ __forceinline__ int64_t edge(const Geo& q, int i, int j, int k) {
+  return ((int64_t)k * (q.sy + 1) + j) * (q.sx + 1) + i;
+}
+
+// scratch layout (doubles): flux[d][c] | Bcc[3] | Ecc[3] | Eedge[3] | bracket[2]
+__host__ __device__ __forceinline__ int64_t off_flux(const Geo& q, int d, int c) {
+  int64_t o = 0;
+  for (int dd = 0; dd < d; ++dd) o += 7 * n_faces(q, dd);
+  return o + c * n_faces(q, d);
+}
+__host__ __device__ __forceinline__ int64_t off_bcc(const Geo& q) {
+  return off_flux(q, 3, 0);
+}
+__host__ __device__ __forceinline__ int64_t off_ecc(const Geo& q) {
+  return off_bcc(q) + 3 * n_cells(q);
+}
+__host__ __device__ __forceinline__ int64_t off_edge(const Geo& q) {
+  return off_ecc(q) + 3 * n_cells(q);
+}
+// learned bracket [lo, hi] of the stage inversion, per padded cell
+__host__ __device__ __forceinline__ int64_t off_br(const Geo& q) {
+  return off_edge(q) + 3 * n_edges(q);
+}
+__host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
+  return off_br(q) + 2 * n_cells(q);
+}
+
+// Launch shapes: every kernel runs over one "shape" of items per block,
+// flattened over the whole block list in 64-item waves (a wave never spans
+// two blocks; the host stores each block's first wave per shape in wave0).
+enum {
+  S_CELLS = 0,    // padded cells
+  S_INTERIOR,     // interior cells
+  S_EXT,          // cells [g-1, g+n] (cell-centre EMF)
+  S_XFACE,        // extended face ranges of direction x, y, z (fluxes)
+  S_YFACE,
+  S_ZFACE,
+  S_XEDGE,        // corner-EMF ranges of component x, y, z
+  S_YEDGE,
+  S_ZEDGE,
+  S_XIFACE,       // interior faces of direction x, y, z (CT update)
+  S_YIFACE,
+  S_ZIFACE,
+  S_XPFACE,       // padded faces of direction x, y, z (ghost fill)
+  S_YPFACE,
+  S_ZPFACE,
+  S_COUNT
+};
+
+__host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
+  const int n[3] = {q.nx, q.ny, q.nz};
+  int64_t c = 1;
+  switch (cls) {
+    case S_CELLS: return n_cells(q);
+    case S_INTERIOR: return (int64_t)n[0] * n[1] * n[2];
+    case S_EXT: return (int64_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
+    case S_XFACE: case S_YFACE: case S_ZFACE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XFACE ? n[a] + 1 : n[a] + 2;
+      return c;
+    case S_XEDGE: case S_YEDGE: case S_ZEDGE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XEDGE ? n[a] : n[a] + 1;
+      return c;
+    case S_XIFACE: case S_YIFACE: case S_ZIFACE:
+      for (int a = 0; a < 3; ++a) c *= a == cls - S_XIFACE ? n[a] + 1 : n[a];
+      return c;
+    default: return n_faces(q, cls - S_XPFACE);
+  }
+}
+
+// XCD-aware order.  Workgroups are dealt round-robin to the 8 XCDs by
+// linear id L; each XCD has its own L2.  Renumber so that XCD x owns a
+// contiguous range of tiles (its y/z stencil neighbours then share that L2):
+// L -> start(L % 8) + L / 8, a bijection of [0, N) for any N.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_linear() {
+  const int n = gridDim.x;
+  const int L = blockIdx.x;
+  const int x = L % kXcds, i = L / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+// block and item of this thread for launch shape cls; false when the thread
+// has no item (past the last wave, or in the padding of a block's last wave)
+__device__ __forceinline__ bool locate(const grmhd_block* __restrict__ blks, int cls, int& bi,
+                                       int64_t& t) {
+  const int64_t g = (int64_t)xcd_linear() * blockDim.x + threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane((int)(g >> 6));
+  const int nb = blks[0].nblk;
+  const int last = blks[nb - 1].wave0[cls];
+  // binary search: largest b with wave0[b] <= w
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blks[mid].wave0[cls] <= w) lo = mid; else hi = mid - 1;
+  }
+  bi = lo;
+  const Geo q = geo_of(blks[bi]);
+  if (bi == nb - 1 && w >= last + (int)((shape_items(q, cls) + 63) >> 6)) return false;
+  t = (int64_t)(w - blks[bi].wave0[cls]) * 64 + (threadIdx.x & 63);
+  return t < shape_items(q, cls);
+}
+
+// decompose a linear item index over a box [lo, lo+cnt)
+struct Box {
+  int lo[3], cnt[3];
+  __device__ __forceinline__ int64_t size() const { return (int64_t)cnt[0] * cnt[1] * cnt[2]; }
+  __device__ __forceinline__ void at(int64_t t, int& i, int& j, int& k) const {
+    i = lo[0] + (int)(t % cnt[0]);
+    const int64_t r = t / cnt[0];
+    j = lo[1] + (int)(r % cnt[1]);
+    k = lo[2] + (int)(r / cnt[1]);
+  }
+};
+
+// extended face range of direction D: faces [g, g+n_D] along D, cells
+// [g-1, g+n_t] across (one ghost column each side for the corner EMFs)
+template <int D>
+__device__ __forceinline__ Box face_box(const Geo& q) {
+  Box b;
+  const int n[3] = {q.nx, q.ny, q.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == D) { b.lo[a] = q.g; b.cnt[a] = n[a] + 1; }
+    else { b.lo[a] = q.g - 1; b.cnt[a] = n[a] + 2; }
+  }
+  return b;
+}
+__device__ __forceinline__ Box interior_box(const Geo& q) {
+  Box b;
+  b.lo[0] = b.lo[1] = b.lo[2] = q.g;
+  b.cnt[0] = q.nx; b.cnt[1] = q.ny; b.cnt[2] = q.nz;
+  return b;
+}
+
+__device__ __forceinline__ double dt_of(const double* dt_d, double dt) {
+  return dt_d ? *dt_d : dt;
+}
+
+__device__ __forceinline__ void cell_metric(const grmhd_block& b, int64_t c, M3& m) {
+  metric_build(m, b.adm[4][c], b.adm[5][c], b.adm[6][c], b.adm[7][c], b.adm[8][c], b.adm[9][c]);
+}
+
+// densitized cell-centred field from the faces of slot f
+__device__ __forceinline__ void cell_bt(const Geo& q, double* const f[3], int i, int j, int k,
+                                        double Bt[3]) {
+  Bt[0] = 0.5 * (f[0][face<0>(q, i, j, k)] + f[0][face<0>(q, i + 1, j, k)]);
+  Bt[1] = 0.5 * (f[1][face<1>(q, i, j, k)] + f[1][face<1>(q, i, j + 1, k)]);
+  Bt[2] = 0.5 * (f[2][face<2>(q, i, j, k)] + f[2][face<2>(q, i, j, k + 1)]);
+}
+
+}  // namespace gk

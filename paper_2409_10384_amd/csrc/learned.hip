@@ -20,6 +20,9 @@ using namespace gk;
 namespace gk {
 Eos make_eos_host(const grmhd_params& p);
 int check_params_host(const grmhd_params* p);
+void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* const* gam, double* const* w,
+                      uint16_t* flags, const grmhd_params& p, const double* blo, const double* bhi,
+                      double* mu_out, int32_t* nev_out, c2p_stats* stats, hipStream_t s);
 }  // namespace gk
 
 namespace {
@@ -143,6 +146,63 @@ __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 g
       atomicAdd(&stats->fallbacks, c_fb);
       atomicAdd(&stats->failures, c_fail);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the network alone: bracket [lo, hi] of every state into br[0..n), br[n..2n)
+// (states that an atmosphere rule settles get an empty bracket)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 gm, Eos e,
+                                                    grmhd_params p, const uint16_t* wh,
+                                                    const float* wf, Feat ft, float width_k,
+                                                    float width_min, double* br) {
+  __shared__ InvLds s;
+  mlp_load(s.w, wh, wf);
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * kT; base < n; base += (int64_t)gridDim.x * kT) {
+    const int64_t t = base + threadIdx.x;
+    float x[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    bool done = true;
+    if (t < n) {
+      M3 m;
+      load_metric(gm, t, m);
+      double U[5], B[3], w[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) U[v] = u.p[v][t];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) B[v] = bt.p[v][t];
+      const C2PWork cw = c2p_prepare(e, p, m, U, B, w);
+      done = cw.done;
+      if (!done) features(cw.k, ft, x);
+    }
+    uint16_t* in = s.in[wv];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) in[l * kLdIn + c] = c < 5 ? f2bf(x[c]) : (uint16_t)0;
+    __syncthreads();
+#pragma unroll 1
+    for (int mt = 0; mt < 4; ++mt) {
+      mlp_hidden<1>(in + mt * 16 * kLdIn, kLdIn, s.w.W1, kLdIn, s.w.b1, s.h[wv][0], nullptr);
+      __syncthreads();
+      mlp_hidden<4>(s.h[wv][0], kLdH, s.w.W2, kLdH, s.w.b2, s.h[wv][1], nullptr);
+      __syncthreads();
+      mlp_hidden<4>(s.h[wv][1], kLdH, s.w.W3, kLdH, s.w.b3, s.h[wv][0], nullptr);
+      __syncthreads();
+      mlp_out(s.h[wv][0], s.w.W4, s.w.b4, s.y[wv] + mt * 16 * 2);
+      __syncthreads();
+    }
+    if (t < n) {
+      double lo = 0.0, hi = 0.0;
+      if (!done) {
+        const double y0 = (double)s.y[wv][l * 2 + 0], y1 = (double)s.y[wv][l * 2 + 1];
+        const double half = (double)width_k * exp(fmin(y1, 30.0)) + (double)width_min;
+        lo = 1.0 / (1.0 + exp(-(y0 - half)));
+        hi = 1.0 / (1.0 + exp(-(y0 + half)));
+      }
+      br[t] = lo;
+      br[n + t] = hi;
+    }
+    __syncthreads();
   }
 }
 
@@ -449,6 +509,18 @@ int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], double* cons
     return GRMHD_EINVAL;
   Feat ft;
   for (int c = 0; c < 5; ++c) { ft.mean[c] = mlp->feat_mean[c]; ft.scale[c] = mlp->feat_scale[c]; }
+  if (mlp->bracket_ws) {
+    // network as its own MFMA kernel, then the lean FP64 root kernel
+    {
+      TIMED(T_MLP_BRACKET, (hipStream_t)stream);
+      k_mlp_bracket<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
+          n, pu, pb, pg, make_eos_host(*p), *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,
+          mlp->width_min, mlp->bracket_ws);
+    }
+    launch_c2p_batch(n, u, bt, gam, w, flags, *p, mlp->bracket_ws, mlp->bracket_ws + n, mu_out,
+                     nev_out, stats, (hipStream_t)stream);
+    return learned_err();
+  }
   TIMED(T_C2P_LEARNED, (hipStream_t)stream);
   k_c2p_learned<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
       n, pu, pb, pg, pw, flags, make_eos_host(*p), *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,

@@ -369,7 +369,7 @@ def star_block_numpy(st: StarSetup, ib, jb, kb, n_per_side=4, nb=64, ng=3):
 
 
 def refined_star_blocks(nblocks=1500, nlevels=6, sizes=(16, 24, 32), ng=3, seed_offset=2,
-                        st: StarSetup | None = None, max_blocks=None):
+                        st: StarSetup | None = None, max_blocks=None, device=None):
     """Independent blocks of the star on nlevels nested levels (level l has
     spacing h0 / 2^l on the cube [-box/2^l, box/2^l]^3).  Block sizes and the
     number of blocks per level are drawn from a seeded multinomial; each block
@@ -390,7 +390,8 @@ def refined_star_blocks(nblocks=1500, nlevels=6, sizes=(16, 24, 32), ng=3, seed_
             n = sizes[nsz[t]]
             # origin on the lattice, block inside the level cube
             i0, j0, k0 = (rng.integers(0, ncell_level - n + 1) for _ in range(3))
-            w, bf, adm = _star_block_arrays(st, int(i0), int(j0), int(k0), n, ng, h, -half)
+            w, bf, adm = _star_block_arrays(st, int(i0), int(j0), int(k0), n, ng, h, -half,
+                                            _TorchBackend(device) if device is not None else None)
             blocks.append(BlockInit(n, n, n, ng, (h, h, h), w, bf, adm, [-1] * 27, 0, lev,
                                     (-half + i0 * h, -half + j0 * h, -half + k0 * h)))
             if max_blocks is not None and len(blocks) >= max_blocks:

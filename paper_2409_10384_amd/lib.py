@@ -157,11 +157,12 @@ def _ptr_array(ts):
 # measurement helpers
 # ---------------------------------------------------------------------------
 FAMILIES = ["flux_x", "flux_y", "flux_z", "fofc_flags", "fofc_fix", "ct", "update", "stage_c2p",
-            "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train"]
+            "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train", "mlp_bracket"]
 KERNEL_OF_FAMILY = {"flux_x": "k_flux<0>", "flux_y": "k_flux<1>", "flux_z": "k_flux<2>",
                     "fofc_flags": "k_fofc_flags", "update": "k_update", "stage_c2p": "k_stage_c2p",
                     "dt": "k_dt", "bcc": "k_bcc", "c2p_batch": "k_c2p_batch",
-                    "c2p_learned": "k_c2p_learned", "mlp_train": "k_mlp_train"}
+                    "c2p_learned": "k_c2p_learned", "mlp_train": "k_mlp_train",
+                    "mlp_bracket": "k_mlp_bracket"}
 
 
 def timing(on: bool):
@@ -361,6 +362,42 @@ class DeviceMesh:
             self.stage(2, dt=dt)
         self.ghost_fill(0)
 
+    def rk2_step_per_block(self, dt=None, cfl=0.25):
+        """The same RK2 step launched block by block (one-block tables): the
+        unbatched baseline.  Only for blocks with frozen ghosts (bc == 0)."""
+        L = load()
+        if any(b.bc != 0 for b in self.blocks):
+            raise GrmhdError("per-block launches need independent blocks (bc == 0)")
+        if not hasattr(self, "_single"):
+            self._single = []
+            for ib in range(len(self.blocks)):
+                t = {}
+                for key, stage in (("s1", 1), ("s2", 2)):
+                    arr = (GrmhdBlock * 1)()
+                    if stage == 1:
+                        arr[0] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
+                                            self.b0[ib], self.u1[ib], self.b1[ib], self.w1[ib])
+                    else:
+                        arr[0] = self._desc(ib, self.w1[ib], self.u0[ib], self.u1[ib], self.b0[ib],
+                                            self.b1[ib], self.u0[ib], self.b0[ib], self.w0[ib])
+                    arr[0].nbr = (C.c_int32 * 27)(*([-1] * 27))
+                    check(L.grmhd_blocks_prepare(C.cast(arr, C.c_void_p), 1), "grmhd_blocks_prepare")
+                    raw = bytes(memoryview(arr).cast("B"))
+                    t[key] = (arr, torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device))
+                self._single.append(t)
+        if dt is None:
+            self.compute_dt(cfl)
+            dptr, dval = C.c_void_p(self.dt_dev.data_ptr()), 0.0
+        else:
+            dptr, dval = None, float(dt)
+        pc = C.byref(self.params.c())
+        for stage, (a0, a1, b) in ((1, (0.0, 1.0, 1.0)), (2, (0.5, 0.5, 0.5))):
+            key = "s1" if stage == 1 else "s2"
+            for t in self._single:
+                arr, dev = t[key]
+                check(L.grmhd_stage(C.cast(arr, C.c_void_p), C.c_void_p(dev.data_ptr()), 1, pc, dptr,
+                                    dval, a0, a1, b, self.sp()), "grmhd_stage")
+
     def mass(self):
         check(load().grmhd_mass(*self._args("fillA"), C.c_void_p(self.mass_part.data_ptr()),
                                 C.c_void_p(self.mass_out.data_ptr()), self.sp()), "grmhd_mass")
@@ -407,7 +444,8 @@ NPARAM = 8834
 
 class C2PMlp(C.Structure):
     _fields_ = [("w_bf16", C.c_void_p), ("w_f32", C.c_void_p), ("feat_mean", C.c_float * 5),
-                ("feat_scale", C.c_float * 5), ("width_k", C.c_float), ("width_min", C.c_float)]
+                ("feat_scale", C.c_float * 5), ("width_k", C.c_float), ("width_min", C.c_float),
+                ("bracket_ws", C.c_void_p)]
 
 
 class LearnedC2P:
@@ -494,8 +532,10 @@ class LearnedC2P:
 
 
 def c2p_batch_learned(u, bt, gam, params: MethodParams, net: LearnedC2P, want_mu=False,
-                      want_nev=False, stats=False, stream=None):
-    """c2p_batch with the learned bracket (same outputs as c2p_batch)."""
+                      want_nev=False, stats=False, stream=None, split=True, workspace=None):
+    """c2p_batch with the learned bracket (same outputs as c2p_batch).
+    split: the network runs as its own MFMA kernel writing the brackets into a
+    workspace of 2n doubles, then the FP64 root kernel; else one fused kernel."""
     L = load()
     n = u.shape[1]
     dev = u.device
@@ -505,6 +545,9 @@ def c2p_batch_learned(u, bt, gam, params: MethodParams, net: LearnedC2P, want_mu
     nev = torch.empty(n, dtype=torch.int32, device=dev) if want_nev else None
     st = torch.zeros(4, dtype=torch.int64, device=dev) if stats else None
     mlp = net.c()
+    if split:
+        ws = workspace if workspace is not None else torch.empty(2 * n, dtype=torch.float64, device=dev)
+        mlp.bracket_ws = _ptr(ws)
     rc = L.c2p_batch(n, _ptr_array(list(u)), _ptr_array(list(bt)), _ptr_array(list(gam)),
                      _ptr_array(list(w)), _ptr(flags), C.byref(params.c()), C.byref(mlp),
                      _ptr(st) if st is not None else None, _ptr(mu) if mu is not None else None,
