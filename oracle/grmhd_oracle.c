@@ -552,29 +552,43 @@ static void face_physics(const eos_t *e, const met3 *m, double alpha, const doub
   *lm = alpha * (v[d] * (1.0 - c2) - sq) / den - beta[d];
 }
 
+/* Mass-flux dead band.  The upwind CT (Sec. III-B) picks the upwind cell by
+   the sign of the face mass flux.  Where that flux vanishes in exact
+   arithmetic (e.g. atmosphere at rest on both sides) the computed value is
+   rounding noise of either sign, so the pick would be arbitrary.  A mass flux
+   whose magnitude is at most MASS_FLUX_ZERO times the magnitude scale of the
+   Riemann formula that produced it is taken to be exactly zero. */
+#define MASS_FLUX_ZERO 1e-12
+
 /* HLLE (Harten 1983, Einfeldt 1991); LLF when riemann == 0 */
 static void riemann_solve(int riemann, const double UL[7], const double FL[7], double lmL,
                           double lpL, const double UR[7], const double FR[7], double lmR,
                           double lpR, double F[7]) {
+  double scale;
   if (riemann == 0) {
     double a = fabs(lmL);
     if (fabs(lpL) > a) a = fabs(lpL);
     if (fabs(lmR) > a) a = fabs(lmR);
     if (fabs(lpR) > a) a = fabs(lpR);
     for (int c = 0; c < 7; ++c) F[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * a * (UR[c] - UL[c]);
-    return;
+    scale = 0.5 * (fabs(FL[0]) + fabs(FR[0])) + 0.5 * a * (fabs(UR[0]) + fabs(UL[0]));
+  } else {
+    double lr = 0.0, ll = 0.0;
+    if (lpL > lr) lr = lpL;
+    if (lpR > lr) lr = lpR;
+    if (lmL < ll) ll = lmL;
+    if (lmR < ll) ll = lmR;
+    if (lr - ll == 0.0) {
+      for (int c = 0; c < 7; ++c) F[c] = 0.5 * (FL[c] + FR[c]);
+      scale = 0.5 * (fabs(FL[0]) + fabs(FR[0]));
+    } else {
+      for (int c = 0; c < 7; ++c)
+        F[c] = (lr * FL[c] - ll * FR[c] + lr * ll * (UR[c] - UL[c])) / (lr - ll);
+      scale = (lr * fabs(FL[0]) - ll * fabs(FR[0]) - lr * ll * (fabs(UR[0]) + fabs(UL[0]))) /
+              (lr - ll);
+    }
   }
-  double lr = 0.0, ll = 0.0;
-  if (lpL > lr) lr = lpL;
-  if (lpR > lr) lr = lpR;
-  if (lmL < ll) ll = lmL;
-  if (lmR < ll) ll = lmR;
-  if (lr - ll == 0.0) {
-    for (int c = 0; c < 7; ++c) F[c] = 0.5 * (FL[c] + FR[c]);
-    return;
-  }
-  for (int c = 0; c < 7; ++c)
-    F[c] = (lr * FL[c] - ll * FR[c] + lr * ll * (UR[c] - UL[c])) / (lr - ll);
+  if (fabs(F[0]) <= MASS_FLUX_ZERO * scale) F[0] = 0.0;
 }
 
 /* WENOZ (Borges et al. 2008), value at the right interface of cell 0 from

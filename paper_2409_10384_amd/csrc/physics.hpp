@@ -207,25 +207,37 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
   s.lm = alpha * (base - sq) * iden - beta[DIR];
 }
 
+// A mass flux below this fraction of the magnitude scale of its Riemann
+// formula is rounding noise of a flux that vanishes exactly (e.g. atmosphere
+// at rest); it is set to zero so that the upwind CT averages there instead of
+// following the noise's sign.
+constexpr double kMassFluxZero = 1e-12;
+
 __device__ __forceinline__ void riemann(int kind, const Side& L, const Side& R, double F[7]) {
+  double scale;
   if (kind == 0) {
     double a = fmax(fmax(fabs(L.lm), fabs(L.lp)), fmax(fabs(R.lm), fabs(R.lp)));
 #pragma unroll
     for (int c = 0; c < 7; ++c) F[c] = 0.5 * (L.F[c] + R.F[c]) - 0.5 * a * (R.U[c] - L.U[c]);
-    return;
-  }
-  const double ar = fmax(0.0, fmax(L.lp, R.lp));
-  const double al = fmin(0.0, fmin(L.lm, R.lm));
-  const double den = ar - al;
-  if (den == 0.0) {
+    scale = 0.5 * (fabs(L.F[0]) + fabs(R.F[0])) + 0.5 * a * (fabs(R.U[0]) + fabs(L.U[0]));
+  } else {
+    const double ar = fmax(0.0, fmax(L.lp, R.lp));
+    const double al = fmin(0.0, fmin(L.lm, R.lm));
+    const double den = ar - al;
+    if (den == 0.0) {
 #pragma unroll
-    for (int c = 0; c < 7; ++c) F[c] = 0.5 * (L.F[c] + R.F[c]);
-    return;
-  }
-  const double id = 1.0 / den;
-  const double arl = ar * al;
+      for (int c = 0; c < 7; ++c) F[c] = 0.5 * (L.F[c] + R.F[c]);
+      scale = 0.5 * (fabs(L.F[0]) + fabs(R.F[0]));
+    } else {
+      const double id = 1.0 / den;
+      const double arl = ar * al;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) F[c] = (ar * L.F[c] - al * R.F[c] + arl * (R.U[c] - L.U[c])) * id;
+      for (int c = 0; c < 7; ++c)
+        F[c] = (ar * L.F[c] - al * R.F[c] + arl * (R.U[c] - L.U[c])) * id;
+      scale = (ar * fabs(L.F[0]) - al * fabs(R.F[0]) - arl * (fabs(R.U[0]) + fabs(L.U[0]))) * id;
+    }
+  }
+  if (fabs(F[0]) <= kMassFluxZero * scale) F[0] = 0.0;
 }
 
 // WENOZ value at the upper interface of cell c from cells c-2..c+2

@@ -239,6 +239,29 @@ def test_hlle_upwinding_and_formula():
     np.testing.assert_allclose(F, 0.5 * (FL + FR) - 0.5 * a * (UR - UL), rtol=1e-13)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mass_flux_dead_band(kind):
+    """A face mass flux that vanishes in exact arithmetic (equal densities at
+    rest on both sides, differing only by rounding) comes out exactly zero, so
+    the upwind CT averages instead of following the sign of the noise; a real
+    mass flux a million times larger than the noise passes unchanged."""
+    n = 6
+    UL = np.zeros((7, n)); UR = np.zeros((7, n)); FL = np.zeros((7, n)); FR = np.zeros((7, n))
+    D = np.array([1.28e-13, 1.0, 3.7e-7, 2.0, 5e-9, 1.0])
+    UL[0] = D
+    UR[0] = D * (1 + np.array([1, -1, 2, -3, 1, 4]) * 2.0 ** -52)
+    lm = np.full(n, -0.3); lp = np.full(n, 0.5)
+    F = O.riemann(kind, UL, FL, lm, lp, UR, FR, lm, lp)
+    assert np.all(F[0] == 0.0)
+    UR[0] = D * (1 + 1e-9)
+    F = O.riemann(kind, UL, FL, lm, lp, UR, FR, lm, lp)
+    if kind == 1:
+        ref = (-0.3 * 0.5) * (UR[0] - UL[0]) / 0.8
+    else:
+        ref = -0.5 * 0.5 * (UR[0] - UL[0])
+    np.testing.assert_allclose(F[0], ref, rtol=1e-6)
+
+
 # ---------------------------------------------------------------------------
 # WENOZ reconstruction
 # ---------------------------------------------------------------------------
