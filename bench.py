@@ -18,6 +18,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -260,8 +261,8 @@ def c2p_section(args, torch, inputs, lib):
     steps = args.train_steps
     for it in range(steps):
         idx = torch.randint(0, feats.shape[1], (4096,), device="cuda", generator=gen)
-        loss, _ = net.train_step(feats[:, idx].contiguous(), target[idx].contiguous(),
-                                 lr=2e-3 if it < 0.7 * steps else 5e-4)
+        lr = 2e-3 * 0.5 * (1.0 + math.cos(math.pi * it / steps)) + 1e-5   # cosine decay
+        loss, _ = net.train_step(feats[:, idx].contiguous(), target[idx].contiguous(), lr=lr)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     log(f"trained {steps} steps in {train_s:.1f} s, final loss {float(loss.item()):.3g}")
@@ -270,6 +271,8 @@ def c2p_section(args, torch, inputs, lib):
     for kind in ("plain", "learned", "learned_fused"):
         times = []
         for rep in range(args.c2p_reps + 1):
+            if rep == 1:
+                lib.timing(True)
             u = u0.clone()
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -284,14 +287,18 @@ def c2p_section(args, torch, inputs, lib):
             torch.cuda.synchronize()
             if rep > 0:
                 times.append(e0.elapsed_time(e1))
+        kt = lib.timing_read()
+        lib.timing(False)
         ms = sorted(times)[len(times) // 2]
         err = ((out["mu"] - mu_exact).abs() / mu_exact).max().item()
         stt = out["stats"].cpu().tolist()
         res[kind] = {"solves_per_s": n / (ms * 1e-3), "ms": ms, "max_mu_rel_err": err,
                      "mean_master_evals": stt[1] / stt[0], "fallback_rate": stt[2] / stt[0],
-                     "unrecovered_failures": int(stt[3])}
+                     "unrecovered_failures": int(stt[3]),
+                     "kernel_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]}}
         log(f"c2p {kind}: {res[kind]['solves_per_s']:.3e} solves/s, err {err:.2e}, "
-            f"evals {res[kind]['mean_master_evals']:.2f}, fallback {res[kind]['fallback_rate']:.4f}")
+            f"evals {res[kind]['mean_master_evals']:.2f}, fallback {res[kind]['fallback_rate']:.4f}, "
+            f"kernels {res[kind]['kernel_ms']}")
     res["states"] = n
     res["train_steps"] = steps
     res["train_s"] = train_s
@@ -309,7 +316,7 @@ def main():
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--c2p-log2", type=int, default=24)
     ap.add_argument("--c2p-reps", type=int, default=3)
-    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--no-c2p", action="store_true")
     ap.add_argument("--c2p-only", action="store_true", help="only the C2P solves/s section")
     ap.add_argument("--no-refined", action="store_true")

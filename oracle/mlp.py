@@ -23,7 +23,9 @@ with the logistic function.
 
 Loss per sample: 0.5 (y0 - t)^2 + 0.5 (y1 - log(|y0 - t| + c))^2 with
 t = logit(mu*), the second target using y0 without gradient; averaged over
-the batch.
+the batch.  The second output is a linear read-out of the last hidden layer:
+its loss trains only that read-out (W4[1], b4[1]), so the noisy error-scale
+target does not pull the shared hidden layers away from the guess.
 """
 import numpy as np
 
@@ -99,7 +101,10 @@ def backward(params, cache, dy):
         dW = g.T @ acts[li]
         db = g.sum(axis=0)
         grads[li] = [dW, db]
-        g = g @ W
+        if li == len(params) - 1:
+            g = g[:, :1] @ W[:1]        # the error-scale output stops here
+        else:
+            g = g @ W
     return grads
 
 

@@ -102,9 +102,10 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   riemann(p.riemann, L, R, F);
 }
 
-template <int D>
-__global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e,
+template <int D, int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e_in,
                                                    grmhd_params p) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_XFACE + D, bi, t)) return;
@@ -149,10 +150,12 @@ __device__ __forceinline__ double flux_div(const grmhd_block& b, const Geo& q, i
          (fz[face<2>(q, i, j, k + 1)] - fz[face<2>(q, i, j, k)]) / b.dx[2];
 }
 
+template <int ET>
 __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* __restrict__ blks,
-                                                         Eos e, grmhd_params p,
+                                                         Eos e_in, grmhd_params p,
                                                          const double* dt_d, double dt_h,
                                                          double a0, double a1, double bb) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_INTERIOR, bi, t)) return;
@@ -186,20 +189,30 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* _
       if (!(U[v] >= lo && U[v] <= hi)) fl |= GRMHD_F_DMP;
     }
   }
-  M3 m;
-  cell_metric(b, c, m);
-  double Bt[3], w[5];
-  cell_bt(q, b.bs, i, j, k, Bt);
-  int nev;
-  double mu;
-  const uint32_t r = c2p_cell(e, p, m, U, Bt, w, false, 0.0, 0.0, nev, mu);
+  // trial inversion: only whether a rule fires matters (U is not rebuilt)
+  double w[5];
+  C2PWork cw;
+  {
+    M3 m;
+    cell_metric(b, c, m);
+    double Bt[3];
+    cell_bt(q, b.bs, i, j, k, Bt);
+    cw = c2p_prepare(e, p, m, U, Bt, w);
+  }
+  uint32_t r = cw.fl;
+  if (!cw.done) {
+    int nev;
+    double mu;
+    r = c2p_lean(e, p, cw, w, false, 0.0, 0.0, nev, mu);
+  }
   if (r & kFloorBits) fl |= GRMHD_F_FOFC;
   b.flags[c] = (uint16_t)fl;
 }
 
-template <int D>
-__global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e,
+template <int D, int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e_in,
                                                        grmhd_params p) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_XFACE + D, bi, t)) return;
@@ -365,9 +378,11 @@ __device__ __forceinline__ double dcen(const double* a, int64_t c, int64_t st, d
   return ((a[c - 2 * st] - a[c + 2 * st]) - 8.0 * (a[c - st] - a[c + st])) * idx12;
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e,
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e_in,
                                                      const double* dt_d, double dt_h, double a0,
                                                      double a1, double bb) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_INTERIOR, bi, t)) return;
@@ -455,8 +470,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
 // ---------------------------------------------------------------------------
 // a8: inversion of the updated state with the updated field
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e,
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e_in,
                                                         grmhd_params p) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_INTERIOR, bi, t)) return;
@@ -466,20 +483,41 @@ __global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __
   int i, j, k;
   bx.at(t, i, j, k);
   const int64_t c = cell(q, i, j, k);
-  M3 m;
-  cell_metric(b, c, m);
-  double U[5], Bt[3], w[5];
+  double w[5];
+  C2PWork cw;
+  {
+    M3 m;
+    cell_metric(b, c, m);
+    double U[5], Bt[3];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
-  cell_bt(q, b.bo, i, j, k, Bt);
-  int nev;
-  double mu;
-  const uint32_t r = c2p_cell(e, p, m, U, Bt, w, false, 0.0, 0.0, nev, mu);
+    for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
+    cell_bt(q, b.bo, i, j, k, Bt);
+    cw = c2p_prepare(e, p, m, U, Bt, w);
+    if (cw.done) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    b.uo[v][c] = U[v];
-    b.wo[v][c] = w[v];
+      for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+    }
   }
+  uint32_t r = cw.fl;
+  if (!cw.done) {
+    int nev;
+    double mu;
+    r = c2p_lean(e, p, cw, w, false, 0.0, 0.0, nev, mu);
+    if (r & kFloorBits) {
+      // U from the final primitives; metric and field loaded again (the
+      // barrier keeps them from living across the root solve)
+      __asm__ volatile("" ::: "memory");
+      M3 m;
+      cell_metric(b, c, m);
+      double U[5], Bt[3];
+      cell_bt(q, b.bo, i, j, k, Bt);
+      prim_to_cons(e, m, w, Bt, U);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) b.wo[v][c] = w[v];
   b.flags[c] = (uint16_t)(b.flags[c] | r);
 }
 
@@ -592,8 +630,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e,
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e_in,
                                                  double* red) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   const bool live = locate(blks, S_INTERIOR, bi, t);   // no early return: barrier below
@@ -673,7 +713,9 @@ __global__ void k_mass_final(const double* partial, int nblk, double* out) {
 }
 
 // Eq. 7 over every padded cell of a block: us <- prim2con(w, B~_cc(bs))
-__global__ __launch_bounds__(kMaxThreads) void k_p2c_block(const grmhd_block* __restrict__ blks, Eos e) {
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_p2c_block(const grmhd_block* __restrict__ blks, Eos e_in) {
+  const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
   if (!locate(blks, S_CELLS, bi, t)) return;
@@ -698,8 +740,10 @@ struct Ptrs5 { double* p[5]; };
 struct Ptrs3 { double* p[3]; };
 struct Ptrs6 { double* p[6]; };
 
+template <int ET>
 __global__ __launch_bounds__(kThreads) void k_prim2con(int64_t n, Ptrs5 w, Ptrs3 bt, Ptrs6 gm,
-                                                       Ptrs5 u, Eos e) {
+                                                       Ptrs5 u, Eos e_in) {
+  const Eos e = eos_fixed<ET>(e_in);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   M3 m;
@@ -714,28 +758,50 @@ __global__ __launch_bounds__(kThreads) void k_prim2con(int64_t n, Ptrs5 w, Ptrs3
 
 // inversion of n states; optional per-state bracket [blo, bhi] (learned
 // guess, computed by a separate kernel); statistics reduced per wave first
+template <int ET>
 __global__ __launch_bounds__(kThreads) void k_c2p_batch(int64_t n, Ptrs5 u, Ptrs3 bt, Ptrs6 gm,
-                                                        Ptrs5 w, uint16_t* flags, Eos e,
+                                                        Ptrs5 w, uint16_t* flags, Eos e_in,
                                                         grmhd_params p, const double* blo,
                                                         const double* bhi, double* mu_out,
                                                         int32_t* nev_out, c2p_stats* stats) {
+  const Eos e = eos_fixed<ET>(e_in);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_n = 0, c_ev = 0, c_fb = 0, c_fail = 0;
   if (t < n) {
-    M3 m;
-    metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
-    double U[5] = {u.p[0][t], u.p[1][t], u.p[2][t], u.p[3][t], u.p[4][t]};
-    const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+    C2PWork cw;
     double ww[5];
-    int nev;
-    double mu;
-    const bool br = blo != nullptr;
-    const uint32_t r = c2p_cell(e, p, m, U, B, ww, br, br ? blo[t] : 0.0, br ? bhi[t] : 0.0, nev, mu);
+    {
+      M3 m;
+      metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
+      double U[5] = {u.p[0][t], u.p[1][t], u.p[2][t], u.p[3][t], u.p[4][t]};
+      const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+      cw = c2p_prepare(e, p, m, U, B, ww);
+      if (cw.done) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      u.p[v][t] = U[v];
-      w.p[v][t] = ww[v];
+        for (int v = 0; v < 5; ++v) u.p[v][t] = U[v];
+      }
     }
+    int nev = 0;
+    double mu = 0.0;
+    uint32_t r = cw.fl;
+    if (!cw.done) {
+      const bool br = blo != nullptr;
+      r = c2p_lean(e, p, cw, ww, br, br ? blo[t] : 0.0, br ? bhi[t] : 0.0, nev, mu);
+      if (r & kFloorBits) {
+        // a rule fired: U from the final primitives, with the metric and field
+        // loaded again (the barrier keeps them from living across the solve)
+        __asm__ volatile("" ::: "memory");
+        M3 m;
+        metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
+        const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+        double U[5];
+        prim_to_cons(e, m, ww, B, U);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u.p[v][t] = U[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w.p[v][t] = ww[v];
     flags[t] = (uint16_t)r;
     if (mu_out) mu_out[t] = mu;
     if (nev_out) nev_out[t] = nev;
@@ -902,14 +968,20 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
   }
   {
     TIMED(T_FLUX_X, s);
-    k_flux<0><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FLUX_X)), tpb(T_FLUX_X), 0, s>>>(d, e, p);
+    eos_dispatch(e.type, [&](auto et) {
+      k_flux<0, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FLUX_X)), tpb(T_FLUX_X), 0, s>>>(d, e, p);
+    });
   }
   {
     TIMED(T_FLUX_Y, s);
-    k_flux<1><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FLUX_Y)), tpb(T_FLUX_Y), 0, s>>>(d, e, p);
+    eos_dispatch(e.type, [&](auto et) {
+      k_flux<1, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FLUX_Y)), tpb(T_FLUX_Y), 0, s>>>(d, e, p);
+    });
   }
   TIMED(T_FLUX_Z, s);
-  k_flux<2><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FLUX_Z)), tpb(T_FLUX_Z), 0, s>>>(d, e, p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_flux<2, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FLUX_Z)), tpb(T_FLUX_Z), 0, s>>>(d, e, p);
+  });
 }
 
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
@@ -920,16 +992,21 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   if (!p.fofc) return;
   {
     TIMED(T_FOFC_FLAGS, s);
-    k_fofc_flags<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
+    eos_dispatch(e.type, [&](auto et) {
+      k_fofc_flags<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
+    });
   }
   {
     TIMED(T_GHOST, s);
     k_ghost_cells<<<grid_cls(h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8);
   }
   TIMED(T_FOFC_FIX, s);
-  k_fofc_fix<0><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
-  k_fofc_fix<1><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
-  k_fofc_fix<2><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+  eos_dispatch(e.type, [&](auto et) {
+    constexpr int ET = decltype(et)::value;
+    k_fofc_fix<0, ET><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+    k_fofc_fix<1, ET><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+    k_fofc_fix<2, ET><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+  });
 }
 
 void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
@@ -949,14 +1026,18 @@ void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos&
                 const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_UPDATE, s);
-  k_update<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(d, e, dt_d, dt, a0, a1, b);
+  eos_dispatch(e.type, [&](auto et) {
+    k_update<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(d, e, dt_d, dt, a0, a1, b);
+  });
 }
 
 void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
              const Eos& e, hipStream_t s) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_C2P, s);
-  k_stage_c2p<<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(d, e, p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_stage_c2p<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(d, e, p);
+  });
 }
 
 // plain streaming copy (counter calibration)
@@ -982,8 +1063,11 @@ void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* co
   for (int v = 0; v < 3; ++v) pb.p[v] = bt[v];
   for (int v = 0; v < 6; ++v) pg.p[v] = gam[v];
   TIMED(blo ? T_C2P_LEARNED : T_C2P_BATCH, s);
-  k_c2p_batch<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-      n, pu, pb, pg, pw, flags, make_eos(p), p, blo, bhi, mu_out, nev_out, stats);
+  const Eos e = make_eos(p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_c2p_batch<decltype(et)::value><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        n, pu, pb, pg, pw, flags, e, p, blo, bhi, mu_out, nev_out, stats);
+  });
 }
 Eos make_eos_host(const grmhd_params& p) { return make_eos(p); }
 int check_params_host(const grmhd_params* p) { return check_params(p); }
@@ -1133,7 +1217,10 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
   k_zero1<<<1, 64, 0, s>>>(red);
   {
     TIMED(T_DT, s);
-    k_dt<<<grid_cls(blk_h, nblk, S_INTERIOR, tpb(T_DT)), tpb(T_DT), 0, s>>>(blk_d, make_eos(*p), red);
+    const Eos e = make_eos(*p);
+    eos_dispatch(e.type, [&](auto et) {
+      k_dt<decltype(et)::value><<<grid_cls(blk_h, nblk, S_INTERIOR, tpb(T_DT)), tpb(T_DT), 0, s>>>(blk_d, e, red);
+    });
   }
   k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
   return last_err();
@@ -1160,8 +1247,11 @@ int prim2con(int64_t n, double* const w[5], double* const bt[3], double* const g
   for (int v = 0; v < 5; ++v) { pw.p[v] = w[v]; pu.p[v] = u[v]; if (!w[v] || !u[v]) return GRMHD_EINVAL; }
   for (int v = 0; v < 3; ++v) { pb.p[v] = bt[v]; if (!bt[v]) return GRMHD_EINVAL; }
   for (int v = 0; v < 6; ++v) { pg.p[v] = gam[v]; if (!gam[v]) return GRMHD_EINVAL; }
-  k_prim2con<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, (hipStream_t)stream>>>(
-      n, pw, pb, pg, pu, make_eos(*p));
+  const Eos e = make_eos(*p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_prim2con<decltype(et)::value><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0,
+                                      (hipStream_t)stream>>>(n, pw, pb, pg, pu, e);
+  });
   return last_err();
 }
 
@@ -1188,7 +1278,11 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
   if (!blk_h || !blk_d || nblk < 1) return GRMHD_EINVAL;
   if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
   const Sizes z = max_sizes(blk_h, nblk);
-  k_p2c_block<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, (hipStream_t)stream>>>(blk_d, make_eos(*p));
+  const Eos e = make_eos(*p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_p2c_block<decltype(et)::value><<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0,
+                                       (hipStream_t)stream>>>(blk_d, e);
+  });
   return last_err();
 }
 

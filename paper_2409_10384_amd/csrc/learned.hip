@@ -34,94 +34,118 @@ struct P3 { double* p[3]; };
 struct P6 { double* p[6]; };
 struct Feat { float mean[5], scale[5]; };
 
-// invariant features of the scaled state (see the oracle's definition)
+// invariant features of the scaled state (the oracle's definition), in fp32:
+// they are rounded to bf16 on entry to the network anyway.  log10 D from the
+// FP64 exponent plus the fp32 log of the mantissa, so any D > 0 is in range.
 __device__ __forceinline__ void features(const KState& k, const Feat& f, float x[5]) {
-  const double q1 = 1.0 + k.q;
-  double raw[5];
-  raw[0] = log10(k.D);
-  raw[1] = log10(q1);
-  raw[2] = sqrt(k.r2) / q1;
-  raw[3] = k.b2 / q1;
-  raw[4] = k.s * k.s / (k.r2 * k.b2 + 1e-300);
+  constexpr float kLog10_2 = 0.30102999566398120f;
+  int ex;
+  const double man = frexp(k.D, &ex);
+  const float iq1 = __builtin_amdgcn_rcpf((float)(1.0 + k.q));
+  const float den = (float)(k.r2 * k.b2);
+  float raw[5];
+  raw[0] = ((float)ex + __log2f((float)man)) * kLog10_2;
+  raw[1] = __log2f((float)(1.0 + k.q)) * kLog10_2;
+  raw[2] = __builtin_sqrtf((float)k.r2) * iq1;
+  raw[3] = (float)k.b2 * iq1;
+  raw[4] = den > 1e-30f ? fminf((float)(k.s * k.s) * __builtin_amdgcn_rcpf(den), 1.0f) : 0.0f;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) x[c] = (float)((raw[c] - (double)f.mean[c]) * (double)f.scale[c]);
+  for (int c = 0; c < 5; ++c) x[c] = (raw[c] - f.mean[c]) * f.scale[c];
 }
 
 __device__ __forceinline__ void load_metric(const P6& gm, int64_t t, M3& m) {
   metric_build(m, gm.p[0][t], gm.p[1][t], gm.p[2][t], gm.p[3][t], gm.p[4][t], gm.p[5][t]);
 }
 
-// ---------------------------------------------------------------------------
-// inversion with the learned bracket: one workgroup walks 256-state tiles;
-// the network runs on the MFMA units between the conserved-floor rules and
-// the FP64 root solve
-// ---------------------------------------------------------------------------
-struct InvLds {
-  MlpLds w;
-  uint16_t in[4][64 * kLdIn];
-  uint16_t h[4][2][16 * kLdH];
-  float y[4][64 * 2];
+// bracket [lo, hi] of mu from the network outputs: logistic(y0 -/+ half),
+// half = k exp(y1) + delta_min (exponentials in fp32, the logistic's division
+// in FP64 so that brackets near mu = 1 stay distinct)
+__device__ __forceinline__ void bracket_of(float y0, float y1, float width_k, float width_min,
+                                           double& lo, double& hi) {
+  const float half = width_k * __expf(fminf(y1, 30.0f)) + width_min;
+  lo = 1.0 / (1.0 + (double)__expf(-(y0 - half)));
+  hi = 1.0 / (1.0 + (double)__expf(-(y0 + half)));
+}
+
+// Persistent wave loop: wave w of the grid handles states [64 w', 64 w' + 64)
+// for w' = w, w + (waves in grid), ...; the loop bound is wave-uniform so
+// that every lane reaches the MFMA chain.
+struct WaveLoop {
+  int64_t first, stride;
+  __device__ WaveLoop() {
+    const int wpb = blockDim.x >> 6;
+    first = ((int64_t)blockIdx.x * wpb + (threadIdx.x >> 6)) * 64;
+    stride = (int64_t)gridDim.x * wpb * 64;
+  }
 };
 
+// ---------------------------------------------------------------------------
+// inversion with the learned bracket, fused: per wave, the conserved-floor
+// rules and features in FP64, the network on the MFMA units (activations in
+// registers), then the FP64 bracketed root solve
+// ---------------------------------------------------------------------------
+template <int ET>
 __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 gm, P5 wout,
-                                                    uint16_t* flags, Eos e, grmhd_params p,
+                                                    uint16_t* flags, Eos e_in, grmhd_params p,
                                                     const uint16_t* wh, const float* wf, Feat ft,
                                                     float width_k, float width_min, double* mu_out,
                                                     int32_t* nev_out, c2p_stats* stats) {
-  __shared__ InvLds s;
-  mlp_load(s.w, wh, wf);
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const Eos e = eos_fixed<ET>(e_in);
+  __shared__ MlpLds s;
+  mlp_load(s, wh, wf);
+  __syncthreads();
+  const int l = threadIdx.x & 63;
   unsigned long long c_solves = 0, c_nev = 0, c_fb = 0, c_fail = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kT; base < n; base += (int64_t)gridDim.x * kT) {
-    const int64_t t = base + threadIdx.x;
+  const WaveLoop wl;
+  for (int64_t base = wl.first; base < n; base += wl.stride) {
+    const int64_t t = base + l;
     const bool live = t < n;
-    M3 m;
-    double U[5], B[3], w[5];
+    double w[5];
     C2PWork cw;
     float x[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (live) {
+      M3 m;
+      double U[5], B[3];
       load_metric(gm, t, m);
 #pragma unroll
       for (int v = 0; v < 5; ++v) U[v] = u.p[v][t];
 #pragma unroll
       for (int v = 0; v < 3; ++v) B[v] = bt.p[v][t];
       cw = c2p_prepare(e, p, m, U, B, w);
-      if (!cw.done) features(cw.k, ft, x);
+      if (cw.done) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) u.p[v][t] = U[v];
+      } else {
+        features(cw.k, ft, x);
+      }
     } else {
       cw.done = true;
       cw.fl = 0;
     }
-    uint16_t* in = s.in[wv];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) in[l * kLdIn + c] = c < 5 ? f2bf(x[c]) : (uint16_t)0;
-    __syncthreads();
-#pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
-      mlp_hidden<1>(in + mt * 16 * kLdIn, kLdIn, s.w.W1, kLdIn, s.w.b1, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][0], kLdH, s.w.W2, kLdH, s.w.b2, s.h[wv][1], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][1], kLdH, s.w.W3, kLdH, s.w.b3, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_out(s.h[wv][0], s.w.W4, s.w.b4, s.y[wv] + mt * 16 * 2);
-      __syncthreads();
-    }
+    float y0, y1;
+    mlp_wave(s, x, y0, y1);
     if (live) {
       uint32_t r = cw.fl;
       int nev = 0;
       double mu = 0.0;
       if (!cw.done) {
-        const double y0 = (double)s.y[wv][l * 2 + 0], y1 = (double)s.y[wv][l * 2 + 1];
-        const double half = (double)width_k * exp(fmin(y1, 30.0)) + (double)width_min;
-        const double lo = 1.0 / (1.0 + exp(-(y0 - half)));
-        const double hi = 1.0 / (1.0 + exp(-(y0 + half)));
-        r = c2p_solve(e, p, m, cw, U, B, w, true, lo, hi, nev, mu);
+        double lo, hi;
+        bracket_of(y0, y1, width_k, width_min, lo, hi);
+        r = c2p_lean(e, p, cw, w, true, lo, hi, nev, mu);
+        if (r & kFloorBits) {
+          // U from the final primitives, metric and field loaded again
+          __asm__ volatile("" ::: "memory");
+          M3 m;
+          load_metric(gm, t, m);
+          const double B[3] = {bt.p[0][t], bt.p[1][t], bt.p[2][t]};
+          double U[5];
+          prim_to_cons(e, m, w, B, U);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) u.p[v][t] = U[v];
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        u.p[v][t] = U[v];
-        wout.p[v][t] = w[v];
-      }
+      for (int v = 0; v < 5; ++v) wout.p[v][t] = w[v];
       flags[t] = (uint16_t)r;
       if (mu_out) mu_out[t] = mu;
       if (nev_out) nev_out[t] = nev;
@@ -130,7 +154,6 @@ __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 g
       c_fb += (r & GRMHD_F_BRACKET_FALLBACK) ? 1 : 0;
       c_fail += (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
     }
-    __syncthreads();
   }
   if (stats) {
 #pragma unroll
@@ -153,15 +176,19 @@ __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 g
 // the network alone: bracket [lo, hi] of every state into br[0..n), br[n..2n)
 // (states that an atmosphere rule settles get an empty bracket)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 gm, Eos e,
+template <int ET>
+__global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 gm, Eos e_in,
                                                     grmhd_params p, const uint16_t* wh,
                                                     const float* wf, Feat ft, float width_k,
                                                     float width_min, double* br) {
-  __shared__ InvLds s;
-  mlp_load(s.w, wh, wf);
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * kT; base < n; base += (int64_t)gridDim.x * kT) {
-    const int64_t t = base + threadIdx.x;
+  const Eos e = eos_fixed<ET>(e_in);
+  __shared__ MlpLds s;
+  mlp_load(s, wh, wf);
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  const WaveLoop wl;
+  for (int64_t base = wl.first; base < n; base += wl.stride) {
+    const int64_t t = base + l;
     float x[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     bool done = true;
     if (t < n) {
@@ -176,33 +203,14 @@ __global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 g
       done = cw.done;
       if (!done) features(cw.k, ft, x);
     }
-    uint16_t* in = s.in[wv];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) in[l * kLdIn + c] = c < 5 ? f2bf(x[c]) : (uint16_t)0;
-    __syncthreads();
-#pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
-      mlp_hidden<1>(in + mt * 16 * kLdIn, kLdIn, s.w.W1, kLdIn, s.w.b1, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][0], kLdH, s.w.W2, kLdH, s.w.b2, s.h[wv][1], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][1], kLdH, s.w.W3, kLdH, s.w.b3, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_out(s.h[wv][0], s.w.W4, s.w.b4, s.y[wv] + mt * 16 * 2);
-      __syncthreads();
-    }
+    float y0, y1;
+    mlp_wave(s, x, y0, y1);
     if (t < n) {
       double lo = 0.0, hi = 0.0;
-      if (!done) {
-        const double y0 = (double)s.y[wv][l * 2 + 0], y1 = (double)s.y[wv][l * 2 + 1];
-        const double half = (double)width_k * exp(fmin(y1, 30.0)) + (double)width_min;
-        lo = 1.0 / (1.0 + exp(-(y0 - half)));
-        hi = 1.0 / (1.0 + exp(-(y0 + half)));
-      }
+      if (!done) bracket_of(y0, y1, width_k, width_min, lo, hi);
       br[t] = lo;
       br[n + t] = hi;
     }
-    __syncthreads();
   }
 }
 
@@ -211,9 +219,11 @@ __global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 g
 // conserved-floor rules) and the target logit(mu*), mu* = 1/(h W) of the
 // primitives that generated the state
 // ---------------------------------------------------------------------------
+template <int ET>
 __global__ __launch_bounds__(kT) void k_mlp_features(int64_t n, P5 u, P3 bt, P6 gm, P5 wtrue,
-                                                     int has_target, Eos e, grmhd_params p, Feat ft,
+                                                     int has_target, Eos e_in, grmhd_params p, Feat ft,
                                                      float* feats, float* target) {
+  const Eos e = eos_fixed<ET>(e_in);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   M3 m;
@@ -244,32 +254,22 @@ __global__ __launch_bounds__(kT) void k_mlp_features(int64_t n, P5 u, P3 bt, P6 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_mlp_forward(int64_t n, const float* feats, float* y,
                                                     const uint16_t* wh, const float* wf) {
-  __shared__ InvLds s;
-  mlp_load(s.w, wh, wf);
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * kT; base < n; base += (int64_t)gridDim.x * kT) {
-    const int64_t t = base + threadIdx.x;
-    uint16_t* in = s.in[wv];
+  __shared__ MlpLds s;
+  mlp_load(s, wh, wf);
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  const WaveLoop wl;
+  for (int64_t base = wl.first; base < n; base += wl.stride) {
+    const int64_t t = base + l;
+    float x[5];
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      in[l * kLdIn + c] = (c < 5 && t < n) ? f2bf(feats[c * n + t]) : (uint16_t)0;
-    __syncthreads();
-#pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
-      mlp_hidden<1>(in + mt * 16 * kLdIn, kLdIn, s.w.W1, kLdIn, s.w.b1, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][0], kLdH, s.w.W2, kLdH, s.w.b2, s.h[wv][1], nullptr);
-      __syncthreads();
-      mlp_hidden<4>(s.h[wv][1], kLdH, s.w.W3, kLdH, s.w.b3, s.h[wv][0], nullptr);
-      __syncthreads();
-      mlp_out(s.h[wv][0], s.w.W4, s.w.b4, s.y[wv] + mt * 16 * 2);
-      __syncthreads();
-    }
+    for (int c = 0; c < 5; ++c) x[c] = t < n ? feats[c * n + t] : 0.f;
+    float y0, y1;
+    mlp_wave(s, x, y0, y1);
     if (t < n) {
-      y[t] = s.y[wv][l * 2];
-      y[n + t] = s.y[wv][l * 2 + 1];
+      y[t] = y0;
+      y[n + t] = y1;
     }
-    __syncthreads();
   }
 }
 
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t nbatch, const float* f
     if (l == 0 && loss_part) loss_part[blockIdx.x] = ls;
   }
   __syncthreads();
-  // output layer in fp32 (two outputs): dW4, db4 and dh3 = dy W4, g3 = dh3 * SiLU'(z3)
+  // output layer in fp32 (two outputs): dW4, db4 and dh3 = dy0 W4[0], g3 = dh3 * SiLU'(z3)
   {
     // dW4[o][i] = sum_r dy[r][o] h3[r][i]; lane l owns column i = l
     float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
@@ -413,9 +413,11 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t nbatch, const float* f
       pg[kOffB4] = b0;
       pg[kOffB4 + 1] = b1;
     }
-    const float w0 = bf2f(s.w.W4[0 * kLdH + l]), w1 = bf2f(s.w.W4[1 * kLdH + l]);
+    // only the guess output trains the hidden layers: the error-scale output
+    // is a linear read-out of the last hidden layer (its gradient stops there)
+    const float w0 = bf2f(s.w.W4[0 * kLdH + l]);
     for (int r = 0; r < 64; ++r) {
-      const float g = (s.dy[r * 2] * w0 + s.dy[r * 2 + 1] * w1) * s.d[2][r * 64 + l];
+      const float g = s.dy[r * 2] * w0 * s.d[2][r * 64 + l];
       s.d[2][r * 64 + l] = g;
       s.ga[r * kLdH + l] = f2bf(g);
     }
@@ -487,7 +489,7 @@ unsigned persistent_grid(int64_t n) {
     if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cus = pr.multiProcessorCount;
   }
   const int64_t tiles = (n + kT - 1) / kT;
-  const int64_t g = (int64_t)cus * 2;
+  const int64_t g = (int64_t)cus * 8;   // enough resident waves at any occupancy
   return (unsigned)(tiles < g ? tiles : g);
 }
 
@@ -513,18 +515,24 @@ int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], double* cons
     // network as its own MFMA kernel, then the lean FP64 root kernel
     {
       TIMED(T_MLP_BRACKET, (hipStream_t)stream);
-      k_mlp_bracket<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
-          n, pu, pb, pg, make_eos_host(*p), *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,
-          mlp->width_min, mlp->bracket_ws);
+      const Eos e = make_eos_host(*p);
+      eos_dispatch(e.type, [&](auto et) {
+        k_mlp_bracket<decltype(et)::value><<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
+            n, pu, pb, pg, e, *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k, mlp->width_min,
+            mlp->bracket_ws);
+      });
     }
     launch_c2p_batch(n, u, bt, gam, w, flags, *p, mlp->bracket_ws, mlp->bracket_ws + n, mu_out,
                      nev_out, stats, (hipStream_t)stream);
     return learned_err();
   }
   TIMED(T_C2P_LEARNED, (hipStream_t)stream);
-  k_c2p_learned<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
-      n, pu, pb, pg, pw, flags, make_eos_host(*p), *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,
-      mlp->width_min, mu_out, nev_out, stats);
+  const Eos e = make_eos_host(*p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_c2p_learned<decltype(et)::value><<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(
+        n, pu, pb, pg, pw, flags, e, *p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k,
+        mlp->width_min, mu_out, nev_out, stats);
+  });
   return learned_err();
 }
 
@@ -545,8 +553,11 @@ int c2p_mlp_features(int64_t n, double* const u[5], double* const bt[3], double*
   }
   Feat ft;
   for (int c = 0; c < 5; ++c) { ft.mean[c] = mean[c]; ft.scale[c] = scale[c]; }
-  k_mlp_features<<<(unsigned)((n + kT - 1) / kT), kT, 0, (hipStream_t)stream>>>(
-      n, pu, pb, pg, pw, w_true ? 1 : 0, make_eos_host(*p), *p, ft, feats, target);
+  const Eos e = make_eos_host(*p);
+  eos_dispatch(e.type, [&](auto et) {
+    k_mlp_features<decltype(et)::value><<<(unsigned)((n + kT - 1) / kT), kT, 0, (hipStream_t)stream>>>(
+        n, pu, pb, pg, pw, w_true ? 1 : 0, e, *p, ft, feats, target);
+  });
   return learned_err();
 }
 

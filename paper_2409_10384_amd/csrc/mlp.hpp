@@ -26,17 +26,20 @@ constexpr int kOffW1 = 0, kOffB1 = 320, kOffW2 = 384, kOffB2 = 4480, kOffW3 = 45
 constexpr int kLdIn = 24;   // input tile / W1: 16 used
 constexpr int kLdH = 72;    // hidden activations / W2, W3, W4: 64 used
 
+// fp32 -> bf16, round to nearest even (one v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// logistic function with the hardware exp and reciprocal (relative error a
+// few ulp of fp32, far below the bf16 rounding of the activations)
+__device__ __forceinline__ float sigmoid_f(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float dsilu_f(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid_f(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -62,7 +65,10 @@ struct MlpLds {
   uint16_t W2[64 * kLdH];
   uint16_t W3[64 * kLdH];
   uint16_t W4[16 * kLdH];
-  float b1[64], b2[64], b3[64], b4[2];
+  alignas(16) float b1[64];
+  alignas(16) float b2[64];
+  alignas(16) float b3[64];
+  alignas(16) float b4[4];
 };
 
 // cooperative load of the bf16 weights (padded) and fp32 biases into LDS
@@ -131,6 +137,83 @@ __device__ __forceinline__ void mlp_out(const uint16_t* in, const uint16_t* W4, 
   if (r < 2) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) y[(4 * q + e) * 2 + r] = acc[e] + b4[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident forward pass of one wave over its 64 lanes' states.
+//
+// Each layer is computed transposed, H^T = W X^T, on 16-state tiles: the
+// weights are the A operand (rows = output neurons), the previous layer's
+// activations the B operand (k = input neuron, column = state).  The MFMA
+// result D[4 (l / 16) + e][l % 16] (neuron, state) is then exactly the B
+// fragment of the next layer's k-step, so activations never leave the
+// registers.  Lane l contributes its own state's 5 features x and receives
+// (y0, y1) of its own state.  All 64 lanes must call this together.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bf16x4 silu_frag(f32x4 acc, const float* bias) {
+  // bias: the 4 consecutive neurons of this lane's fragment rows
+  const float4 bv = *(const float4*)bias;
+  bf16x4 h;
+  h[0] = (short)f2bf(silu_f(acc[0] + bv.x));
+  h[1] = (short)f2bf(silu_f(acc[1] + bv.y));
+  h[2] = (short)f2bf(silu_f(acc[2] + bv.z));
+  h[3] = (short)f2bf(silu_f(acc[3] + bv.w));
+  return h;
+}
+
+__device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], float& y0, float& y1) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, q = l >> 4;
+  y0 = 0.f;
+  y1 = 0.f;
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    // keep the weight fragments in LDS: re-read them per tile instead of
+    // letting them be hoisted into ~80 live VGPRs across the caller's loop
+    __asm__ volatile("" ::: "memory");
+    // B operand of layer 1: features 4q..4q+3 of state 16 t + r
+    const int src = t * 16 + r;
+    float f[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) f[c] = __shfl(x[c], src, 64);
+    bf16x4 xb;
+    xb[0] = (short)(q == 0 ? f2bf(f[0]) : (q == 1 ? f2bf(f[4]) : 0));
+    xb[1] = (short)(q == 0 ? f2bf(f[1]) : 0);
+    xb[2] = (short)(q == 0 ? f2bf(f[2]) : 0);
+    xb[3] = (short)(q == 0 ? f2bf(f[3]) : 0);
+    bf16x4 h1[4], h2[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma16(ld4(w.W1 + (nt * 16 + r) * kLdIn + 4 * q), xb, acc);
+      h1[nt] = silu_frag(acc, w.b1 + nt * 16 + 4 * q);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        acc = mfma16(ld4(w.W2 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h1[ks], acc);
+      h2[nt] = silu_frag(acc, w.b2 + nt * 16 + 4 * q);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        acc = mfma16(ld4(w.W3 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h2[ks], acc);
+      h1[nt] = silu_frag(acc, w.b3 + nt * 16 + 4 * q);
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) acc = mfma16(ld4(w.W4 + r * kLdH + ks * 16 + 4 * q), h1[ks], acc);
+    // rows 0 and 1 (lanes 0..15, e = 0, 1) hold the two outputs of state 16 t + r
+    const float o0 = __shfl(acc[0], r, 64), o1 = __shfl(acc[1], r, 64);
+    if (q == t) {
+      y0 = o0 + w.b4[0];
+      y1 = o1 + w.b4[1];
+    }
   }
 }
 

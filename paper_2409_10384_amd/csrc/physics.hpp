@@ -11,6 +11,7 @@
 //                       bracketed root by Brent's method, atmosphere rules
 //                       of Sec. III-C
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,6 +32,23 @@ struct Eos {
   double gam, gth;
   double rb[3], K[4], G[4], a[4];
 };
+
+// The EOS type as a compile-time constant inside a kernel: every eos_*
+// branch on e.type folds away, so an ideal-gas kernel carries none of the
+// piecewise-polytrope code (nor its registers).
+template <int ET>
+__device__ __forceinline__ Eos eos_fixed(const Eos& e) {
+  Eos r = e;
+  r.type = ET;
+  return r;
+}
+
+// host side: call f(std::integral_constant<int, type>) for type 0 or 1
+template <class F>
+inline void eos_dispatch(int type, F&& f) {
+  if (type == 0) f(std::integral_constant<int, 0>{});
+  else f(std::integral_constant<int, 1>{});
+}
 
 __device__ __forceinline__ int eos_piece(const Eos& e, double rho) {
   int i = 0;
@@ -460,10 +478,13 @@ __device__ __forceinline__ C2PWork c2p_prepare(const Eos& e, const grmhd_params&
 
 // Root solve, recovery, primitive floors and the failure policy.  With
 // use_br, [blo, bhi] is tried first (learned bracket).
-__device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& p, const M3& m,
-                                              C2PWork& cw, double U[5], const double Bt[3],
-                                              double w[5], bool use_br, double blo, double bhi,
-                                              int& nev, double& mu_out) {
+// Root solve and primitive rules of one prepared cell.  Needs neither the
+// metric nor the field: when the result has a kFloorBits rule set, the
+// caller rebuilds U from w (prim_to_cons) with the metric and field it
+// reloads, so that they need not stay live across the root solve.
+__device__ __forceinline__ uint32_t c2p_lean(const Eos& e, const grmhd_params& p, C2PWork& cw,
+                                             double w[5], bool use_br, double blo, double bhi,
+                                             int& nev, double& mu_out) {
   uint32_t fl = cw.fl;
   const KState& k = cw.k;
   const double* ru = cw.ru;
@@ -471,24 +492,31 @@ __device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& 
   auto fm = [&](double x) { return k_master(e, k, x); };
   nev = 0;
   mu_out = 0.0;
-  bool ok = false, have = false;
-  double mu = 0.0;
+  // Bracket: the given one when f changes sign over it, else (0, 1] cut at
+  // mu_+.  One Brent loop serves both, so that lanes of a wave that fall
+  // back do not run a second, serialised root loop.
+  double lo = 0.0, hi = 1.0, flo = 0.0, fhi = 0.0;
+  bool have = false;
   if (use_br) {
-    const double lo = fmax(blo, 0.0), hi = fmin(bhi, 1.0);
-    if (lo < hi && __builtin_isfinite(lo) && __builtin_isfinite(hi)) {
-      const double flo = fm(lo), fhi = fm(hi);
+    const double l0 = fmax(blo, 0.0), h0 = fmin(bhi, 1.0);
+    if (l0 < h0 && __builtin_isfinite(l0) && __builtin_isfinite(h0)) {
+      flo = fm(l0);
+      fhi = fm(h0);
       nev += 2;
       if (flo <= 0.0 && fhi >= 0.0) {
-        mu = brent_root(fm, lo, hi, flo, fhi, p.c2p_tol, p.c2p_maxit, nev, ok);
+        lo = l0;
+        hi = h0;
         have = true;
       }
     }
     if (!have) fl |= GRMHD_F_BRACKET_FALLBACK;
   }
+  bool valid = true;
   if (!have) {
-    double hi = 1.0;
-    const double flo = fm(0.0);
-    double fhi = fm(hi);
+    lo = 0.0;
+    hi = 1.0;
+    flo = fm(0.0);
+    fhi = fm(hi);
     nev += 2;
     if (fhi < 0.0) {
       // bound from above by the root mu_+ of the auxiliary function
@@ -499,12 +527,11 @@ __device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& 
       fhi = fm(hi);
       nev += 1;
     }
-    if (flo > 0.0 || fhi < 0.0 || !__builtin_isfinite(flo) || !__builtin_isfinite(fhi)) {
-      ok = false;
-    } else {
-      mu = brent_root(fm, 0.0, hi, flo, fhi, p.c2p_tol, p.c2p_maxit, nev, ok);
-    }
+    valid = !(flo > 0.0 || fhi < 0.0 || !__builtin_isfinite(flo) || !__builtin_isfinite(fhi));
   }
+  bool ok = false;
+  double mu = 0.0;
+  if (valid) mu = brent_root(fm, lo, hi, flo, fhi, p.c2p_tol, p.c2p_maxit, nev, ok);
   mu_out = mu;
   bool good = ok && __builtin_isfinite(mu);
   if (good) {
@@ -533,6 +560,14 @@ __device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& 
     atmosphere(e, p, w);
     fl |= GRMHD_F_C2P_FAIL;
   }
+  return fl;
+}
+
+__device__ __forceinline__ uint32_t c2p_solve(const Eos& e, const grmhd_params& p, const M3& m,
+                                              C2PWork& cw, double U[5], const double Bt[3],
+                                              double w[5], bool use_br, double blo, double bhi,
+                                              int& nev, double& mu_out) {
+  const uint32_t fl = c2p_lean(e, p, cw, w, use_br, blo, bhi, nev, mu_out);
   if (fl & kFloorBits) prim_to_cons(e, m, w, Bt, U);
   return fl;
 }

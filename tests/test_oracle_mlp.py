@@ -22,13 +22,17 @@ def test_backward_matches_finite_differences():
 
     def loss_at(ps):
         y, _ = M.forward(ps, x)
-        # fix the second target at the unperturbed first output (no gradient)
+        # fix the second target at the unperturbed first output (no gradient),
+        # and the second output's input at the unperturbed last hidden layer
+        # (its gradient stops at the read-out)
         e0 = y[:, 0] - t
         t1 = np.log(np.abs(y0_fixed - t) + M.LOG_ERR_C)
-        return 0.5 * np.mean(e0 * e0 + (y[:, 1] - t1) ** 2)
+        y1 = h3_fixed @ ps[3][0][1] + ps[3][1][1]
+        return 0.5 * np.mean(e0 * e0 + (y1 - t1) ** 2)
 
     y, cache = M.forward(params, x)
     y0_fixed = y[:, 0].copy()
+    h3_fixed = cache[0][3].copy()
     loss, dy = M.loss_and_grad_out(y, t)
     assert abs(loss - loss_at(params)) < 1e-14
     grads = M.backward(params, cache, dy)
