@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -240,6 +242,157 @@ def refined_section(args, torch, inputs, lib):
     return res
 
 
+def _clone_blocks(blocks):
+    import copy
+    out = []
+    for b in blocks:
+        c = copy.copy(b)
+        c.w = b.w.clone()
+        c.bf = [x.clone() for x in b.bf]
+        c.adm = b.adm.clone()
+        out.append(c)
+    return out
+
+
+def _block_numpy(b):
+    import copy
+    c = copy.copy(b)
+    c.w = b.w.cpu().numpy()
+    c.bf = [x.cpu().numpy() for x in b.bf]
+    c.adm = b.adm.cpu().numpy()
+    return c
+
+
+def c5_section(args, torch, inputs, lib):
+    """End-to-end: the refined star (the ~1500-block list, frozen ghosts) with a
+    seeded 3-piece piecewise polytrope + Gamma_th = 1.75 thermal part, K RK2
+    steps with device dt, plain C2P against the learned bracket in the stage
+    inversion (network trained on prim/cons pairs of the run's own states)"""
+    pp, pK = inputs.pp_eos()
+    st = inputs.calibrate_field(inputs.StarSetup(pp=pp, pp_K=pK))
+    blocks, st = inputs.refined_star_blocks(nblocks=args.refined_blocks, device="cuda", st=st)
+    params_kw = {**STAR_PARAMS, **pp}
+    params = lib.MethodParams(**params_kw)
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    K = args.c5_steps
+    # seeded subset of 16 of the 16^3 blocks for the oracle check on the host
+    rng = np.random.default_rng(inputs.SEED_BASE + 55)
+    small = [i for i, b in enumerate(blocks) if b.nx == 16]
+    subset = sorted(int(i) for i in rng.choice(small, size=min(16, len(small)), replace=False))
+    init_sub = [_block_numpy(blocks[i]) for i in subset]
+    log(f"c5: {len(blocks)} blocks, {ncell} cells, piecewise polytrope Gamma={pp['Gam'][:3]}")
+    plain = lib.DeviceMesh(blocks, params, device="cuda")
+    learned = lib.DeviceMesh(_clone_blocks(blocks), params, device="cuda")
+    net = lib.LearnedC2P(seed=0)
+    # warm every kernel of both paths once on a two-block copy
+    warm = lib.DeviceMesh(_clone_blocks(blocks[:2]), params, device="cuda")
+    wu, wb, wg, ww = warm.c2p_pairs(0)
+    net.fit(wu, wb, wg, params, ww, steps=2)
+    warm.rk2_step(cfl=0.25)
+    warm.rk2_step(cfl=0.25, mlp=net)
+    del warm
+    torch.cuda.synchronize()
+
+    def run(mesh, mlp=None, stats=None, dts_in=None):
+        # device dt every step; with dts_in the stages take that sequence
+        # instead (same work, so that both runs see the same time steps)
+        dts = torch.zeros(K, dtype=torch.float64, device="cuda")
+        m0 = float(mesh.mass().item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lib.timing(True)
+        e0.record()
+        for k in range(K):
+            mesh.compute_dt(0.25)
+            dk = mesh.dt_dev if dts_in is None else dts_in[k:k + 1]
+            mesh.stage(1, dt_dev=dk, mlp=mlp, stats=stats)
+            mesh.ghost_fill(1)
+            mesh.stage(2, dt_dev=dk, mlp=mlp, stats=stats)
+            mesh.ghost_fill(0)
+            dts[k:k + 1].copy_(dk)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = {k: round(v[0] / K, 4) for k, v in lib.timing_read().items()}
+        lib.timing(False)
+        m1 = float(mesh.mass().item())
+        return ms, (m1 - m0) / m0, dts, kt
+
+    train_u = [plain.c2p_pairs(0, stride=2)]
+    ms_p, drift_p, dts_p, kt_p = run(plain)
+    log(f"c5 plain: {K} steps {ms_p:.1f} ms, {ncell * K / (ms_p * 1e-3):.3e} zone-updates/s, "
+        f"mass drift {drift_p:.3e}")
+    train_u.append(plain.c2p_pairs(0, stride=2))
+    u, bt, gam, w = (torch.cat([t[i] for t in train_u], dim=1).contiguous() for i in range(4))
+    t0 = time.perf_counter()
+    losses = net.fit(u, bt, gam, params, w, steps=args.train_steps, log_every=max(1, args.train_steps // 4))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"c5 network trained on {u.shape[1]} pairs of the run's own states in {train_s:.1f} s, "
+        f"losses {['%.3g' % x for x in losses]}")
+    del u, bt, gam, w, train_u
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ms_l, drift_l, _, kt_l = run(learned, mlp=net, stats=stats, dts_in=dts_p)
+    n_s, n_ev, n_fb, n_fail = (int(x) for x in stats.cpu())
+    log(f"c5 kernels plain (ms/step) {kt_p}")
+    log(f"c5 kernels learned (ms/step) {kt_l}")
+    log(f"c5 learned: {K} steps {ms_l:.1f} ms, {ncell * K / (ms_l * 1e-3):.3e} zone-updates/s, "
+        f"mass drift {drift_l:.3e}, fallback {n_fb / max(n_s, 1):.4f}, evals/solve {n_ev / max(n_s, 1):.2f}")
+    res = {"blocks": len(blocks), "cells": ncell, "steps": K, "eos": {k: pp[k] for k in ("Gam", "rho_b", "K0", "gamma_th")},
+           "plain": {"ms": ms_p, "zone_updates_per_s": ncell * K / (ms_p * 1e-3), "mass_drift": drift_p,
+                     "kernel_ms_per_step": kt_p},
+           "learned": {"ms": ms_l, "zone_updates_per_s": ncell * K / (ms_l * 1e-3), "mass_drift": drift_l,
+                       "fallback_rate": n_fb / max(n_s, 1), "evals_per_solve": n_ev / max(n_s, 1),
+                       "failures": n_fail, "solves": n_s, "kernel_ms_per_step": kt_l},
+           "learned_speedup": ms_p / ms_l, "train_s": train_s,
+           "note": "ghosts frozen at the analytic data, so mass also flows through block faces"}
+    # the oracle check runs on the host in the cpu leg, from these
+    sub = {"subset": subset, "init": init_sub, "dts": dts_p.cpu().numpy(),
+           "gpu_plain": [(plain.u0[i].cpu().numpy(), plain.w0[i].cpu().numpy()) for i in subset],
+           "gpu_learned": [(learned.u0[i].cpu().numpy(), learned.w0[i].cpu().numpy()) for i in subset],
+           "params": params_kw}
+    del plain, learned
+    torch.cuda.synchronize()
+    return res, sub
+
+
+def c5_oracle_check(sub):
+    """The FP64 oracle (plain C2P) on the seeded 16-block subset with the GPU
+    run's dt sequence; max deviation of the GPU's final state from it."""
+    import oracle as O
+    out = {"blocks": sub["subset"]}
+    m = O.Mesh([_copy_np(b) for b in sub["init"]], O.Params(**sub["params"]))
+    t0 = time.perf_counter()
+    for dt in sub["dts"]:
+        m.rk2_step(float(dt))
+    el = time.perf_counter() - t0
+    out["oracle_s"] = el
+    for kind in ("learned", "plain"):
+        worst_all, worst_star = 0.0, 0.0
+        for j, (gu, gw) in enumerate(sub["gpu_" + kind]):
+            ou, ow = m.interior(m.u0[j], j), m.interior(m.w0[j], j)
+            gu_i = m.interior(gu, j)
+            scale = np.max(np.abs(ou[0]))
+            worst_all = max(worst_all, float(np.max(np.abs(gu_i[0] - ou[0])) / scale))
+            star = ow[0] > 1e-6 * 1.28e-3
+            if star.any():
+                worst_star = max(worst_star, float(np.max(np.abs(gu_i[0][star] - ou[0][star]) / ou[0][star])))
+        out[kind] = {"max_dev_D_over_block_max": worst_all, "max_rel_dev_D_star": worst_star}
+        log(f"c5 oracle check ({kind}): max |dD|/max D {worst_all:.2e}, star rel {worst_star:.2e}")
+    cells = sum(b.nx * b.ny * b.nz for b in sub["init"])
+    out["oracle_zone_updates_per_s"] = cells * len(sub["dts"]) / el
+    log(f"c5 oracle: {len(sub['dts'])} steps of {len(sub['init'])} blocks in {el:.1f} s")
+    return out
+
+
+def _copy_np(b):
+    import copy
+    c = copy.copy(b)
+    c.w = np.array(b.w)
+    c.bf = [np.array(x) for x in b.bf]
+    c.adm = np.array(b.adm)
+    return c
+
+
 def c2p_section(args, torch, inputs, lib):
     """C2P solves/s on 2^k random states, plain vs learned bracket"""
     n = 1 << args.c2p_log2
@@ -324,6 +477,9 @@ def main():
     ap.add_argument("--refined-blocks", type=int, default=1500)
     ap.add_argument("--refined-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the end-to-end refined star section")
+    ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")
+    ap.add_argument("--c5-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB plain copy first (for counter scaling)")
     args = ap.parse_args()
@@ -352,6 +508,12 @@ def main():
     if args.refined_only:
         print(json.dumps({"refined": refined_section(args, torch, inputs, lib)}), flush=True)
         return
+    if args.c5_only:
+        res, sub = c5_section(args, torch, inputs, lib)
+        if not args.no_cpu_baseline:
+            res["oracle_check"] = c5_oracle_check(sub)
+        print(json.dumps({"end_to_end": res}), flush=True)
+        return
     star = star_section(args, torch, inputs, lib)
     out = {
         "metric": "zone-updates/s per GPU (GRMHD SSP-RK2 step, plain C2P)",
@@ -378,9 +540,14 @@ def main():
         out["refined"] = refined_section(args, torch, inputs, lib)
     if not args.no_c2p:
         out["c2p"] = c2p_section(args, torch, inputs, lib)
+    c5_sub = None
+    if not args.no_c5:
+        out["end_to_end"], c5_sub = c5_section(args, torch, inputs, lib)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(star["st"], args.blocks_per_side, args.block, STAR_PARAMS)
+        if c5_sub is not None:
+            out["end_to_end"]["oracle_check"] = c5_oracle_check(c5_sub)
     print(json.dumps(out), flush=True)
 
 

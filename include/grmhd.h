@@ -225,6 +225,22 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
               uint16_t *flags, const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
               double *mu_out, int32_t *nev_out, void *stream);
 
+/* grmhd_stage with the stage's final inversion (step a8) started from the
+   learned bracket (mlp != NULL; NULL = grmhd_stage).  Same outputs and
+   atmosphere rules; cells whose bracket holds no sign change fall back to the
+   full bracket and carry bit 8 in flags.  The FOFC trial inversion stays
+   plain.  stats (device, may be NULL) accumulates solves, master-function
+   evaluations, fallbacks and failures of the final inversion.  mlp's
+   bracket_ws is not used. */
+int grmhd_stage_learned(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                        const grmhd_params *p, const double *dt_d, double dt, double a0,
+                        double a1, double b, const c2p_mlp *mlp, c2p_stats *stats,
+                        void *stream);
+/* grmhd_stage_c2p with the learned bracket (mlp required). */
+int grmhd_stage_c2p_learned(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                            const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
+                            void *stream);
+
 /* Learned-bracket training support (device memory throughout).
    c2p_mlp_features: standardised features [5][n] (fp32) of the conserved
    states u after the conserved-floor rules and, when w_true != NULL, the
@@ -238,7 +254,9 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
    0.999, eps 1e-8, bias correction for `step`) on theta with moments adam_m,
    adam_v, and theta_bf16 refreshed.  grad_out (C2P_MLP_NPARAM), loss_part
    (nbatch/64) and loss_out (1) may be NULL.  Loss per sample:
-   0.5 (y0 - t)^2 + 0.5 (y1 - log(|y0 - t| + 1e-4))^2, batch mean. */
+   0.5 (y0 - t)^2 + 0.5 (y1 - log(|y0 - t| + 1e-4))^2, batch mean; the
+   second term trains only the read-out W4[1], b4[1] (its gradient does not
+   enter the hidden layers). */
 int c2p_mlp_features(int64_t n, double *const u[5], double *const bt[3], double *const gam[6],
                      double *const w_true[5], const grmhd_params *p, const float mean[5],
                      const float scale[5], float *feats, float *target, void *stream);
@@ -259,7 +277,8 @@ const char *grmhd_version(void);
    launch count of a family since timing was enabled.  Families: 0/1/2
    face fluxes x/y/z, 3 FOFC flags, 4 FOFC refluxing, 5 CT, 6 update with
    sources, 7 stage C2P, 8 ghost fill, 9 dt, 10 cell-centred field,
-   11 c2p_batch plain, 12 c2p_batch learned, 13 MLP training. */
+   11 c2p_batch plain, 12 c2p_batch learned, 13 MLP training, 14 MLP
+   bracket kernel, 15 stage C2P with the learned bracket. */
 int grmhd_timing(int32_t on);
 /* Workgroup size (64..512, a multiple of 64) of a kernel family of the stage
    (families as for grmhd_timing, 0..10); default 256.  Set by the

@@ -253,9 +253,11 @@ class Mesh:
             self.u0.append(np.ascontiguousarray(u))
             self.w0.append(w)
             self.b0.append(bf)
-            self.u1.append(np.zeros_like(u))
-            self.w1.append(np.zeros_like(w))
-            self.b1.append([np.zeros_like(x) for x in bf])
+            # set B starts as a copy of set A, so that frozen ghosts (bc == 0)
+            # hold the initial data in both sets (stages write interiors only)
+            self.u1.append(np.ascontiguousarray(u).copy())
+            self.w1.append(w.copy())
+            self.b1.append([x.copy() for x in bf])
             self.flags.append(np.zeros(shp, dtype=np.uint16))
         self.adm = [np.ascontiguousarray(b.adm) for b in blocks]
 

@@ -1070,6 +1070,12 @@ void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* co
   });
 }
 Eos make_eos_host(const grmhd_params& p) { return make_eos(p); }
+unsigned stage_grid(const grmhd_block* h, int nblk, int cls, int threads) {
+  return grid_cls(h, nblk, cls, threads).x;
+}
+int launch_stage_c2p_learned(const grmhd_block* h, const grmhd_block* d, int nblk,
+                             const grmhd_params& p, const c2p_mlp* mlp, c2p_stats* stats,
+                             hipStream_t s);
 int check_params_host(const grmhd_params* p) { return check_params(p); }
 }  // namespace gk
 
@@ -1157,16 +1163,39 @@ int grmhd_stage_c2p(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t 
 int grmhd_stage(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
                 const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
                 double b, void* stream) {
+  return grmhd_stage_learned(blk_h, blk_d, nblk, p, dt_d, dt, a0, a1, b, nullptr, nullptr, stream);
+}
+
+int grmhd_stage_learned(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                        const grmhd_params* p, const double* dt_d, double dt, double a0,
+                        double a1, double b, const c2p_mlp* mlp, c2p_stats* stats, void* stream) {
   int r = check_params(p);
   if (r) return r;
   if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  if (mlp && (!mlp->w_bf16 || !mlp->w_f32)) return GRMHD_EINVAL;
   const Eos e = make_eos(*p);
   hipStream_t s = (hipStream_t)stream;
   run_fluxes(blk_h, blk_d, nblk, *p, e, s);
   run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s);
   run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s);
   run_update(blk_h, blk_d, nblk, e, dt_d, dt, a0, a1, b, s);
-  run_c2p(blk_h, blk_d, nblk, *p, e, s);
+  if (mlp) {
+    if ((r = launch_stage_c2p_learned(blk_h, blk_d, nblk, *p, mlp, stats, s))) return r;
+  } else {
+    run_c2p(blk_h, blk_d, nblk, *p, e, s);
+  }
+  return last_err();
+}
+
+int grmhd_stage_c2p_learned(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                            const grmhd_params* p, const c2p_mlp* mlp, c2p_stats* stats,
+                            void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  if (!mlp) return GRMHD_EINVAL;
+  if ((r = launch_stage_c2p_learned(blk_h, blk_d, nblk, *p, mlp, stats, (hipStream_t)stream)))
+    return r;
   return last_err();
 }
 

@@ -10,6 +10,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include "blocks.hpp"
 #include "grmhd.h"
 #include "mlp.hpp"
 #include "physics.hpp"
@@ -19,6 +20,7 @@ using namespace gk;
 
 namespace gk {
 Eos make_eos_host(const grmhd_params& p);
+unsigned stage_grid(const grmhd_block* h, int nblk, int cls, int threads);
 int check_params_host(const grmhd_params* p);
 void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* const* gam, double* const* w,
                       uint16_t* flags, const grmhd_params& p, const double* blo, const double* bhi,
@@ -45,7 +47,7 @@ __device__ __forceinline__ void features(const KState& k, const Feat& f, float x
   const float den = (float)(k.r2 * k.b2);
   float raw[5];
   raw[0] = ((float)ex + __log2f((float)man)) * kLog10_2;
-  raw[1] = __log2f((float)(1.0 + k.q)) * kLog10_2;
+  raw[1] = log1pf((float)k.q) * 0.43429448190325182f;   // log10(1 + q)
   raw[2] = __builtin_sqrtf((float)k.r2) * iq1;
   raw[3] = (float)k.b2 * iq1;
   raw[4] = den > 1e-30f ? fminf((float)(k.s * k.s) * __builtin_amdgcn_rcpf(den), 1.0f) : 0.0f;
@@ -210,6 +212,98 @@ __global__ __launch_bounds__(kT) void k_mlp_bracket(int64_t n, P5 u, P3 bt, P6 g
       if (!done) bracket_of(y0, y1, width_k, width_min, lo, hi);
       br[t] = lo;
       br[n + t] = hi;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a8 with the learned bracket: the stage's inversion over the interior cells
+// of every block (flattened wave layout).  Lanes without a cell still run the
+// network with their wave; the root solve, the atmosphere rules and the
+// flags are those of the plain stage inversion.
+// ---------------------------------------------------------------------------
+template <int ET>
+__global__ __launch_bounds__(kT) void k_stage_c2p_learned(const grmhd_block* __restrict__ blks,
+                                                          Eos e_in, grmhd_params p,
+                                                          const uint16_t* wh, const float* wf,
+                                                          Feat ft, float width_k, float width_min,
+                                                          c2p_stats* stats) {
+  const Eos e = eos_fixed<ET>(e_in);
+  __shared__ MlpLds s;
+  mlp_load(s, wh, wf);
+  __syncthreads();
+  int bi = 0;
+  int64_t t = 0;
+  const bool live = locate(blks, S_INTERIOR, bi, t);
+  const grmhd_block& b = blks[bi];
+  const Geo q = geo_of(b);
+  int i = 0, j = 0, k = 0;
+  int64_t c = 0;
+  double w[5];
+  C2PWork cw;
+  cw.done = true;
+  cw.fl = 0;
+  float x[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (live) {
+    interior_box(q).at(t, i, j, k);
+    c = cell(q, i, j, k);
+    M3 m;
+    cell_metric(b, c, m);
+    double U[5], Bt[3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
+    cell_bt(q, b.bo, i, j, k, Bt);
+    cw = c2p_prepare(e, p, m, U, Bt, w);
+    if (cw.done) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+    } else {
+      features(cw.k, ft, x);
+    }
+  }
+  float y0, y1;
+  mlp_wave(s, x, y0, y1);
+  unsigned long long c_n = 0, c_ev = 0, c_fb = 0, c_fail = 0;
+  if (live) {
+    uint32_t r = cw.fl;
+    int nev = 0;
+    if (!cw.done) {
+      double lo, hi, mu;
+      bracket_of(y0, y1, width_k, width_min, lo, hi);
+      r = c2p_lean(e, p, cw, w, true, lo, hi, nev, mu);
+      if (r & kFloorBits) {
+        // U from the final primitives, metric and field loaded again
+        __asm__ volatile("" ::: "memory");
+        M3 m;
+        cell_metric(b, c, m);
+        double U[5], Bt[3];
+        cell_bt(q, b.bo, i, j, k, Bt);
+        prim_to_cons(e, m, w, Bt, U);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) b.wo[v][c] = w[v];
+    b.flags[c] = (uint16_t)(b.flags[c] | r);
+    c_n = 1;
+    c_ev = (unsigned long long)nev;
+    c_fb = (r & GRMHD_F_BRACKET_FALLBACK) ? 1 : 0;
+    c_fail = (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
+  }
+  if (stats) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      c_n += __shfl_xor(c_n, o, 64);
+      c_ev += __shfl_xor(c_ev, o, 64);
+      c_fb += __shfl_xor(c_fb, o, 64);
+      c_fail += __shfl_xor(c_fail, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && c_n) {
+      atomicAdd(&stats->solves, c_n);
+      atomicAdd(&stats->evaluations, c_ev);
+      if (c_fb) atomicAdd(&stats->fallbacks, c_fb);
+      if (c_fail) atomicAdd(&stats->failures, c_fail);
     }
   }
 }
@@ -494,6 +588,24 @@ unsigned persistent_grid(int64_t n) {
 }
 
 }  // namespace
+
+namespace gk {
+// the stage inversion with the learned bracket over every block's interior
+int launch_stage_c2p_learned(const grmhd_block* h, const grmhd_block* d, int nblk,
+                             const grmhd_params& p, const c2p_mlp* mlp, c2p_stats* stats,
+                             hipStream_t s) {
+  if (!mlp || !mlp->w_bf16 || !mlp->w_f32) return GRMHD_EINVAL;
+  Feat ft;
+  for (int c = 0; c < 5; ++c) { ft.mean[c] = mlp->feat_mean[c]; ft.scale[c] = mlp->feat_scale[c]; }
+  const Eos e = make_eos_host(p);
+  TIMED(T_STAGE_C2P_LEARNED, s);
+  eos_dispatch(e.type, [&](auto et) {
+    k_stage_c2p_learned<decltype(et)::value><<<stage_grid(h, nblk, S_INTERIOR, kT), kT, 0, s>>>(
+        d, e, p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k, mlp->width_min, stats);
+  });
+  return learned_err();
+}
+}  // namespace gk
 
 extern "C" {
 

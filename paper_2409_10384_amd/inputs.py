@@ -53,6 +53,38 @@ def _maxs(a, s):
         return np.maximum(a, s)
     return a.clamp(min=s)
 
+
+def _where(c, a, b):
+    if isinstance(c, np.ndarray) or np.isscalar(c):
+        return np.where(c, a, b)
+    import torch
+    return torch.where(c, a, b)
+
+
+def pp_cold_pressure(rho, pp, K):
+    """cold pressure K_i rho^Gamma_i of the 3-piece polytrope of pp_eos"""
+    G, rb = pp["Gam"], pp["rho_b"]
+    return _where(rho < rb[0], K[0] * rho ** G[0],
+                  _where(rho < rb[1], K[1] * rho ** G[1], K[2] * rho ** G[2]))
+
+
+def pp_eos(seed_offset=5, rho_c=1.28e-3, K_ref=100.0, gamma_th=1.75):
+    """Seeded 3-piece cold piecewise polytrope with a thermal part (the
+    end-to-end star's gas): adiabatic indices Gamma_i ~ U[1.8, 3.2], dividing
+    densities rho_c * {0.05, 0.3}, and K of the lowest piece chosen so that
+    the cold pressure at rho_c is K_ref rho_c^2 with P continuous at the
+    dividing densities.  Returns the EOS fields of the method parameters
+    (eos, npieces, rho_b, K0, Gam, gamma_th) and the per-piece K."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    G = rng.uniform(1.8, 3.2, size=3)
+    rb = (0.05 * rho_c, 0.3 * rho_c)
+    K2 = K_ref * rho_c ** 2 / rho_c ** G[2]
+    K1 = K2 * rb[1] ** G[2] / rb[1] ** G[1]
+    K0 = K1 * rb[0] ** G[1] / rb[0] ** G[0]
+    return dict(eos=1, npieces=3, rho_b=(rb[0], rb[1], 0.0), K0=float(K0),
+                Gam=(float(G[0]), float(G[1]), float(G[2]), float(G[2])),
+                gamma_th=gamma_th), (float(K0), float(K1), float(K2))
+
 # neighbour table order: (ox+1) + 3 (oy+1) + 9 (oz+1)
 def nbr_index(ox: int, oy: int, oz: int) -> int:
     return (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)
@@ -217,16 +249,23 @@ class StarSetup:
     box: float = 12.0
     pcut: float = 0.04
     A_b: float = 0.0              # set by calibrate_field
+    pp: dict | None = None        # piecewise-polytrope gas (pp_eos); None: P = K rho^Gamma
+    pp_K: tuple = ()
 
     def rho(self, r):
         return _maxs(self.rho_c * (1.0 - (r / self.radius) ** 2), self.rho_atm)
 
     def press(self, r):
         rho = self.rho(r)
-        return _maximum(self.K * rho ** self.Gamma, rho * self.T_atm)
+        if self.pp is None:
+            return _maximum(self.K * rho ** self.Gamma, rho * self.T_atm)
+        # cold star: P_cold(rho) plus the atmosphere temperature everywhere
+        return pp_cold_pressure(rho, self.pp, self.pp_K) + rho * self.T_atm
 
     def p_max(self):
-        return self.K * self.rho_c ** self.Gamma
+        if self.pp is None:
+            return self.K * self.rho_c ** self.Gamma
+        return float(self.press(np.array([0.0]))[0])
 
     def potential_scale(self, r):
         return _maxs(self.press(r) - self.pcut * self.p_max(), 0.0)
@@ -403,7 +442,7 @@ def refined_star_blocks(nblocks=1500, nlevels=6, sizes=(16, 24, 32), ng=3, seed_
 # conservative-to-primitive test states
 # ---------------------------------------------------------------------------
 def c2p_states(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps=(-6.0, 1.0),
-               W_range=(1.0, 10.0), log_bsq_rho=(-4.0, 1.0), metric_dev=0.1):
+               W_range=(1.0, 10.0), log_bsq_rho=(-4.0, 1.0), metric_dev=0.1, pp=None, pp_K=None):
     """n primitive states with their densitized field and 3-metric.
 
     log10 rho ~ U[log_rho]; log10 eps ~ U[log_eps]; W ~ U[W_range];
@@ -411,7 +450,9 @@ def c2p_states(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps
     the field direction n is isotropic, |B| set from b^2 = B^2/W^2 + (B.v)^2;
     gamma = Q diag(lambda) Q^T with lambda ~ U[1-dev, 1+dev], Q a random
     rotation.  The ideal-gas pressure P = (gamma-1) rho eps specifies the
-    state.  Returns dict with w (5,n), bt (3,n) densitized, gam (6,n)."""
+    state; with a piecewise polytrope (pp, pp_K from pp_eos) the drawn eps is
+    the thermal part: P = P_cold(rho) + (gamma_th - 1) rho eps.  Returns dict
+    with w (5,n), bt (3,n) densitized, gam (6,n)."""
     rng = np.random.default_rng(SEED_BASE + seed_offset)
     rho = 10.0 ** rng.uniform(*log_rho, size=n)
     eps = 10.0 ** rng.uniform(*log_eps, size=n)
@@ -440,7 +481,10 @@ def c2p_states(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps
     Bmag = np.sqrt(bsq / (1.0 / (W * W) + nv * nv))
     B = nb * Bmag[:, None]
     sqrtg = np.sqrt(np.linalg.det(G))
-    P = (gamma - 1.0) * rho * eps
+    if pp is None:
+        P = (gamma - 1.0) * rho * eps
+    else:
+        P = pp_cold_pressure(rho, pp, pp_K) + (pp["gamma_th"] - 1.0) * rho * eps
     w = np.stack([rho, W * v[:, 0], W * v[:, 1], W * v[:, 2], P])
     bt = (B * sqrtg[:, None]).T
     return {"w": np.ascontiguousarray(w), "bt": np.ascontiguousarray(bt),

@@ -77,6 +77,8 @@ def load():
         getattr(L, name).argtypes = stage
     L.grmhd_fluxes.argtypes = blk + [C.c_void_p, C.c_void_p]
     L.grmhd_stage_c2p.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_stage_learned.argtypes = stage[:-1] + [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.grmhd_stage_c2p_learned.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.grmhd_prim2con_blocks.argtypes = blk + [C.c_void_p, C.c_void_p]
     L.grmhd_ghost_fill.argtypes = blk + [C.c_int32, C.c_void_p]
     L.grmhd_dt.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -97,6 +99,11 @@ def load():
                                      vp, vp, vp]
     _lib = L
     return L
+
+
+def _nullctx():
+    import contextlib
+    return contextlib.nullcontext()
 
 
 def check(rc, what):
@@ -157,12 +164,13 @@ def _ptr_array(ts):
 # measurement helpers
 # ---------------------------------------------------------------------------
 FAMILIES = ["flux_x", "flux_y", "flux_z", "fofc_flags", "fofc_fix", "ct", "update", "stage_c2p",
-            "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train", "mlp_bracket"]
+            "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train", "mlp_bracket",
+            "stage_c2p_learned"]
 KERNEL_OF_FAMILY = {"flux_x": "k_flux<0>", "flux_y": "k_flux<1>", "flux_z": "k_flux<2>",
                     "fofc_flags": "k_fofc_flags", "update": "k_update", "stage_c2p": "k_stage_c2p",
                     "dt": "k_dt", "bcc": "k_bcc", "c2p_batch": "k_c2p_batch",
                     "c2p_learned": "k_c2p_learned", "mlp_train": "k_mlp_train",
-                    "mlp_bracket": "k_mlp_bracket"}
+                    "mlp_bracket": "k_mlp_bracket", "stage_c2p_learned": "k_stage_c2p_learned"}
 
 
 def timing(on: bool):
@@ -274,6 +282,14 @@ class DeviceMesh:
         # conserved state from the primitives (Eq. 7) on the device, all cells
         check(L.grmhd_prim2con_blocks(*self._args("fillA"), C.byref(params.c()), self.sp()),
               "grmhd_prim2con_blocks")
+        # set B starts as a copy of set A: frozen ghosts (bc == 0) then hold the
+        # initial data in both sets (the stages write interiors only)
+        with torch.cuda.stream(self.stream) if self.stream is not None else _nullctx():
+            for ib in range(len(blocks)):
+                self.u1[ib].copy_(self.u0[ib])
+                self.w1[ib].copy_(self.w0[ib])
+                for d in range(3):
+                    self.b1[ib][d].copy_(self.b0[ib][d])
         self.red = torch.zeros(1, **f64)
         self.dt_dev = torch.zeros(1, **f64)
         self.mass_part = torch.zeros(len(blocks), **f64)
@@ -328,13 +344,23 @@ class DeviceMesh:
         return stream_ptr(self.stream)
 
     # --- steps --------------------------------------------------------------
-    def stage(self, stage, dt=None, dt_dev=None):
+    def stage(self, stage, dt=None, dt_dev=None, mlp=None, stats=None):
+        """One stage; mlp (a LearnedC2P) starts the final inversion from the
+        learned bracket, stats (a 4-element int64 device tensor) accumulates
+        its solves, evaluations, fallbacks and failures."""
         L = load()
         a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
         key = "s1" if stage == 1 else "s2"
         dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
-        rc = L.grmhd_stage(*self._args(key), C.byref(self.params.c()), dptr,
-                           float(dt) if dt is not None else 0.0, a0, a1, b, self.sp())
+        dval = float(dt) if dt is not None else 0.0
+        if mlp is None:
+            rc = L.grmhd_stage(*self._args(key), C.byref(self.params.c()), dptr, dval, a0, a1, b,
+                               self.sp())
+        else:
+            self._mlp_keep = mlp.c()
+            sptr = C.c_void_p(stats.data_ptr()) if stats is not None else None
+            rc = L.grmhd_stage_learned(*self._args(key), C.byref(self.params.c()), dptr, dval, a0,
+                                       a1, b, C.byref(self._mlp_keep), sptr, self.sp())
         check(rc, "grmhd_stage")
 
     def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
@@ -349,17 +375,18 @@ class DeviceMesh:
         check(rc, "grmhd_dt")
         return self.dt_dev
 
-    def rk2_step(self, dt=None, cfl=0.25):
-        """One SSP-RK2 step; dt from the device CFL reduction when dt is None."""
+    def rk2_step(self, dt=None, cfl=0.25, mlp=None, stats=None):
+        """One SSP-RK2 step; dt from the device CFL reduction when dt is None;
+        mlp/stats as for stage()."""
         if dt is None:
             self.compute_dt(cfl)
-            self.stage(1, dt_dev=self.dt_dev)
+            self.stage(1, dt_dev=self.dt_dev, mlp=mlp, stats=stats)
             self.ghost_fill(1)
-            self.stage(2, dt_dev=self.dt_dev)
+            self.stage(2, dt_dev=self.dt_dev, mlp=mlp, stats=stats)
         else:
-            self.stage(1, dt=dt)
+            self.stage(1, dt=dt, mlp=mlp, stats=stats)
             self.ghost_fill(1)
-            self.stage(2, dt=dt)
+            self.stage(2, dt=dt, mlp=mlp, stats=stats)
         self.ghost_fill(0)
 
     def rk2_step_per_block(self, dt=None, cfl=0.25):
@@ -429,6 +456,29 @@ class DeviceMesh:
         off = flux_offset(b.nx, b.ny, b.nz, b.ng, d, c)
         n = shape[0] * shape[1] * shape[2]
         return self.scratch[ib][off:off + n].view(shape)
+
+    def c2p_pairs(self, which=0, stride=1):
+        """Conserved/primitive pairs of the interior cells of every block (the
+        states this mesh holds), flattened: u (5, n), densitized cell-centred
+        field bt (3, n), gamma_ij (6, n), w (5, n).  stride > 1 keeps every
+        stride-th cell along x (to subsample)."""
+        U = self.u0 if which == 0 else self.u1
+        W = self.w0 if which == 0 else self.w1
+        Bf = self.b0 if which == 0 else self.b1
+        us, bts, gs, ws = [], [], [], []
+        for ib, b in enumerate(self.blocks):
+            g = b.ng
+            sl = (slice(g, g + b.nz), slice(g, g + b.ny), slice(g, g + b.nx, stride))
+            us.append(U[ib][(slice(None),) + sl].reshape(5, -1))
+            ws.append(W[ib][(slice(None),) + sl].reshape(5, -1))
+            gs.append(self.adm[ib][(slice(4, 10),) + sl].reshape(6, -1))
+            fx, fy, fz = Bf[ib]
+            bx = 0.5 * (fx[:, :, :-1] + fx[:, :, 1:])
+            by = 0.5 * (fy[:, :-1, :] + fy[:, 1:, :])
+            bz = 0.5 * (fz[:-1, :, :] + fz[1:, :, :])
+            bts.append(torch.stack([bx[sl], by[sl], bz[sl]]).reshape(3, -1))
+        cat = lambda xs: torch.cat(xs, dim=1).contiguous()
+        return cat(us), cat(bts), cat(gs), cat(ws)
 
     def interior(self, t, ib):
         b = self.blocks[ib]
@@ -503,6 +553,31 @@ class LearnedC2P:
         self.mean = [float(x) for x in raw_feats.double().mean(dim=1).cpu()]
         sd = raw_feats.double().std(dim=1).cpu()
         self.scale = [float(1.0 / max(x, 1e-12)) for x in sd]
+
+    def fit(self, u, bt, gam, params: MethodParams, w_true, steps=20000, batch=4096, lr=2e-3,
+            seed=0, log_every=0, log=None):
+        """Standardise on the raw features of (u, bt, gam), then train on the
+        targets of w_true for `steps` Adam steps of `batch` samples with a
+        cosine-decaying learning rate (the training kernels of this library).
+        Returns the loss of every log_every-th step."""
+        import math
+        raw, _ = self.features(u, bt, gam, params, standardise=False)
+        self.fit_standardisation(raw)
+        feats, target = self.features(u, bt, gam, params, w_true=w_true)
+        keep = torch.isfinite(target) & (target.abs() < 40.0)
+        if not bool(keep.all()):
+            feats, target = feats[:, keep].contiguous(), target[keep].contiguous()
+        gen = torch.Generator(device=feats.device).manual_seed(seed)
+        losses = []
+        for it in range(steps):
+            idx = torch.randint(0, feats.shape[1], (batch,), device=feats.device, generator=gen)
+            rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps)) + 1e-5
+            loss, _ = self.train_step(feats[:, idx].contiguous(), target[idx].contiguous(), lr=rate)
+            if log_every and it % log_every == 0:
+                losses.append(float(loss.item()))
+                if log:
+                    log(f"  train step {it}: loss {losses[-1]:.4g}")
+        return losses
 
     def forward(self, feats, stream=None):
         n = feats.shape[1]

@@ -156,3 +156,77 @@ def test_learned_c2p_beats_plain_at_equal_error(G):
     assert n_l < n_p
     st_l = learned["stats"].cpu().numpy()
     assert st_l[0] == u.shape[1] and st_l[3] == 0
+
+
+def test_features_match_the_oracle_definition(G):
+    """fp32 features of the GPU against the oracle's FP64 definition on the
+    invariants of the same conserved states (no floor rule fires here)."""
+    say("learned: features of 65536 states against the oracle definition")
+    p = G.MethodParams(**C4P)
+    st, w, bt, gam, u = _c4_device(G, 1 << 16, 302)
+    net = G.LearnedC2P(seed=0)
+    raw, _ = net.features(u, bt, gam, p, standardise=False)
+    raw = raw.double().cpu().numpy()
+    U = u.cpu().numpy()
+    g = st["gam"]
+    Gm = np.array([[g[0], g[1], g[2]], [g[1], g[3], g[4]], [g[2], g[4], g[5]]]).transpose(2, 0, 1)
+    sg = np.sqrt(np.linalg.det(Gm))
+    D = U[0] / sg
+    r = (U[1:4] / sg / D).T
+    B = st["bt"] / sg
+    r2 = np.einsum("ni,nij,nj->n", r, np.linalg.inv(Gm), r)
+    b2 = np.einsum("in,nij,jn->n", B, Gm, B) / D
+    s = np.einsum("ni,in->n", r, B) / np.sqrt(D)
+    q = U[4] / sg / D
+    ref = M.features(D, q, r2, b2, s).T
+    for c in range(5):
+        err = np.max(np.abs(raw[c] - ref[c]) / np.maximum(np.abs(ref[c]), 1e-3))
+        say(f"  feature {c}: max rel err {err:.2e}")
+        assert err < 1e-5, (c, err)
+
+
+STAR = dict(gamma=2.0, rho_atm=1.28e-13, T_atm=1.28e-11, f_thr=0.1, M_max=100.0, fofc=1, dmp_M=1.1)
+
+
+def test_learned_stage_matches_plain_stage(G):
+    """Two RK2 steps of the star (2^3 blocks of 16^3, FOFC+DMP) with the
+    learned bracket in the stage inversion against the plain stage: the same
+    decisions, the same state to the root-solve tolerance, no failures."""
+    import copy
+    say("learned stage: star 2^3 x 16^3, network trained on the mesh's own states")
+    blocks, _ = inputs.star_blocks(n_per_side=2, nb=16)
+    mp = G.MethodParams(**STAR)
+    gp = G.DeviceMesh(copy.deepcopy(blocks), mp)
+    gl = G.DeviceMesh(copy.deepcopy(blocks), mp)
+    net = G.LearnedC2P(seed=0)
+    u, bt, gam, w = gp.c2p_pairs(0)
+    net.fit(u, bt, gam, mp, w, steps=2000)
+    dt = float(gp.compute_dt(0.25).item())
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        gp.rk2_step(dt=dt)
+        gl.rk2_step(dt=dt, mlp=net, stats=stats)
+    torch.cuda.synchronize()
+    n_s, n_ev, n_fb, n_fail = [int(x) for x in stats.cpu()]
+    say(f"  solves {n_s}, evaluations/solve {n_ev / max(n_s, 1):.2f}, fallbacks {n_fb}, failures {n_fail}")
+    assert n_s == 4 * sum(b.nx * b.ny * b.nz for b in blocks)
+    assert n_fail == 0
+    for ib in range(len(blocks)):
+        fp = gp.interior(gp.flags[ib], ib).cpu().numpy().astype(np.uint16)
+        fl = gl.interior(gl.flags[ib], ib).cpu().numpy().astype(np.uint16)
+        bad = (fp & ~np.uint16(O.F_BRACKET_FALLBACK)) != (fl & ~np.uint16(O.F_BRACKET_FALLBACK))
+        assert np.mean(bad) < 0.01
+        dil = bad.copy()
+        for ax in range(3):
+            dil = dil | np.roll(dil, 1, axis=ax) | np.roll(dil, -1, axis=ax)
+        rho = gp.interior(gp.w0[ib], ib)[0].cpu().numpy()
+        ok = ~dil & (rho > 1e-8)         # the star (atmosphere velocities are ill-conditioned)
+        for name, a, b in (("U", gl.u0[ib], gp.u0[ib]), ("w", gl.w0[ib], gp.w0[ib])):
+            ga = gl.interior(a, ib).cpu().numpy()
+            pa = gp.interior(b, ib).cpu().numpy()
+            assert np.all(np.isfinite(ga))
+            for c in range(5):
+                scale = np.max(np.abs(pa[c][ok])) if ok.any() else 1.0
+                e = np.max(np.abs(ga[c][ok] - pa[c][ok])) / max(scale, 1e-300) if ok.any() else 0.0
+                assert e < 1e-10, (ib, name, c, e)
+    say("  learned and plain stages agree on the star")
