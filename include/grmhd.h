@@ -110,8 +110,10 @@ int grmhd_blocks_prepare(grmhd_block *blk_h, int32_t nblk);
 /* Doubles of per-block scratch needed by the stage: the 21 face-flux arrays
    (7 components D~, S~_xyz, tau~, F(B~^{t1}), F(B~^{t2}) per direction, t1 =
    (d+1)%3, t2 = (d+2)%3), the cell-centred field B^i = B~_cc/sqrt(gamma)
-   (3 cell arrays), the cell-centre EMF (3 cell arrays) and the corner EMFs
-   (3 arrays of (sx+1)(sy+1)(sz+1)).  Flux d, component c starts at
+   (3 cell arrays), the cell-centre EMF (3 cell arrays), the corner EMFs
+   (3 arrays of (sx+1)(sy+1)(sz+1)), the learned bracket (2 cell arrays) and
+   the FOFC list of flagged cells of [g-1, g+n]^3 (a counter and
+   (nx+2)(ny+2)(nz+2) int32 cell indices).  Flux d, component c starts at
    grmhd_flux_offset(...) doubles into scratch. */
 int64_t grmhd_scratch_doubles(int32_t nx, int32_t ny, int32_t nz, int32_t ng);
 int64_t grmhd_flux_offset(int32_t nx, int32_t ny, int32_t nz, int32_t ng, int32_t d, int32_t c);

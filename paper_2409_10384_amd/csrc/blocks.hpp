@@ -66,8 +66,41 @@ __host__ __device__ __forceinline__ int64_t off_edge(const Geo& q) {
 __host__ __device__ __forceinline__ int64_t off_br(const Geo& q) {
   return off_edge(q) + 3 * n_edges(q);
 }
-__host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
+// FOFC cell list: the flagged cells of [g-1, g+n]^3 (interior cells and the
+// first ghost shell), int32 padded-cell indices after a uint32 counter
+__host__ __device__ __forceinline__ int64_t fofc_cap(const Geo& q) {
+  return (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
+}
+__host__ __device__ __forceinline__ int64_t off_fofc(const Geo& q) {
   return off_br(q) + 2 * n_cells(q);
+}
+__host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
+  return off_fofc(q) + (fofc_cap(q) + 2 + 1) / 2;
+}
+__device__ __forceinline__ unsigned int* fofc_count(const grmhd_block& b, const Geo& q) {
+  return (unsigned int*)(b.scratch + off_fofc(q));
+}
+__device__ __forceinline__ int* fofc_list(const grmhd_block& b, const Geo& q) {
+  return (int*)(b.scratch + off_fofc(q)) + 2;
+}
+
+// Append cell c to the block's FOFC list when `take`; all lanes of the wave
+// belong to one block.  One atomic per wave; entries beyond the capacity are
+// dropped (cannot happen when the counter is cleared every stage).
+__device__ __forceinline__ void fofc_append(const grmhd_block& b, const Geo& q, bool take,
+                                            int64_t c) {
+  const unsigned long long m = __ballot(take);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(fofc_count(b, q), (unsigned int)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (take) {
+    const unsigned int below = (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+    const unsigned int idx = base + below;
+    if ((int64_t)idx < fofc_cap(q)) fofc_list(b, q)[idx] = (int)c;
+  }
 }
 
 // Launch shapes: every kernel runs over one "shape" of items per block,

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_clear_flags(const grmhd_block* 
   const grmhd_block& b = blks[bi];
   const Geo q = geo_of(b);
   if (t < n_cells(q)) b.flags[t] = 0;
+  if (t == 0) *fofc_count(b, q) = 0u;
 }
 
 __device__ __forceinline__ void dmp_range(double mn, double mx, double M, double& lo, double& hi) {
@@ -207,31 +208,64 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* _
   }
   if (r & kFloorBits) fl |= GRMHD_F_FOFC;
   b.flags[c] = (uint16_t)fl;
+  fofc_append(b, q, fl != 0u, c);
 }
 
-template <int D, int ET>
-__global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e_in,
-                                                       grmhd_params p) {
-  const Eos e = eos_fixed<ET>(e_in);
-  int bi;
-  int64_t t;
-  if (!locate(blks, S_XFACE + D, bi, t)) return;
-  const grmhd_block& b = blks[bi];
-  const Geo q = geo_of(b);
-  const Box bx = face_box<D>(q);
-  int i, j, k;
-  bx.at(t, i, j, k);
+// donor-cell refluxing of the faces of one listed (flagged) cell along D:
+// the lower face always, the upper face unless the upper neighbour is listed
+// too (it owns that face as its lower one), so each face is written once
+template <int D>
+__device__ __forceinline__ void fofc_cell_faces(const Eos& e, const grmhd_params& p,
+                                                const grmhd_block& b, const Geo& q, int x[3]) {
+  const int n[3] = {q.nx, q.ny, q.nz};
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
-  const int64_t c = cell(q, i, j, k);
-  const uint32_t fl = (uint32_t)b.flags[c] | (uint32_t)b.flags[c - st];
-  if (!(fl & (GRMHD_F_FOFC | GRMHD_F_DMP))) return;
-  double F[7];
-  face_flux<D>(e, p, b, q, i, j, k, 0, F);
-  const int64_t f = face<D>(q, i, j, k);
   const int64_t nf = n_faces(q, D);
   double* out = b.scratch + off_flux(q, D, 0);
+  double F[7];
+  if (x[D] >= q.g) {
+    face_flux<D>(e, p, b, q, x[0], x[1], x[2], 0, F);
+    const int64_t f = face<D>(q, x[0], x[1], x[2]);
 #pragma unroll
-  for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
+    for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
+  }
+  if (x[D] + 1 <= q.g + n[D]) {
+    const int64_t cu = cell(q, x[0], x[1], x[2]) + st;
+    if (!(b.flags[cu] & (GRMHD_F_FOFC | GRMHD_F_DMP))) {
+      int y[3] = {x[0], x[1], x[2]};
+      y[D] += 1;
+      face_flux<D>(e, p, b, q, y[0], y[1], y[2], 0, F);
+      const int64_t f = face<D>(q, y[0], y[1], y[2]);
+#pragma unroll
+      for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
+    }
+  }
+}
+
+// a4 refluxing: workgroup (block bi, chunk r) of a grid of nblk * chunks
+// walks entries r * blockDim + tid, stride chunks * blockDim, of block bi's
+// list of flagged cells; every face of the extended ranges with a flagged
+// cell on either side gets the donor-cell flux
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __restrict__ blks, Eos e_in,
+                                                       grmhd_params p, int chunks) {
+  const Eos e = eos_fixed<ET>(e_in);
+  const int bi = blockIdx.x / chunks, r = blockIdx.x % chunks;
+  const grmhd_block& b = blks[bi];
+  const Geo q = geo_of(b);
+  const int64_t cnt_raw = (int64_t)*fofc_count(b, q);
+  const int64_t cnt = cnt_raw < fofc_cap(q) ? cnt_raw : fofc_cap(q);
+  const int* list = fofc_list(b, q);
+  for (int64_t ei = (int64_t)r * blockDim.x + threadIdx.x; ei < cnt;
+       ei += (int64_t)chunks * blockDim.x) {
+    const int64_t c = list[ei];
+    int x[3];
+    x[0] = (int)(c % q.sx);
+    x[1] = (int)((c / q.sx) % q.sy);
+    x[2] = (int)(c / ((int64_t)q.sx * q.sy));
+    fofc_cell_faces<0>(e, p, b, q, x);
+    fofc_cell_faces<1>(e, p, b, q, x);
+    fofc_cell_faces<2>(e, p, b, q, x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -577,8 +611,10 @@ __device__ __forceinline__ bool ghost_src(const grmhd_block* blks, int ib, int f
   return true;
 }
 
+// list != 0 (flags exchange of a stage): flagged cells of the first ghost
+// shell [g-1, g+n]^3 are appended to the block's FOFC list
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* __restrict__ blks,
-                                                          int mask) {
+                                                          int mask, int list) {
   int ib;
   int64_t t;
   if (!locate(blks, S_CELLS, ib, t)) return;
@@ -586,6 +622,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* 
   if (b.bc == 0) return;
   const Geo q = geo_of(b);
   int x[3] = {(int)(t % q.sx), (int)((t / q.sx) % q.sy), (int)(t / ((int64_t)q.sx * q.sy))};
+  const bool shell = x[0] >= q.g - 1 && x[0] <= q.g + q.nx && x[1] >= q.g - 1 &&
+                     x[1] <= q.g + q.ny && x[2] >= q.g - 1 && x[2] <= q.g + q.nz;
   int sb;
   if (!ghost_src(blks, ib, -1, x, sb)) return;
   const grmhd_block& s = blks[sb];
@@ -597,7 +635,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* 
   if (mask & 2)
 #pragma unroll
     for (int v = 0; v < 5; ++v) b.us[v][t] = s.us[v][src];
-  if (mask & 8) b.flags[t] = s.flags[src];
+  if (mask & 8) {
+    const uint16_t f = s.flags[src];
+    b.flags[t] = f;
+    if (list) fofc_append(b, q, shell && (f & (GRMHD_F_FOFC | GRMHD_F_DMP)), t);
+  }
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_faces(const grmhd_block* __restrict__ blks,
@@ -996,16 +1038,17 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
       k_fofc_flags<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d, e, p, dt_d, dt, a0, a1, b);
     });
   }
-  {
+  bool exchange = false;
+  for (int i = 0; i < nblk; ++i) exchange = exchange || h[i].bc == 1;
+  if (exchange) {
     TIMED(T_GHOST, s);
-    k_ghost_cells<<<grid_cls(h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8);
+    k_ghost_cells<<<grid_cls(h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8, 1);
   }
   TIMED(T_FOFC_FIX, s);
+  const int chunks = nblk >= 4096 ? 1 : (4096 + nblk - 1) / nblk;
   eos_dispatch(e.type, [&](auto et) {
-    constexpr int ET = decltype(et)::value;
-    k_fofc_fix<0, ET><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
-    k_fofc_fix<1, ET><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
-    k_fofc_fix<2, ET><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FOFC_FIX)), tpb(T_FOFC_FIX), 0, s>>>(d, e, p);
+    k_fofc_fix<decltype(et)::value><<<(unsigned)(nblk * chunks), tpb(T_FOFC_FIX), 0, s>>>(d, e, p,
+                                                                                        chunks);
   });
 }
 
@@ -1203,10 +1246,12 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
                      int32_t mask, void* stream) {
   if (!blk_h || !blk_d || nblk < 1 || (mask & ~15)) return GRMHD_EINVAL;
   if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
+  bool any = false;
   for (int i = 0; i < nblk; ++i) {
     const grmhd_block& b = blk_h[i];
     if (b.ng < 1 || b.nx < 1 || b.ny < 1 || b.nz < 1) return GRMHD_EINVAL;
     if (b.bc != 1) continue;
+    any = true;
     if (((mask & 1) && !b.w[4]) || ((mask & 2) && !b.us[4]) || ((mask & 4) && !b.bs[2]) ||
         ((mask & 8) && !b.flags))
       return GRMHD_EINVAL;
@@ -1219,10 +1264,11 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
       if (b.nx < b.ng || b.ny < b.ng || b.nz < b.ng) return GRMHD_EINVAL;
     }
   }
+  if (!any) return GRMHD_OK;   // every block's ghosts are frozen: nothing to launch
   const Sizes z = max_sizes(blk_h, nblk);
   hipStream_t s = (hipStream_t)stream;
   TIMED(T_GHOST, s);
-  if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11);
+  if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11, 0);
   if (mask & 4) {
     int64_t mf[3] = {0, 0, 0};
     for (int i = 0; i < nblk; ++i)

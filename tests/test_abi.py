@@ -55,10 +55,12 @@ def test_host_side_argument_checks_reject_bad_input():
                          None, 0.0, 0.0, 1.0, 1.0, None) == -3
     assert L.grmhd_scratch_doubles(0, 4, 4, 3) == -1
     assert L.grmhd_flux_offset(8, 8, 8, 3, 3, 0) == -1
-    # scratch layout: 21 face arrays + 6 cell arrays + 3 edge arrays + 2 bracket arrays
+    # scratch layout: 21 face arrays + 6 cell arrays + 3 edge arrays + 2 bracket
+    # arrays + the FOFC cell list ((n+2)^3 int32 after an 8-byte counter)
     n, g = 8, 3
     s = n + 2 * g
-    expect = 7 * 3 * (s + 1) * s * s + 6 * s ** 3 + 3 * (s + 1) ** 3 + 2 * s ** 3
+    expect = 7 * 3 * (s + 1) * s * s + 6 * s ** 3 + 3 * (s + 1) ** 3 + 2 * s ** 3 + \
+        ((n + 2) ** 3 + 3) // 2
     assert L.grmhd_scratch_doubles(n, n, n, g) == expect
 
 
