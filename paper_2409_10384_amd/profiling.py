@@ -18,23 +18,41 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = (1 << 27) * 8
 
-FAMILY_OF_KERNEL = {"k_flux<0>": "flux_x", "k_flux<1>": "flux_y", "k_flux<2>": "flux_z",
-                    "k_fofc_flags": "fofc_flags", "k_update": "update", "k_stage_c2p": "stage_c2p",
-                    "k_dt": "dt", "k_bcc": "bcc", "k_c2p_batch": "c2p_batch",
-                    "k_c2p_learned": "c2p_learned", "k_copy": "copy"}
+# kernel base name -> timing family; for the per-direction kernels the first
+# template argument picks the family
+FAMILY_OF_BASE = {"k_fofc_flags": "fofc_flags", "k_fofc_fix": "fofc_fix", "k_update": "update",
+                  "k_stage_c2p": "stage_c2p", "k_dt": "dt", "k_bcc": "bcc",
+                  "k_c2p_batch": "c2p_batch", "k_c2p_learned": "c2p_learned",
+                  "k_stage_c2p_learned": "stage_c2p_learned", "k_mlp_bracket": "mlp_bracket",
+                  "k_copy": "copy"}
+FLUX_FAMILY = ["flux_x", "flux_y", "flux_z"]
 
 
 def short(name):
-    """kernel name without namespace, return type and argument list"""
-    for k in FAMILY_OF_KERNEL:
-        if ("::" + k + "(") in name or name.startswith(k + "("):
-            return k
-    # 'void (anonymous namespace)::k_emf_edge<1>(...)' -> 'k_emf_edge<1>'
+    """kernel name without namespace, return type and argument list, e.g.
+    'void (anonymous namespace)::k_flux<1, 0>(...)' -> 'k_flux<1, 0>'"""
     head = name.replace("(anonymous namespace)", "anon")
-    head = head.split("(")[0]
-    if "::" in head:
-        head = head[head.rindex("::") + 2:]
-    return head.split(" ")[-1][:80]
+    depth, cut, start = 0, len(head), 0
+    for i, ch in enumerate(head):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif depth == 0 and ch == "(":
+            cut = i
+            break
+        elif depth == 0 and (ch == " " or (ch == ":" and head[i - 1:i] == ":")):
+            start = i + 1        # after a top-level space (return type) or '::'
+    return head[start:cut][:80]
+
+
+def family(kname):
+    """timing family of a short kernel name (None if not a tracked kernel)"""
+    base, _, rest = kname.partition("<")
+    args = [a.strip() for a in rest.rstrip(">").split(",")] if rest else []
+    if base == "k_flux" and args:
+        return FLUX_FAMILY[int(args[0])]
+    return FAMILY_OF_BASE.get(base)
 
 
 def source_hash():
@@ -71,7 +89,7 @@ def traffic(fetch_csv, write_csv, out_json):
     w_scale = COPY_BYTES / (write["k_copy"] * 1024.0)
     kernels = {}
     for k in fetch:
-        fam = FAMILY_OF_KERNEL.get(k)
+        fam = family(k)
         if fam is None or fam == "copy":
             continue
         b = fetch[k] * 1024.0 * f_scale + write.get(k, 0.0) * 1024.0 * w_scale
