@@ -421,7 +421,7 @@ def c2p_section(args, torch, inputs, lib):
     log(f"trained {steps} steps in {train_s:.1f} s, final loss {float(loss.item()):.3g}")
     res = {}
     ws = torch.empty(2 * n, dtype=torch.float64, device="cuda")
-    for kind in ("plain", "learned", "learned_fused"):
+    for kind in ("plain", "learned", "learned_split"):
         times = []
         for rep in range(args.c2p_reps + 1):
             if rep == 1:
@@ -434,8 +434,10 @@ def c2p_section(args, torch, inputs, lib):
             if kind == "plain":
                 out = lib.c2p_batch(u, s["bt"], s["gam"], p, want_mu=True, want_nev=True, stats=True)
             else:
+                # learned: the fused kernel (network + root solve in one pass);
+                # learned_split: bracket kernel, then the plain kernel reading it
                 out = lib.c2p_batch_learned(u, s["bt"], s["gam"], p, net, want_mu=True, want_nev=True,
-                                            stats=True, split=(kind == "learned"), workspace=ws)
+                                            stats=True, split=(kind == "learned_split"), workspace=ws)
             e1.record()
             torch.cuda.synchronize()
             if rep > 0:

@@ -607,10 +607,11 @@ class LearnedC2P:
 
 
 def c2p_batch_learned(u, bt, gam, params: MethodParams, net: LearnedC2P, want_mu=False,
-                      want_nev=False, stats=False, stream=None, split=True, workspace=None):
+                      want_nev=False, stats=False, stream=None, split=False, workspace=None):
     """c2p_batch with the learned bracket (same outputs as c2p_batch).
-    split: the network runs as its own MFMA kernel writing the brackets into a
-    workspace of 2n doubles, then the FP64 root kernel; else one fused kernel."""
+    Default: one fused kernel (network and root solve per wave).  split: the
+    network runs as its own MFMA kernel writing the brackets into a workspace
+    of 2n doubles, then the FP64 root kernel."""
     L = load()
     n = u.shape[1]
     dev = u.device

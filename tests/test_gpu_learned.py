@@ -156,6 +156,10 @@ def test_learned_c2p_beats_plain_at_equal_error(G):
     assert n_l < n_p
     st_l = learned["stats"].cpu().numpy()
     assert st_l[0] == u.shape[1] and st_l[3] == 0
+    # the split path (bracket kernel, then the plain kernel reading it) agrees
+    split = G.c2p_batch_learned(u.clone(), bt, gam, p, net, want_mu=True, stats=True, split=True)
+    assert np.max(np.abs(split["mu"].cpu().numpy() - mus) / mus) < 1e-10
+    assert int(split["stats"][3].item()) == 0
 
 
 def test_features_match_the_oracle_definition(G):
