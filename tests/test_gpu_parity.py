@@ -333,3 +333,32 @@ def _star_parity(G, blocks, params):
                 say(f"    {name}[{c}] max rel err {e:.2e} over {int(ok.sum())} cells")
                 assert e < 1e-10, (ib, name, c, e)
     assert nflag > 0
+
+
+def test_riemann_tube_parity_and_exact_solution(G):
+    """the 1-D relativistic blast wave (B = 0, flat space, 200 cells, t = 0.4)
+    on the GPU: the oracle's dt sequence, density within 1e-9 of the oracle
+    and the exact solution's L1 error of the oracle"""
+    from tests import exact_riemann as X
+    from tests.test_oracle_riemann import PROBLEMS, _tube, GAM
+    say("Riemann tube (blast wave), 200 cells, GPU vs oracle vs exact")
+    L, R = PROBLEMS["blast"]
+    N = 200
+    blk = _tube(L, R, N)
+    p = O.Params(gamma=GAM, rho_atm=1e-12, T_atm=1e-14, f_thr=1.0, recon=2, riemann=1)
+    om, gm = _meshes(G, [blk], p)
+    t, t_end = 0.0, 0.4
+    while t < t_end - 1e-14:
+        dt = min(om.dt(0.25), t_end - t)
+        om.rk2_step(dt)
+        gm.rk2_step(dt=dt)
+        t += dt
+    ro = om.interior(om.w0[0], 0)[0, 0, 0, :]
+    rg = om.interior(host(gm.w0[0]), 0)[0, 0, 0, :]
+    e = np.max(np.abs(rg - ro) / ro)
+    xc = (np.arange(N) + 0.5) / N
+    ex = X.sample(L, R, (xc - 0.5) / t_end)[0]
+    l1o, l1g = np.mean(np.abs(ro - ex)), np.mean(np.abs(rg - ex))
+    say(f"  max rel GPU-oracle {e:.2e}; L1 vs exact: oracle {l1o:.4e}, GPU {l1g:.4e}")
+    assert e < 1e-9
+    assert abs(l1g - l1o) <= 1e-9 * l1o

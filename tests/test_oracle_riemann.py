@@ -1,0 +1,117 @@
+"""Flat-space 1-D Riemann problems (B = 0): the oracle's stage (WENOZ + HLLE,
+SSP-RK2) against the exact special-relativistic solution of Marti & Mueller
+(tests/exact_riemann.py), after the exact solver is itself checked against
+the conservation laws (jump conditions across its shocks) and the simple-wave
+relation of its rarefactions.  Shock-dominated solutions converge at first
+order in the L1 norm (the paper's shock-tube convergence, Sec. IV)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_10384_amd import inputs
+from tests import exact_riemann as X
+
+GAM = 5.0 / 3.0
+PROBLEMS = {
+    # mildly relativistic blast wave: shock at ~0.83 c behind a dense shell
+    "blast": (X.State(10.0, 13.33, 0.0, GAM), X.State(1.0, 1e-6, 0.0, GAM)),
+    # Sod-type tube
+    "sod": (X.State(1.0, 1.0, 0.0, GAM), X.State(0.125, 0.1, 0.0, GAM)),
+}
+
+
+def _cons(s):
+    """D, S, E = tau + D and their x-fluxes of a state (flat space)"""
+    W, h = s.W, s.h
+    D, S, E = s.rho * W, s.rho * h * W * W * s.v, s.rho * h * W * W - s.p
+    return np.array([D, S, E]), np.array([D * s.v, S * s.v + s.p, S])
+
+
+@pytest.mark.parametrize("side", ["L", "R"])
+def test_exact_shocks_satisfy_the_jump_conditions(side):
+    """F_b - V_s U_b = F_a - V_s U_a for D, S, E across every computed shock"""
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        a = X.State(10 ** rng.uniform(-2, 1), 10 ** rng.uniform(-3, 1), rng.uniform(-0.9, 0.9), GAM)
+        pb = a.p * 10 ** rng.uniform(0.05, 3)
+        b, Vs = X.shock(a, pb, side)
+        Ua, Fa = _cons(a)
+        Ub, Fb = _cons(b)
+        scale = np.abs(Fa) + np.abs(Fb) + np.abs(Vs) * (np.abs(Ua) + np.abs(Ub))
+        assert np.all(np.abs((Fb - Vs * Ub) - (Fa - Vs * Ua)) <= 1e-11 * scale)
+        assert abs(Vs) < 1.0 and abs(b.v) < 1.0
+        # the shock moves away from the state it runs into
+        assert (Vs > a.v) if side == "R" else (Vs < a.v)
+
+
+@pytest.mark.parametrize("side", ["L", "R"])
+def test_exact_rarefactions_follow_the_simple_wave(side):
+    """dv/dP = -+ 1 / (rho h c_s W^2) along the isentrope (finite differences)"""
+    rng = np.random.default_rng(8)
+    sgn = -1.0 if side == "L" else 1.0
+    for _ in range(40):
+        a = X.State(10 ** rng.uniform(-2, 1), 10 ** rng.uniform(-3, 1), rng.uniform(-0.8, 0.8), GAM)
+        p = a.p * 10 ** rng.uniform(-2, -0.1)
+        e = 1e-6 * p
+        vp, vm = X.rarefaction(a, p + e, side).v, X.rarefaction(a, p - e, side).v
+        b = X.rarefaction(a, p, side)
+        ref = sgn / (b.rho * b.h * b.cs * b.W ** 2)
+        assert abs((vp - vm) / (2 * e) - ref) <= 1e-5 * abs(ref)
+        # rho on the isentrope
+        assert abs(b.rho - a.rho * (p / a.p) ** (1 / GAM)) <= 1e-13 * b.rho
+
+
+def test_exact_solution_pressure_and_velocity_are_continuous_at_the_contact():
+    for L, R in PROBLEMS.values():
+        ps, vs = X.solve(L, R)
+        bl, br = X.behind(L, ps, "L"), X.behind(R, ps, "R")
+        assert abs(bl.v - br.v) <= 1e-12 and bl.p == br.p == ps
+
+
+def _tube(L, R, N):
+    """one block of N x 1 x 1 cells on [0, 1] (outflow in x, periodic in y, z)"""
+    g = 3
+    sx, sy, sz = N + 2 * g, 1 + 2 * g, 1 + 2 * g
+    x = (np.arange(sx) - g + 0.5) / N
+    left = x < 0.5
+    w = np.zeros((5, sz, sy, sx))
+    for c, (a, b) in enumerate([(L.rho, R.rho), (L.W * L.v, R.W * R.v), (0, 0), (0, 0), (L.p, R.p)]):
+        w[c] = np.where(left, a, b)[None, None, :]
+    adm = np.zeros((16, sz, sy, sx))
+    adm[0] = 1.0
+    adm[4] = adm[7] = adm[9] = 1.0
+    bf = [np.zeros((sz, sy, sx + 1)), np.zeros((sz, sy + 1, sx)), np.zeros((sz + 1, sy, sx))]
+    nbr = []
+    for oz in (-1, 0, 1):
+        for oy in (-1, 0, 1):
+            for ox in (-1, 0, 1):
+                nbr.append(-1 if ox != 0 else 0)
+    h = 1.0 / N
+    return inputs.BlockInit(N, 1, 1, g, (h, h, h), w, bf, adm, nbr, 1)
+
+
+def _l1_error(name, N, t_end=0.4):
+    L, R = PROBLEMS[name]
+    blk = _tube(L, R, N)
+    p = O.Params(gamma=GAM, rho_atm=1e-12, T_atm=1e-14, f_thr=1.0, recon=2, riemann=1)
+    m = O.Mesh([blk], p)
+    t = 0.0
+    while t < t_end - 1e-14:
+        dt = min(m.dt(0.25), t_end - t)
+        m.rk2_step(dt)
+        t += dt
+    rho = m.interior(m.w0[0], 0)[0, 0, 0, :]
+    xc = (np.arange(N) + 0.5) / N
+    ex = X.sample(L, R, (xc - 0.5) / t_end)[0]
+    return np.mean(np.abs(rho - ex)), rho, ex
+
+
+@pytest.mark.parametrize("name", ["sod", "blast"])
+def test_oracle_converges_to_the_exact_riemann_solution(name):
+    errs = [_l1_error(name, N)[0] for N in (100, 200, 400)]
+    order = np.log2(errs[0] / errs[2]) / 2.0
+    print(name, "L1 errors", errs, "order", order)
+    assert errs[0] > errs[1] > errs[2]
+    assert order > 0.6
+    bound = {"sod": 3e-3, "blast": 3.5e-2}[name]
+    assert errs[2] < bound, errs
