@@ -228,12 +228,12 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
               double *mu_out, int32_t *nev_out, void *stream);
 
 /* grmhd_stage with the stage's final inversion (step a8) started from the
-   learned bracket (mlp != NULL; NULL = grmhd_stage).  Same outputs and
-   atmosphere rules; cells whose bracket holds no sign change fall back to the
-   full bracket and carry bit 8 in flags.  The FOFC trial inversion stays
-   plain.  stats (device, may be NULL) accumulates solves, master-function
-   evaluations, fallbacks and failures of the final inversion.  mlp's
-   bracket_ws is not used. */
+   learned bracket (mlp != NULL; NULL = the plain inversion of grmhd_stage).
+   Same outputs and atmosphere rules; cells whose bracket holds no sign
+   change fall back to the full bracket and carry bit 8 in flags.  The FOFC
+   trial inversion stays plain.  stats (device, may be NULL) accumulates
+   solves, master-function evaluations, fallbacks and failures of the final
+   inversion (plain or learned).  mlp's bracket_ws is not used. */
 int grmhd_stage_learned(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
                         const grmhd_params *p, const double *dt_d, double dt, double a0,
                         double a1, double b, const c2p_mlp *mlp, c2p_stats *stats,

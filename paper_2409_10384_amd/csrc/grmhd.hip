@@ -506,53 +506,72 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
 // ---------------------------------------------------------------------------
 template <int ET>
 __global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __restrict__ blks, Eos e_in,
-                                                        grmhd_params p) {
+                                                        grmhd_params p, c2p_stats* stats) {
   const Eos e = eos_fixed<ET>(e_in);
   int bi;
   int64_t t;
-  if (!locate(blks, S_INTERIOR, bi, t)) return;
-  const grmhd_block& b = blks[bi];
-  const Geo q = geo_of(b);
-  const Box bx = interior_box(q);
-  int i, j, k;
-  bx.at(t, i, j, k);
-  const int64_t c = cell(q, i, j, k);
-  double w[5];
-  C2PWork cw;
-  {
-    M3 m;
-    cell_metric(b, c, m);
-    double U[5], Bt[3];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
-    cell_bt(q, b.bo, i, j, k, Bt);
-    cw = c2p_prepare(e, p, m, U, Bt, w);
-    if (cw.done) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
-    }
-  }
-  uint32_t r = cw.fl;
-  if (!cw.done) {
-    int nev;
-    double mu;
-    r = c2p_lean(e, p, cw, w, false, 0.0, 0.0, nev, mu);
-    if (r & kFloorBits) {
-      // U from the final primitives; metric and field loaded again (the
-      // barrier keeps them from living across the root solve)
-      __asm__ volatile("" ::: "memory");
+  const bool live = locate(blks, S_INTERIOR, bi, t);   // no early return: wave sums below
+  unsigned long long c_n = 0, c_ev = 0, c_fail = 0;
+  if (live) {
+    const grmhd_block& b = blks[bi];
+    const Geo q = geo_of(b);
+    const Box bx = interior_box(q);
+    int i, j, k;
+    bx.at(t, i, j, k);
+    const int64_t c = cell(q, i, j, k);
+    double w[5];
+    C2PWork cw;
+    {
       M3 m;
       cell_metric(b, c, m);
       double U[5], Bt[3];
-      cell_bt(q, b.bo, i, j, k, Bt);
-      prim_to_cons(e, m, w, Bt, U);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+      for (int v = 0; v < 5; ++v) U[v] = b.uo[v][c];
+      cell_bt(q, b.bo, i, j, k, Bt);
+      cw = c2p_prepare(e, p, m, U, Bt, w);
+      if (cw.done) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+      }
+    }
+    uint32_t r = cw.fl;
+    int nev = 0;
+    if (!cw.done) {
+      double mu;
+      r = c2p_lean(e, p, cw, w, false, 0.0, 0.0, nev, mu);
+      if (r & kFloorBits) {
+        // U from the final primitives; metric and field loaded again (the
+        // barrier keeps them from living across the root solve)
+        __asm__ volatile("" ::: "memory");
+        M3 m;
+        cell_metric(b, c, m);
+        double U[5], Bt[3];
+        cell_bt(q, b.bo, i, j, k, Bt);
+        prim_to_cons(e, m, w, Bt, U);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) b.uo[v][c] = U[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) b.wo[v][c] = w[v];
+    b.flags[c] = (uint16_t)(b.flags[c] | r);
+    c_n = 1;
+    c_ev = (unsigned long long)nev;
+    c_fail = (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
+  }
+  if (stats) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      c_n += __shfl_xor(c_n, o, 64);
+      c_ev += __shfl_xor(c_ev, o, 64);
+      c_fail += __shfl_xor(c_fail, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && c_n) {
+      atomicAdd(&stats->solves, c_n);
+      atomicAdd(&stats->evaluations, c_ev);
+      if (c_fail) atomicAdd(&stats->failures, c_fail);
     }
   }
-#pragma unroll
-  for (int v = 0; v < 5; ++v) b.wo[v][c] = w[v];
-  b.flags[c] = (uint16_t)(b.flags[c] | r);
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,11 +1094,12 @@ void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos&
 }
 
 void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
-             const Eos& e, hipStream_t s) {
+             const Eos& e, hipStream_t s, c2p_stats* stats = nullptr) {
   const Sizes z = max_sizes(h, nblk);
   TIMED(T_C2P, s);
   eos_dispatch(e.type, [&](auto et) {
-    k_stage_c2p<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(d, e, p);
+    k_stage_c2p<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(
+        d, e, p, stats);
   });
 }
 
@@ -1225,7 +1245,7 @@ int grmhd_stage_learned(const grmhd_block* blk_h, const grmhd_block* blk_d, int3
   if (mlp) {
     if ((r = launch_stage_c2p_learned(blk_h, blk_d, nblk, *p, mlp, stats, s))) return r;
   } else {
-    run_c2p(blk_h, blk_d, nblk, *p, e, s);
+    run_c2p(blk_h, blk_d, nblk, *p, e, s, stats);
   }
   return last_err();
 }

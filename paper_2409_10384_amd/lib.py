@@ -353,9 +353,12 @@ class DeviceMesh:
         key = "s1" if stage == 1 else "s2"
         dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
         dval = float(dt) if dt is not None else 0.0
-        if mlp is None:
+        if mlp is None and stats is None:
             rc = L.grmhd_stage(*self._args(key), C.byref(self.params.c()), dptr, dval, a0, a1, b,
                                self.sp())
+        elif mlp is None:
+            rc = L.grmhd_stage_learned(*self._args(key), C.byref(self.params.c()), dptr, dval, a0,
+                                       a1, b, None, C.c_void_p(stats.data_ptr()), self.sp())
         else:
             self._mlp_keep = mlp.c()
             sptr = C.c_void_p(stats.data_ptr()) if stats is not None else None
@@ -555,11 +558,13 @@ class LearnedC2P:
         self.scale = [float(1.0 / max(x, 1e-12)) for x in sd]
 
     def fit(self, u, bt, gam, params: MethodParams, w_true, steps=20000, batch=4096, lr=2e-3,
-            seed=0, log_every=0, log=None):
+            seed=0, log_every=0, log=None, calibrate=0.99, width_min=1e-4):
         """Standardise on the raw features of (u, bt, gam), then train on the
         targets of w_true for `steps` Adam steps of `batch` samples with a
-        cosine-decaying learning rate (the training kernels of this library).
-        Returns the loss of every log_every-th step."""
+        cosine-decaying learning rate (the training kernels of this library),
+        then (calibrate = q, not None) set the bracket width so that it holds
+        the label of a fraction q of the training samples.  Returns the loss of
+        every log_every-th step."""
         import math
         raw, _ = self.features(u, bt, gam, params, standardise=False)
         self.fit_standardisation(raw)
@@ -577,7 +582,25 @@ class LearnedC2P:
                 losses.append(float(loss.item()))
                 if log:
                     log(f"  train step {it}: loss {losses[-1]:.4g}")
+        if calibrate is not None:
+            self.calibrate_width(feats, target, q=calibrate, seed=seed, width_min=width_min)
         return losses
+
+    def calibrate_width(self, feats, target, q=0.99, nmax=1 << 20, seed=0, width_min=1e-4):
+        """Set the bracket half-width factor k so that the bracket logistic(y0
+        -+ (k exp(y1) + width_min)) holds the training label for a fraction q
+        of (up to nmax) training samples: k is the q-quantile of
+        |y0 - t| / exp(y1)."""
+        n = feats.shape[1]
+        if n > nmax:
+            gen = torch.Generator(device=feats.device).manual_seed(seed + 1)
+            idx = torch.randint(0, n, (nmax,), device=feats.device, generator=gen)
+            feats, target = feats[:, idx].contiguous(), target[idx].contiguous()
+        y = self.forward(feats)
+        ratio = (y[0] - target).abs() / torch.exp(y[1].clamp(max=30.0))
+        self.width_k = float(torch.quantile(ratio.double(), q).item())
+        self.width_min = width_min
+        return self.width_k
 
     def forward(self, feats, stream=None):
         n = feats.shape[1]
