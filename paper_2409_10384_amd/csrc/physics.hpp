@@ -27,6 +27,14 @@ constexpr double kFloorMargin = 1e-10;
 // ---------------------------------------------------------------------------
 // EOS: derived piece constants are computed once on the host
 // ---------------------------------------------------------------------------
+// 1/x for a normal, finite, nonzero x (every use below has x > 0 or a
+// guard): the hardware reciprocal refined by one Newton
+// step (error within an ulp or so of the correctly rounded quotient)
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 struct Eos {
   int type, n;
   double gam, gth;
@@ -171,7 +179,8 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
   lower(m.g, q[1], q[2], q[3], ul[0], ul[1], ul[2]);
   const double usq = q[1] * ul[0] + q[2] * ul[1] + q[3] * ul[2];
   const double W = sqrt(1.0 + usq);
-  const double iW = 1.0 / W;
+  const double iW = rcp_nr(W);
+  const double iW2 = iW * iW;
   double v[3] = {q[1] * iW, q[2] * iW, q[3] * iW};
   double vl[3] = {ul[0] * iW, ul[1] * iW, ul[2] * iW};
   double Bl[3];
@@ -179,16 +188,17 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
   const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
   const double Bv = B[0] * vl[0] + B[1] * vl[1] + B[2] * vl[2];
   const double eps = eos_eps_from_P(e, rho, P);
-  const double h = 1.0 + eps + P / rho;
-  const double ia = 1.0 / alpha;
+  const double h = 1.0 + eps + P * rcp_nr(rho);
+  const double ia = rcp_nr(alpha);
   const double b0 = W * Bv * ia;
   const double W2 = W * W;
-  const double bsq = B2 / W2 + Bv * Bv;
+  const double bsq = B2 * iW2 + Bv * Bv;
   const double sg = m.sg;
   const double Ptt = sg * (P + 0.5 * bsq);
   const double D = rho * W;
   const double ehw = rho * h * W2 + B2;
-  const double tau = tau_hydro(D, usq, W, rho, eps, P) + B2 - 0.5 * (Bv * Bv + B2 / W2);
+  const double tau = D * usq * rcp_nr(W + 1.0) + rho * eps * W2 + P * usq + B2 -
+                     0.5 * (Bv * Bv + B2 * iW2);
   double vh[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) vh[a] = v[a] - beta[a] * ia;
@@ -211,15 +221,15 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
   s.F[6] = alpha * (s.U[6] * vh[DIR] - Btd * vh[T2]);
   // fast magnetosonic estimate c^2 = cs^2 + ca^2 - cs^2 ca^2
   const double cs2 = eos_cs2(e, rho, eps, P, h);
-  const double ca2 = bsq / (rho * h + bsq);
+  const double ca2 = bsq * rcp_nr(rho * h + bsq);
   const double c2 = cs2 + ca2 - cs2 * ca2;
-  const double v2 = usq / W2;
+  const double v2 = usq * iW2;
   const double gdd = m.u[sym(DIR, DIR)];
   const double vd = v[DIR];
   double disc = c2 * (1.0 - v2) * (gdd * (1.0 - v2 * c2) - vd * vd * (1.0 - c2));
   disc = disc > 0.0 ? disc : 0.0;
   const double sq = sqrt(disc);
-  const double iden = 1.0 / (1.0 - v2 * c2);
+  const double iden = rcp_nr(1.0 - v2 * c2);
   const double base = vd * (1.0 - c2);
   s.lp = alpha * (base + sq) * iden - beta[DIR];
   s.lm = alpha * (base - sq) * iden - beta[DIR];
@@ -272,7 +282,7 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   // (each factor lies in [1e-40, ~1e3] for the fields reconstructed here)
   const double e0 = be0 + 1e-40, e1 = be1 + 1e-40, e2 = be2 + 1e-40;
   const double e12 = e1 * e2;
-  const double tip = t5 / (e0 * e12);
+  const double tip = t5 * rcp_nr(e0 * e12);
   const double r0 = tip * e12, r1 = tip * (e0 * e2), r2 = tip * (e0 * e1);
   const double w0 = 0.1 * (1.0 + r0 * r0);
   const double w1 = 0.6 * (1.0 + r1 * r1);
@@ -280,7 +290,7 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   const double p0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
   const double p1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
   const double p2 = (2.0 * c + 5.0 * d - f) * (1.0 / 6.0);
-  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+  return (w0 * p0 + w1 * p1 + w2 * p2) * rcp_nr(w0 + w1 + w2);
 }
 
 // atmosphere rules on a reconstructed face state (Sec. III-C)
@@ -329,12 +339,13 @@ struct KEval { double chi, rb2, qb, vsq, W, rho, eps, P; };
 
 __device__ __forceinline__ KEval k_eval(const Eos& e, const KState& k, double mu) {
   KEval o;
-  const double chi = 1.0 / (1.0 + mu * k.b2);
+  const double chi = rcp_nr(1.0 + mu * k.b2);
   const double rb2 = chi * chi * k.r2 + mu * chi * (1.0 + chi) * (k.s * k.s);
   const double qb = k.q - 0.5 * k.b2 - 0.5 * (mu * mu) * (chi * chi) * (k.b2 * k.r2 - k.s * k.s);
   const double vsq = fmin(mu * mu * rb2, k.v0sq);
-  const double W = 1.0 / sqrt(1.0 - vsq);
-  const double rho = k.D / W;
+  const double sw = sqrt(1.0 - vsq);      // 1 / W
+  const double W = rcp_nr(sw);
+  const double rho = k.D * sw;
   double eps = W * (qb - mu * rb2) + vsq * (W * W) / (1.0 + W);
   eps = fmax(eps, eos_eps_min(e, rho));
   o.chi = chi; o.rb2 = rb2; o.qb = qb; o.vsq = vsq; o.W = W; o.rho = rho; o.eps = eps;
@@ -344,9 +355,9 @@ __device__ __forceinline__ KEval k_eval(const Eos& e, const KState& k, double mu
 
 __device__ __forceinline__ double k_master(const Eos& e, const KState& k, double mu) {
   const KEval s = k_eval(e, k, mu);
-  const double a = s.P / (s.rho * (1.0 + s.eps));
-  const double nu = fmax((1.0 + a) * (1.0 + s.eps) / s.W, (1.0 + a) * (1.0 + s.qb - mu * s.rb2));
-  return mu - 1.0 / (nu + mu * s.rb2);
+  const double a = s.P * rcp_nr(s.rho * (1.0 + s.eps));
+  const double nu = fmax((1.0 + a) * (1.0 + s.eps) * rcp_nr(s.W), (1.0 + a) * (1.0 + s.qb - mu * s.rb2));
+  return mu - rcp_nr(nu + mu * s.rb2);
 }
 
 __device__ __forceinline__ double k_aux(const KState& k, double mu) {
