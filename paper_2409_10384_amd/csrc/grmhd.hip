@@ -955,35 +955,6 @@ int check_blocks(const grmhd_block* h, const grmhd_block* d, int nblk) {
   return GRMHD_OK;
 }
 
-struct Sizes {
-  int64_t cells, interior, ext_cells, faces[3], ifaces[3], edges[3];
-};
-
-Sizes max_sizes(const grmhd_block* h, int nblk) {
-  Sizes s;
-  memset(&s, 0, sizeof(s));
-  for (int i = 0; i < nblk; ++i) {
-    const Geo q = geo_of(h[i]);
-    const int n[3] = {q.nx, q.ny, q.nz};
-    s.cells = s.cells > n_cells(q) ? s.cells : n_cells(q);
-    const int64_t in = (int64_t)q.nx * q.ny * q.nz;
-    s.interior = s.interior > in ? s.interior : in;
-    const int64_t ec = (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
-    s.ext_cells = s.ext_cells > ec ? s.ext_cells : ec;
-    for (int d = 0; d < 3; ++d) {
-      int64_t f = 1, fi = 1, e = 1;
-      for (int a = 0; a < 3; ++a) {
-        f *= a == d ? n[a] + 1 : n[a] + 2;
-        fi *= a == d ? n[a] + 1 : n[a];
-        e *= a == d ? n[a] : n[a] + 1;
-      }
-      s.faces[d] = s.faces[d] > f ? s.faces[d] : f;
-      s.ifaces[d] = s.ifaces[d] > fi ? s.ifaces[d] : fi;
-      s.edges[d] = s.edges[d] > e ? s.edges[d] : e;
-    }
-  }
-  return s;
-}
 
 // 1-D grid over all 64-item waves of launch shape cls in the block list
 dim3 grid_cls(const grmhd_block* h, int nblk, int cls, int threads) {
@@ -1013,16 +984,12 @@ int64_t prepare_layout(grmhd_block* h, int nblk, bool write) {
   return 0;
 }
 
-dim3 grid_for(int64_t items, int nblk) {
-  return dim3((unsigned)((items + kThreads - 1) / kThreads), (unsigned)nblk, 1);
-}
 
 int last_err() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_EHIP; }
 
 // the steps; validation is done by the public entry points
 void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
                 const Eos& e, hipStream_t s) {
-  const Sizes z = max_sizes(h, nblk);
   {
     TIMED(T_BCC, s);
     k_bcc<<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d);
@@ -1048,7 +1015,6 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
               const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
               hipStream_t s) {
-  const Sizes z = max_sizes(h, nblk);
   k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
   if (!p.fofc) return;
   {
@@ -1073,7 +1039,6 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
 
 void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
             double a0, double a1, double b, hipStream_t s) {
-  const Sizes z = max_sizes(h, nblk);
   TIMED(T_CT, s);
   k_emf_cc<<<grid_cls(h, nblk, S_EXT, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
   k_emf_edge<0><<<grid_cls(h, nblk, S_XEDGE + 0, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
@@ -1086,7 +1051,6 @@ void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* 
 
 void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos& e,
                 const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
-  const Sizes z = max_sizes(h, nblk);
   TIMED(T_UPDATE, s);
   eos_dispatch(e.type, [&](auto et) {
     k_update<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(d, e, dt_d, dt, a0, a1, b);
@@ -1095,7 +1059,6 @@ void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos&
 
 void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
              const Eos& e, hipStream_t s, c2p_stats* stats = nullptr) {
-  const Sizes z = max_sizes(h, nblk);
   TIMED(T_C2P, s);
   eos_dispatch(e.type, [&](auto et) {
     k_stage_c2p<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(
@@ -1285,17 +1248,10 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
     }
   }
   if (!any) return GRMHD_OK;   // every block's ghosts are frozen: nothing to launch
-  const Sizes z = max_sizes(blk_h, nblk);
   hipStream_t s = (hipStream_t)stream;
   TIMED(T_GHOST, s);
   if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11, 0);
   if (mask & 4) {
-    int64_t mf[3] = {0, 0, 0};
-    for (int i = 0; i < nblk; ++i)
-      for (int d = 0; d < 3; ++d) {
-        const int64_t f = n_faces(geo_of(blk_h[i]), d);
-        mf[d] = mf[d] > f ? mf[d] : f;
-      }
     for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_cls(blk_h, nblk, S_XPFACE + d, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, d);
   }
   return last_err();
@@ -1308,7 +1264,6 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
   if (!blk_h || !blk_d || nblk < 1 || !red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
   if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  const Sizes z = max_sizes(blk_h, nblk);
   k_zero1<<<1, 64, 0, s>>>(red);
   {
     TIMED(T_DT, s);
@@ -1372,7 +1327,6 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
   if (r) return r;
   if (!blk_h || !blk_d || nblk < 1) return GRMHD_EINVAL;
   if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
-  const Sizes z = max_sizes(blk_h, nblk);
   const Eos e = make_eos(*p);
   eos_dispatch(e.type, [&](auto et) {
     k_p2c_block<decltype(et)::value><<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0,
