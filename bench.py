@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6          # MI355X FP64 vector peak
 
 
 def log(*a):
@@ -95,6 +96,18 @@ def source_hash():
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_2409_10384_amd", "csrc"))):
         h.update(open(os.path.join(ROOT, "paper_2409_10384_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def pmc_fp64():
+    """FP64 operations per launch by kernel family from the committed counter
+    summary (None when the kernel sources changed since)"""
+    path = os.path.join(ROOT, "profiles", "pmc_fp64.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    return {k: v["flops_per_launch"] for k, v in d.get("kernels", {}).items()}
 
 
 def pmc_traffic(family, launches_per_step):
@@ -176,13 +189,27 @@ def star_section(args, torch, inputs, lib):
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": pmc_traffic(dom, None), "bytes_per_launch": nbytes,
                 "avg_launch_ms": dms}
+    # FP64 rate of every stage kernel from the committed FP64 instruction
+    # counters (operations per launch) and the launch times measured here
+    fp64 = None
+    ops = pmc_fp64()
+    if ops:
+        per = {}
+        tot = 0.0
+        for k, v in fam.items():
+            if k in ops:
+                per[k] = {"tflops": ops[k] / (v[0] / v[1] * 1e-3) / 1e12,
+                          "frac": ops[k] / (v[0] / v[1] * 1e-3) / 1e12 / FP64_PEAK_TFS}
+                tot += ops[k] * v[1]
+        fp64 = {"peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "kernels": per,
+                "counted_kernels_tflops": tot / (sum(v[0] for k, v in fam.items() if k in ops) * 1e-3) / 1e12}
     sb = step_bytes(blocks)
     path = {"bound": "hbm", "algorithmic_bytes_per_step": sb,
             "achieved": sb / (ms / args.steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     path["frac"] = path["achieved"] / HBM_PEAK_GBS
     mass = float(mesh.mass().item())
     return dict(value=value, ms=ms, ncell=ncell, roofline=roof, path=path, breakdown=breakdown,
-                st=st, mass=mass)
+                st=st, mass=mass, fp64=fp64)
 
 
 def refined_section(args, torch, inputs, lib):
@@ -538,6 +565,7 @@ def main():
                    "cells": star["ncell"]},
         "roofline": star["roofline"],
         "path_roofline": star["path"],
+        "fp64_rate": star["fp64"],
         "kernel_breakdown": star["breakdown"],
     }
     if not args.no_refined:

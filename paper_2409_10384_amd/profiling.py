@@ -2,6 +2,8 @@
 
   python -m paper_2409_10384_amd.profiling stats <kernel_stats.csv>
       per-kernel calls, total and average duration (markdown table)
+  python -m paper_2409_10384_amd.profiling fp64 <counter_collection.csv> <out.json>
+      FP64 lane operations per launch from the four FP64 VALU counters
   python -m paper_2409_10384_amd.profiling traffic <fetch counter_collection.csv>
       <write counter_collection.csv> <out.json>
       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel, scaled by what the
@@ -101,8 +103,32 @@ def traffic(fetch_csv, write_csv, out_json):
     return d
 
 
+FP64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_INSTS_VALU_TRANS_F64")
+
+
+def fp64(csv_path, out_json):
+    """FP64 lane operations per launch of every stage kernel family from one
+    pass of the four FP64 VALU instruction counters (wave instructions x 64
+    lanes; an FMA counts two operations, a transcendental one)"""
+    per = {c: counter_per_kernel(csv_path, c) for c in FP64_COUNTERS}
+    kernels = {}
+    for k in per["SQ_INSTS_VALU_FMA_F64"]:
+        fam = family(k)
+        if fam is None or fam == "copy":
+            continue
+        add, mul, fma, trans = (per[c].get(k, 0.0) for c in FP64_COUNTERS)
+        kernels[fam] = {"kernel": k, "add": add, "mul": mul, "fma": fma, "trans": trans,
+                        "flops_per_launch": 64.0 * (add + mul + 2.0 * fma + trans)}
+    d = {"source_hash": source_hash(), "kernels": kernels}
+    json.dump(d, open(out_json, "w"), indent=1)
+    return d
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+    elif sys.argv[1] == "fp64":
+        print(json.dumps(fp64(sys.argv[2], sys.argv[3]), indent=1))
