@@ -427,18 +427,42 @@ def _copy_np(b):
     return c
 
 
-def c2p_section(args, torch, inputs, lib):
-    """C2P solves/s on 2^k random states, plain vs learned bracket"""
+def _eps_cold(rho, pp, K):
+    """cold specific energy of the 3-piece polytrope (P and eps continuous at
+    the dividing densities), for the exact labels of the hybrid states"""
+    import torch
+    G, rb = pp["Gam"], pp["rho_b"]
+    a = [0.0]
+    for i in (1, 2):
+        pr = K[i - 1] * rb[i - 1] ** G[i - 1]
+        a.append(a[-1] + pr / (rb[i - 1] * (G[i - 1] - 1.0)) - pr / (rb[i - 1] * (G[i] - 1.0)))
+    e = [a[i] + K[i] * rho ** (G[i] - 1.0) / (G[i] - 1.0) for i in range(3)]
+    return torch.where(rho < rb[0], e[0], torch.where(rho < rb[1], e[1], e[2]))
+
+
+def c2p_section(args, torch, inputs, lib, eos="ideal"):
+    """C2P solves/s on 2^k random states, plain vs learned bracket; eos
+    'ideal' (Gamma = 5/3, the benchmark states) or 'hybrid' (the end-to-end
+    piecewise polytrope, densities up to 10^-2.9 where it stays causal)"""
     n = 1 << args.c2p_log2
-    p = lib.MethodParams(**C2P_PARAMS)
-    log(f"c2p: {n} states")
-    s = inputs.c2p_states_torch(n, seed_offset=3, device="cuda")
+    kw = {}
+    if eos == "ideal":
+        p = lib.MethodParams(**C2P_PARAMS)
+    else:
+        pp, pK = inputs.pp_eos()
+        p = lib.MethodParams(**{**C2P_PARAMS, **pp})
+        kw = dict(pp=pp, pp_K=pK, log_rho=(-10.0, -2.9))
+    log(f"c2p ({eos}): {n} states")
+    s = inputs.c2p_states_torch(n, seed_offset=3, device="cuda", **kw)
     u0 = lib.prim2con(s["w"], s["bt"], s["gam"], p)
-    eps = s["w"][4] / ((C2P_PARAMS["gamma"] - 1.0) * s["w"][0])
+    if eos == "ideal":
+        eps = s["w"][4] / ((C2P_PARAMS["gamma"] - 1.0) * s["w"][0])
+    else:
+        eps = _eps_cold(s["w"][0], pp, pK) + s["eps"]
     mu_exact = 1.0 / ((1.0 + eps + s["w"][4] / s["w"][0]) * s["W"])
     # train the guess network on separate states (own forward/backward kernels)
     t0 = time.perf_counter()
-    tr = inputs.c2p_states_torch(1 << 18, seed_offset=300, device="cuda")
+    tr = inputs.c2p_states_torch(1 << 18, seed_offset=300, device="cuda", **kw)
     ut = lib.prim2con(tr["w"], tr["bt"], tr["gam"], p)
     net = lib.LearnedC2P(seed=0)
     steps = args.train_steps
@@ -479,9 +503,10 @@ def c2p_section(args, torch, inputs, lib):
                      "mean_master_evals": stt[1] / stt[0], "fallback_rate": stt[2] / stt[0],
                      "unrecovered_failures": int(stt[3]),
                      "kernel_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]}}
-        log(f"c2p {kind}: {res[kind]['solves_per_s']:.3e} solves/s, err {err:.2e}, "
+        log(f"c2p ({eos}) {kind}: {res[kind]['solves_per_s']:.3e} solves/s, err {err:.2e}, "
             f"evals {res[kind]['mean_master_evals']:.2f}, fallback {res[kind]['fallback_rate']:.4f}, "
             f"kernels {res[kind]['kernel_ms']}")
+    res["eos"] = eos
     res["states"] = n
     res["train_steps"] = steps
     res["bracket_width_k"] = net.width_k
@@ -534,7 +559,9 @@ def main():
         log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
         del a, b
     if args.c2p_only:
-        print(json.dumps({"c2p": c2p_section(args, torch, inputs, lib)}), flush=True)
+        print(json.dumps({"c2p": c2p_section(args, torch, inputs, lib),
+                          "c2p_hybrid_eos": c2p_section(args, torch, inputs, lib, eos="hybrid")}),
+              flush=True)
         return
     if args.refined_only:
         print(json.dumps({"refined": refined_section(args, torch, inputs, lib)}), flush=True)
@@ -572,6 +599,7 @@ def main():
         out["refined"] = refined_section(args, torch, inputs, lib)
     if not args.no_c2p:
         out["c2p"] = c2p_section(args, torch, inputs, lib)
+        out["c2p_hybrid_eos"] = c2p_section(args, torch, inputs, lib, eos="hybrid")
     c5_sub = None
     if not args.no_c5:
         out["end_to_end"], c5_sub = c5_section(args, torch, inputs, lib)

@@ -111,9 +111,9 @@ int grmhd_blocks_prepare(grmhd_block *blk_h, int32_t nblk);
    (7 components D~, S~_xyz, tau~, F(B~^{t1}), F(B~^{t2}) per direction, t1 =
    (d+1)%3, t2 = (d+2)%3), the cell-centred field B^i = B~_cc/sqrt(gamma)
    (3 cell arrays), the cell-centre EMF (3 cell arrays), the corner EMFs
-   (3 arrays of (sx+1)(sy+1)(sz+1)), the learned bracket (2 cell arrays) and
-   the FOFC list of flagged cells of [g-1, g+n]^3 (a counter and
-   (nx+2)(ny+2)(nz+2) int32 cell indices).  Flux d, component c starts at
+   (3 arrays of (sx+1)(sy+1)(sz+1)), room for per-wave statistics of the
+   stage inversion (2 cell arrays) and the FOFC list of flagged cells of
+   [g-1, g+n]^3 (a counter and (nx+2)(ny+2)(nz+2) int32 cell indices).  Flux d, component c starts at
    grmhd_flux_offset(...) doubles into scratch. */
 int64_t grmhd_scratch_doubles(int32_t nx, int32_t ny, int32_t nz, int32_t ng);
 int64_t grmhd_flux_offset(int32_t nx, int32_t ny, int32_t nz, int32_t ng, int32_t d, int32_t c);
@@ -229,8 +229,9 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
 
 /* grmhd_stage with the stage's final inversion (step a8) started from the
    learned bracket (mlp != NULL; NULL = the plain inversion of grmhd_stage).
-   Same outputs and atmosphere rules; cells whose bracket holds no sign
-   change fall back to the full bracket and carry bit 8 in flags.  The FOFC
+   Same outputs and atmosphere rules; a bracket that holds no sign change is
+   moved towards the root (4 and 16 times its width) and then replaced by the
+   full bracket; such cells carry bit 8 in flags.  The FOFC
    trial inversion stays plain.  stats (device, may be NULL) accumulates
    solves, master-function evaluations, fallbacks and failures of the final
    inversion (plain or learned).  mlp's bracket_ws is not used. */

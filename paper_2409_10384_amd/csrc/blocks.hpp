@@ -47,7 +47,7 @@ __device__ __forceinline__ int64_t edge(const Geo& q, int i, int j, int k) {
   return ((int64_t)k * (q.sy + 1) + j) * (q.sx + 1) + i;
 }
 
-// scratch layout (doubles): flux[d][c] | Bcc[3] | Ecc[3] | Eedge[3] | bracket[2]
+// scratch layout (doubles): flux[d][c] | Bcc[3] | Ecc[3] | Eedge[3] | wave stats | FOFC list
 __host__ __device__ __forceinline__ int64_t off_flux(const Geo& q, int d, int c) {
   int64_t o = 0;
   for (int dd = 0; dd < d; ++dd) o += 7 * n_faces(q, dd);
@@ -62,8 +62,10 @@ __host__ __device__ __forceinline__ int64_t off_ecc(const Geo& q) {
 __host__ __device__ __forceinline__ int64_t off_edge(const Geo& q) {
   return off_ecc(q) + 3 * n_cells(q);
 }
-// learned bracket [lo, hi] of the stage inversion, per padded cell
-__host__ __device__ __forceinline__ int64_t off_br(const Geo& q) {
+// statistics of the stage inversion: per 64-cell wave of the interior shape,
+// the wave's solves, evaluations, fallbacks and failures (4 uint64), summed
+// by a reduction kernel (room for 2 doubles per padded cell)
+__host__ __device__ __forceinline__ int64_t off_wstat(const Geo& q) {
   return off_edge(q) + 3 * n_edges(q);
 }
 // FOFC cell list: the flagged cells of [g-1, g+n]^3 (interior cells and the
@@ -72,7 +74,7 @@ __host__ __device__ __forceinline__ int64_t fofc_cap(const Geo& q) {
   return (int64_t)(q.nx + 2) * (q.ny + 2) * (q.nz + 2);
 }
 __host__ __device__ __forceinline__ int64_t off_fofc(const Geo& q) {
-  return off_br(q) + 2 * n_cells(q);
+  return off_wstat(q) + 2 * n_cells(q);
 }
 __host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
   return off_fofc(q) + (fofc_cap(q) + 2 + 1) / 2;
@@ -82,6 +84,25 @@ __device__ __forceinline__ unsigned int* fofc_count(const grmhd_block& b, const 
 }
 __device__ __forceinline__ int* fofc_list(const grmhd_block& b, const Geo& q) {
   return (int*)(b.scratch + off_fofc(q)) + 2;
+}
+
+// Sum (solves, evaluations, fallbacks, failures) over the wave and store it
+// in the block's per-wave slot (lane 0; item index t of the interior shape).
+// Inactive lanes must not call this; every lane of a live wave does.
+__device__ __forceinline__ void wave_stats_store(const grmhd_block& b, const Geo& q, int64_t t,
+                                                 unsigned long long n, unsigned long long ev,
+                                                 unsigned long long fb, unsigned long long fail) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    n += __shfl_xor(n, o, 64);
+    ev += __shfl_xor(ev, o, 64);
+    fb += __shfl_xor(fb, o, 64);
+    fail += __shfl_xor(fail, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* ws = (unsigned long long*)(b.scratch + off_wstat(q)) + 4 * (t >> 6);
+    ws[0] = n; ws[1] = ev; ws[2] = fb; ws[3] = fail;
+  }
 }
 
 // Append cell c to the block's FOFC list when `take`; all lanes of the wave

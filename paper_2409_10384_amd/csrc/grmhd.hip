@@ -559,18 +559,42 @@ __global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __
     c_ev = (unsigned long long)nev;
     c_fail = (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
   }
-  if (stats) {
+  // per-wave sums into the block's scratch (summed by k_stats_sum): no
+  // global atomics per wave
+  if (stats && __shfl((int)live, 0, 64)) {
+    const grmhd_block& b = blks[bi];
+    wave_stats_store(b, geo_of(b), t, c_n, c_ev, 0ull, c_fail);
+  }
+}
+
+// sum of the per-wave inversion statistics of every block into stats
+// (one workgroup per block, four atomics per block)
+__global__ __launch_bounds__(kThreads) void k_stats_sum(const grmhd_block* __restrict__ blks,
+                                                        c2p_stats* stats) {
+  const grmhd_block& b = blks[blockIdx.x];
+  const Geo q = geo_of(b);
+  const int64_t nw = (shape_items(q, S_INTERIOR) + 63) / 64;
+  const unsigned long long* ws = (const unsigned long long*)(b.scratch + off_wstat(q));
+  unsigned long long a[4] = {0ull, 0ull, 0ull, 0ull};
+  for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      c_n += __shfl_xor(c_n, o, 64);
-      c_ev += __shfl_xor(c_ev, o, 64);
-      c_fail += __shfl_xor(c_fail, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0 && c_n) {
-      atomicAdd(&stats->solves, c_n);
-      atomicAdd(&stats->evaluations, c_ev);
-      if (c_fail) atomicAdd(&stats->failures, c_fail);
-    }
+    for (int c = 0; c < 4; ++c) a[c] += ws[4 * i + c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) a[c] += __shfl_xor(a[c], o, 64);
+  __shared__ unsigned long long part[kThreads / 64][4];
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part[threadIdx.x >> 6][c] = a[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv)
+      for (int c = 0; c < 4; ++c) part[0][c] += part[wv][c];
+    atomicAdd(&stats->solves, part[0][0]);
+    atomicAdd(&stats->evaluations, part[0][1]);
+    atomicAdd(&stats->fallbacks, part[0][2]);
+    atomicAdd(&stats->failures, part[0][3]);
   }
 }
 
@@ -826,9 +850,11 @@ __global__ __launch_bounds__(kThreads) void k_c2p_batch(int64_t n, Ptrs5 u, Ptrs
                                                         const double* bhi, double* mu_out,
                                                         int32_t* nev_out, c2p_stats* stats) {
   const Eos e = eos_fixed<ET>(e_in);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c_n = 0, c_ev = 0, c_fb = 0, c_fail = 0;
-  if (t < n) {
+  // grid-stride loop: each lane keeps its statistics until the end, so the
+  // atomics are per wave of a bounded grid, not per 64 states
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
     C2PWork cw;
     double ww[5];
     {
@@ -866,10 +892,10 @@ __global__ __launch_bounds__(kThreads) void k_c2p_batch(int64_t n, Ptrs5 u, Ptrs
     flags[t] = (uint16_t)r;
     if (mu_out) mu_out[t] = mu;
     if (nev_out) nev_out[t] = nev;
-    c_n = 1;
-    c_ev = (unsigned long long)nev;
-    c_fb = (r & GRMHD_F_BRACKET_FALLBACK) ? 1 : 0;
-    c_fail = (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
+    c_n += 1;
+    c_ev += (unsigned long long)nev;
+    c_fb += (r & GRMHD_F_BRACKET_FALLBACK) ? 1 : 0;
+    c_fail += (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
   }
   if (stats) {
 #pragma unroll
@@ -987,6 +1013,22 @@ int64_t prepare_layout(grmhd_block* h, int nblk, bool write) {
 
 int last_err() { return hipGetLastError() == hipSuccess ? GRMHD_OK : GRMHD_EHIP; }
 
+// grid of a grid-stride point kernel: enough workgroups to fill every CU at
+// any occupancy (8 per CU), no more than the work needs
+unsigned batch_grid(int64_t n) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t pr;
+    cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess)
+              ? pr.multiProcessorCount
+              : 256;
+  }
+  const int64_t tiles = (n + kThreads - 1) / kThreads;
+  const int64_t g = (int64_t)cus * 8;
+  return (unsigned)(tiles < g ? tiles : g);
+}
+
 // the steps; validation is done by the public entry points
 void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
                 const Eos& e, hipStream_t s) {
@@ -1064,6 +1106,7 @@ void run_c2p(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_p
     k_stage_c2p<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_C2P)), tpb(T_C2P), 0, s>>>(
         d, e, p, stats);
   });
+  if (stats) k_stats_sum<<<nblk, kThreads, 0, s>>>(d, stats);
 }
 
 // plain streaming copy (counter calibration)
@@ -1091,13 +1134,16 @@ void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* co
   TIMED(blo ? T_C2P_LEARNED : T_C2P_BATCH, s);
   const Eos e = make_eos(p);
   eos_dispatch(e.type, [&](auto et) {
-    k_c2p_batch<decltype(et)::value><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+    k_c2p_batch<decltype(et)::value><<<batch_grid(n), kThreads, 0, s>>>(
         n, pu, pb, pg, pw, flags, e, p, blo, bhi, mu_out, nev_out, stats);
   });
 }
 Eos make_eos_host(const grmhd_params& p) { return make_eos(p); }
 unsigned stage_grid(const grmhd_block* h, int nblk, int cls, int threads) {
   return grid_cls(h, nblk, cls, threads).x;
+}
+void launch_stats_sum(const grmhd_block* d, int nblk, c2p_stats* stats, hipStream_t s) {
+  k_stats_sum<<<nblk, kThreads, 0, s>>>(d, stats);
 }
 int launch_stage_c2p_learned(const grmhd_block* h, const grmhd_block* d, int nblk,
                              const grmhd_params& p, const c2p_mlp* mlp, c2p_stats* stats,

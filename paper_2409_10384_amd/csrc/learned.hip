@@ -21,6 +21,7 @@ using namespace gk;
 namespace gk {
 Eos make_eos_host(const grmhd_params& p);
 unsigned stage_grid(const grmhd_block* h, int nblk, int cls, int threads);
+void launch_stats_sum(const grmhd_block* d, int nblk, c2p_stats* stats, hipStream_t s);
 int check_params_host(const grmhd_params* p);
 void launch_c2p_batch(int64_t n, double* const* u, double* const* bt, double* const* gam, double* const* w,
                       uint16_t* flags, const grmhd_params& p, const double* blo, const double* bhi,
@@ -291,21 +292,8 @@ __global__ __launch_bounds__(kT) void k_stage_c2p_learned(const grmhd_block* __r
     c_fb = (r & GRMHD_F_BRACKET_FALLBACK) ? 1 : 0;
     c_fail = (r & GRMHD_F_C2P_FAIL) ? 1 : 0;
   }
-  if (stats) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      c_n += __shfl_xor(c_n, o, 64);
-      c_ev += __shfl_xor(c_ev, o, 64);
-      c_fb += __shfl_xor(c_fb, o, 64);
-      c_fail += __shfl_xor(c_fail, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0 && c_n) {
-      atomicAdd(&stats->solves, c_n);
-      atomicAdd(&stats->evaluations, c_ev);
-      if (c_fb) atomicAdd(&stats->fallbacks, c_fb);
-      if (c_fail) atomicAdd(&stats->failures, c_fail);
-    }
-  }
+  // per-wave sums into the block's scratch, summed by the stats reduction
+  if (stats && __shfl((int)live, 0, 64)) wave_stats_store(b, q, t, c_n, c_ev, c_fb, c_fail);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,6 +591,7 @@ int launch_stage_c2p_learned(const grmhd_block* h, const grmhd_block* d, int nbl
     k_stage_c2p_learned<decltype(et)::value><<<stage_grid(h, nblk, S_INTERIOR, kT), kT, 0, s>>>(
         d, e, p, mlp->w_bf16, mlp->w_f32, ft, mlp->width_k, mlp->width_min, stats);
   });
+  if (stats) launch_stats_sum(d, nblk, stats, s);
   return learned_err();
 }
 }  // namespace gk

@@ -151,15 +151,20 @@ __device__ __forceinline__ void mlp_out(const uint16_t* in, const uint16_t* W4, 
 // registers.  Lane l contributes its own state's 5 features x and receives
 // (y0, y1) of its own state.  All 64 lanes must call this together.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bf16x4 silu_frag(f32x4 acc, const float* bias) {
-  // bias: the 4 consecutive neurons of this lane's fragment rows
-  const float4 bv = *(const float4*)bias;
-  bf16x4 h;
-  h[0] = (short)f2bf(silu_f(acc[0] + bv.x));
-  h[1] = (short)f2bf(silu_f(acc[1] + bv.y));
-  h[2] = (short)f2bf(silu_f(acc[2] + bv.z));
-  h[3] = (short)f2bf(silu_f(acc[3] + bv.w));
-  return h;
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+
+// SiLU of an MFMA output fragment (bias already in the accumulator), packed
+// to bf16 two values per conversion
+__device__ __forceinline__ bf16x4 silu_frag(f32x4 acc) {
+  f32x4 h;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) h[e] = silu_f(acc[e]);
+  return __builtin_bit_cast(bf16x4, __builtin_convertvector(h, bf16x4v));
+}
+
+// accumulator start: the biases of this lane's 4 fragment rows (neurons)
+__device__ __forceinline__ f32x4 bias_frag(const float* bias) {
+  return *(const f32x4*)bias;
 }
 
 __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], float& y0, float& y1) {
@@ -185,25 +190,25 @@ __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], floa
     bf16x4 h1[4], h2[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc = bias_frag(w.b1 + nt * 16 + 4 * q);
       acc = mfma16(ld4(w.W1 + (nt * 16 + r) * kLdIn + 4 * q), xb, acc);
-      h1[nt] = silu_frag(acc, w.b1 + nt * 16 + 4 * q);
+      h1[nt] = silu_frag(acc);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc = bias_frag(w.b2 + nt * 16 + 4 * q);
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = mfma16(ld4(w.W2 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h1[ks], acc);
-      h2[nt] = silu_frag(acc, w.b2 + nt * 16 + 4 * q);
+      h2[nt] = silu_frag(acc);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc = bias_frag(w.b3 + nt * 16 + 4 * q);
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = mfma16(ld4(w.W3 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h2[ks], acc);
-      h1[nt] = silu_frag(acc, w.b3 + nt * 16 + 4 * q);
+      h1[nt] = silu_frag(acc);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll

@@ -509,18 +509,40 @@ __device__ __forceinline__ uint32_t c2p_lean(const Eos& e, const grmhd_params& p
   double lo = 0.0, hi = 1.0, flo = 0.0, fhi = 0.0;
   bool have = false;
   if (use_br) {
-    const double l0 = fmax(blo, 0.0), h0 = fmin(bhi, 1.0);
+    double l0 = fmax(blo, 0.0), h0 = fmin(bhi, 1.0);
     if (l0 < h0 && __builtin_isfinite(l0) && __builtin_isfinite(h0)) {
       flo = fm(l0);
       fhi = fm(h0);
       nev += 2;
-      if (flo <= 0.0 && fhi >= 0.0) {
+      have = flo <= 0.0 && fhi >= 0.0;
+      if (!have) fl |= GRMHD_F_BRACKET_FALLBACK;
+      // A bracket that misses the root (mostly by little) is first moved
+      // towards it, 4 and then 16 times its width, one evaluation each; only
+      // then the full bracket.  f(0) < 0, so moving down stays valid.
+      for (int x = 0; x < 2 && !have && __builtin_isfinite(flo) && __builtin_isfinite(fhi); ++x) {
+        const double wdt = 4.0 * (h0 - l0);
+        if (flo > 0.0 && fhi > 0.0) {         // root below the bracket
+          h0 = l0; fhi = flo;
+          l0 = fmax(l0 - wdt, 0.0);
+          flo = fm(l0);
+          ++nev;
+        } else if (flo < 0.0 && fhi < 0.0 && h0 < 1.0) {   // root above it
+          l0 = h0; flo = fhi;
+          h0 = fmin(h0 + wdt, 1.0);
+          fhi = fm(h0);
+          ++nev;
+        } else {
+          break;
+        }
+        have = flo <= 0.0 && fhi >= 0.0;
+      }
+      if (have) {
         lo = l0;
         hi = h0;
-        have = true;
       }
+    } else {
+      fl |= GRMHD_F_BRACKET_FALLBACK;
     }
-    if (!have) fl |= GRMHD_F_BRACKET_FALLBACK;
   }
   bool valid = true;
   if (!have) {

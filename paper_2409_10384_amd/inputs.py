@@ -492,9 +492,11 @@ def c2p_states(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps
 
 
 def c2p_states_torch(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), log_eps=(-6.0, 1.0),
-                     W_range=(1.0, 10.0), log_bsq_rho=(-4.0, 1.0), metric_dev=0.1, device="cuda"):
+                     W_range=(1.0, 10.0), log_bsq_rho=(-4.0, 1.0), metric_dev=0.1, device="cuda",
+                     pp=None, pp_K=None):
     """c2p_states with the same distributions, drawn with torch on a device
-    (for workloads too large to build on the host; different random stream)."""
+    (for workloads too large to build on the host; different random stream).
+    pp, pp_K: piecewise polytrope as in c2p_states (eps is the thermal part)."""
     import torch
     g = torch.Generator(device=device).manual_seed(SEED_BASE + seed_offset)
     f64 = dict(dtype=torch.float64, device=device)
@@ -529,7 +531,10 @@ def c2p_states_torch(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), l
     Bmag = torch.sqrt(bsq / (1.0 / (W * W) + nv * nv))
     B = nb * Bmag[:, None]
     sqrtg = torch.sqrt(torch.linalg.det(G))
-    P = (gamma - 1.0) * rho * eps
+    if pp is None:
+        P = (gamma - 1.0) * rho * eps
+    else:
+        P = pp_cold_pressure(rho, pp, pp_K) + (pp["gamma_th"] - 1.0) * rho * eps
     w = torch.stack([rho, W * v[:, 0], W * v[:, 1], W * v[:, 2], P]).contiguous()
     bt = (B * sqrtg[:, None]).T.contiguous()
     return {"w": w, "bt": bt, "gam": gam.contiguous(), "W": W, "eps": eps}

@@ -207,14 +207,17 @@ def test_learned_stage_matches_plain_stage(G):
     net.fit(u, bt, gam, mp, w, steps=2000)
     dt = float(gp.compute_dt(0.25).item())
     stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stats_p = torch.zeros(4, dtype=torch.int64, device="cuda")
     for _ in range(2):
-        gp.rk2_step(dt=dt)
+        gp.rk2_step(dt=dt, stats=stats_p)
         gl.rk2_step(dt=dt, mlp=net, stats=stats)
     torch.cuda.synchronize()
     n_s, n_ev, n_fb, n_fail = [int(x) for x in stats.cpu()]
-    say(f"  solves {n_s}, evaluations/solve {n_ev / max(n_s, 1):.2f}, fallbacks {n_fb}, failures {n_fail}")
-    assert n_s == 4 * sum(b.nx * b.ny * b.nz for b in blocks)
-    assert n_fail == 0
+    p_s, p_ev, p_fb, p_fail = [int(x) for x in stats_p.cpu()]
+    say(f"  learned: solves {n_s}, evaluations/solve {n_ev / max(n_s, 1):.2f}, fallbacks {n_fb}, "
+        f"failures {n_fail}; plain: evaluations/solve {p_ev / max(p_s, 1):.2f}")
+    assert n_s == p_s == 4 * sum(b.nx * b.ny * b.nz for b in blocks)
+    assert n_fail == 0 and p_fail == 0 and p_fb == 0
     for ib in range(len(blocks)):
         fp = gp.interior(gp.flags[ib], ib).cpu().numpy().astype(np.uint16)
         fl = gl.interior(gl.flags[ib], ib).cpu().numpy().astype(np.uint16)
