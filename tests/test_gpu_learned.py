@@ -132,7 +132,7 @@ def train_network(G, n_train=1 << 18, steps=1500, batch=4096, seed=0):
     return net, losses
 
 
-def test_learned_c2p_beats_plain_at_equal_error(G):
+def test_learned_c2p_needs_fewer_evaluations_at_equal_error(G):
     say("learned: train on prim->cons pairs, compare with the plain solve")
     net, losses = train_network(G)
     say(f"  loss trace {['%.3g' % x for x in losses]}")
