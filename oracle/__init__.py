@@ -75,7 +75,8 @@ def lib():
 @dataclasses.dataclass
 class Params:
     """Method options: EOS, atmosphere (rho_atm, T_atm, f_thr, M_max),
-    reconstruction (0 donor cell, 2 WENOZ), Riemann solver (0 LLF, 1 HLLE),
+    reconstruction (0 donor cell, 1 PLM, 2 WENOZ, 3 PPM4, 4 PPMX), Riemann
+    solver (0 LLF, 1 HLLE),
     FOFC on/off, DMP factor M (<= 0 off), C2P tolerance and iteration cap."""
 
     gamma: float = 5.0 / 3.0
@@ -206,6 +207,17 @@ def wenoz(q5):
     return out
 
 
+def recon_edges(kind, q5):
+    """lower and upper edge values of the middle cell of five-cell stencils
+    q5 (n, 5) for reconstruction kind 0 DC, 1 PLM, 2 WENOZ, 3 PPM4, 4 PPMX"""
+    q5 = np.ascontiguousarray(q5, dtype=np.float64).reshape(-1, 5)
+    lo = np.zeros(q5.shape[0])
+    hi = np.zeros(q5.shape[0])
+    if lib().or_recon_edges(C.c_int(kind), C.c_int64(q5.shape[0]), _pd(q5), _pd(lo), _pd(hi)) != 0:
+        raise ValueError(f"reconstruction kind {kind}")
+    return lo, hi
+
+
 def riemann(riemann_kind, UL, FL, lmL, lpL, UR, FR, lmR, lpR):
     arr = lambda a: np.ascontiguousarray(a, dtype=np.float64)
     UL, FL, UR, FR = arr(UL), arr(FL), arr(UR), arr(FR)
@@ -237,13 +249,22 @@ def cell_bt(bf):
 
 
 class Mesh:
-    """Blocks with two state sets (A = U^n side, B = intermediate) for SSP-RK2
-    in Shu-Osher form: U1 = U0 + dt L(U0); U2 = 1/2 U0 + 1/2 U1 + 1/2 dt L(U1)."""
+    """Blocks with three state sets (A = U^n side, B and C = intermediates).
+    SSP-RK2 in Shu-Osher form: U1 = U0 + dt L(U0); U2 = 1/2 U0 + 1/2 U1 +
+    1/2 dt L(U1).  SSP-RK3 (Gottlieb, Ketcheson & Shu 2009, the three-stage
+    third-order scheme): U1 = U0 + dt L(U0); U2 = 3/4 U0 + 1/4 U1 + 1/4 dt L(U1);
+    U3 = 1/3 U0 + 2/3 U2 + 2/3 dt L(U2).  A stage with coefficients (a0, a1, b)
+    computes a0 U^n + a1 U^(s) + b dt L(U^(s))."""
+
+    RK2 = ((0, 1, (0.0, 1.0, 1.0)), (1, 0, (0.5, 0.5, 0.5)))
+    RK3 = ((0, 1, (0.0, 1.0, 1.0)), (1, 2, (0.75, 0.25, 0.25)),
+           (2, 0, (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)))
 
     def __init__(self, blocks, params: Params):
         self.params = params
         self.blocks = blocks
         self.u0, self.w0, self.b0, self.u1, self.w1, self.b1, self.flags = [], [], [], [], [], [], []
+        self.u2, self.w2, self.b2 = [], [], []
         for b in blocks:
             shp = b.shape
             w = np.array(b.w, dtype=np.float64, order="C", copy=True)
@@ -253,13 +274,18 @@ class Mesh:
             self.u0.append(np.ascontiguousarray(u))
             self.w0.append(w)
             self.b0.append(bf)
-            # set B starts as a copy of set A, so that frozen ghosts (bc == 0)
-            # hold the initial data in both sets (stages write interiors only)
-            self.u1.append(np.ascontiguousarray(u).copy())
-            self.w1.append(w.copy())
-            self.b1.append([x.copy() for x in bf])
+            # sets B and C start as copies of set A, so that frozen ghosts
+            # (bc == 0) hold the initial data in every set (stages write
+            # interiors only)
+            for U, W, Bf in ((self.u1, self.w1, self.b1), (self.u2, self.w2, self.b2)):
+                U.append(np.ascontiguousarray(u).copy())
+                W.append(w.copy())
+                Bf.append([x.copy() for x in bf])
             self.flags.append(np.zeros(shp, dtype=np.uint16))
         self.adm = [np.ascontiguousarray(b.adm) for b in blocks]
+
+    def _set(self, k):
+        return ((self.u0, self.w0, self.b0), (self.u1, self.w1, self.b1), (self.u2, self.w2, self.b2))[k]
 
     def _desc(self, ib, w, un, us, bn, bs, uo, bo, wo):
         b = self.blocks[ib]
@@ -280,46 +306,58 @@ class Mesh:
         d.bc = b.bc
         return d
 
-    def descs(self, stage):
-        """stage 1: (w0, U0, U0, B0, B0) -> (U1, B1, w1);
-        stage 2: (w1, U0, U1, B0, B1) -> (U0, B0, w0)."""
+    def stage_descs(self, src, dst):
+        """stage input w, U^(s), B^(s) from set src, U^n and B^n from set A;
+        output U, B, w into set dst"""
+        (us, ws, bs), (ua, _, ba), (uo, wo, bo) = self._set(src), self._set(0), self._set(dst)
         arr = (OrBlock * len(self.blocks))()
         for ib in range(len(self.blocks)):
-            if stage == 1:
-                arr[ib] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
-                                     self.b0[ib], self.u1[ib], self.b1[ib], self.w1[ib])
-            else:
-                arr[ib] = self._desc(ib, self.w1[ib], self.u0[ib], self.u1[ib], self.b0[ib],
-                                     self.b1[ib], self.u0[ib], self.b0[ib], self.w0[ib])
+            arr[ib] = self._desc(ib, ws[ib], ua[ib], us[ib], ba[ib], bs[ib], uo[ib], bo[ib], wo[ib])
         return arr
 
+    def descs(self, stage):
+        """RK2 stage 1: (w0, U0, U0, B0, B0) -> (U1, B1, w1);
+        stage 2: (w1, U0, U1, B0, B1) -> (U0, B0, w0)."""
+        return self.stage_descs(0, 1) if stage == 1 else self.stage_descs(1, 0)
+
     def ghost_fill_state(self, which):
-        """fill ghosts of state set A (which=0) or B (which=1): w, U, faces"""
+        """fill ghosts of state set A (which=0), B (1) or C (2): w, U, faces"""
+        U, W, Bf = self._set(which)
         arr = (OrBlock * len(self.blocks))()
         for ib in range(len(self.blocks)):
-            w = self.w0[ib] if which == 0 else self.w1[ib]
-            u = self.u0[ib] if which == 0 else self.u1[ib]
-            bf = self.b0[ib] if which == 0 else self.b1[ib]
-            arr[ib] = self._desc(ib, w, u, u, bf, bf, u, bf, w)
+            arr[ib] = self._desc(ib, W[ib], U[ib], U[ib], Bf[ib], Bf[ib], U[ib], Bf[ib], W[ib])
         lib().or_ghost_fill(arr, len(self.blocks), GF_W | GF_US | GF_BS)
 
     def dt(self, cfl):
         arr = self.descs(1)
         return lib().or_dt(arr, len(self.blocks), C.byref(self.params.c()), C.c_double(cfl))
 
-    def stage(self, stage, dt):
-        arr = self.descs(stage)
-        a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
+    def stage_sets(self, src, dst, dt, a0, a1, b):
+        arr = self.stage_descs(src, dst)
         lib().or_stage(arr, len(self.blocks), C.byref(self.params.c()), C.c_double(dt),
                        C.c_double(a0), C.c_double(a1), C.c_double(b))
+
+    def stage(self, stage, dt):
+        src, dst, (a0, a1, b) = self.RK2[stage - 1]
+        self.stage_sets(src, dst, dt, a0, a1, b)
+
+    def rk_step(self, scheme, dt):
+        """one step of the Shu-Osher scheme `scheme` (RK2 or RK3), ghosts of
+        each stage's output filled before the next stage"""
+        for src, dst, (a0, a1, b) in scheme:
+            self.stage_sets(src, dst, dt, a0, a1, b)
+            self.ghost_fill_state(dst)
+
+    def rk3_step(self, dt=None, cfl=0.25):
+        if dt is None:
+            dt = self.dt(cfl)
+        self.rk_step(self.RK3, dt)
+        return dt
 
     def rk2_step(self, dt=None, cfl=0.25):
         if dt is None:
             dt = self.dt(cfl)
-        self.stage(1, dt)
-        self.ghost_fill_state(1)
-        self.stage(2, dt)
-        self.ghost_fill_state(0)
+        self.rk_step(self.RK2, dt)
         return dt
 
     def mass(self):

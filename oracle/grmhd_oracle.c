@@ -19,8 +19,10 @@
  *   b^mu               Eq. 8
  *   fluxes             Eq. 9
  *   sources            Eq. 10
- *   reconstruction     WENOZ (Borges et al. 2008) / donor cell of rho, W v^i, P
- *                      (Sec. III-B)
+ *   reconstruction     of rho, W v^i, P (Sec. III-B): donor cell; PLM with van
+ *                      Leer's (1974) limiter; PPM4, the piecewise-parabolic method
+ *                      of Colella & Woodward (1984); PPMX, the extremum-preserving
+ *                      limiter of Colella & Sekora (2008); WENOZ (Borges et al. 2008)
  *   Riemann solver     HLLE / LLF (Sec. III-B)
  *   CT                 upwind constrained transport (Sec. III-B; Gardiner & Stone)
  *   floors             atmosphere rules for primitive and conserved variables
@@ -57,7 +59,7 @@ typedef struct {
   double c2p_tol;     /* relative tolerance of the root bracket */
   int32_t eos;        /* 0 ideal gas, 1 hybrid piecewise polytrope */
   int32_t npieces;    /* hybrid: number of cold pieces (1..4) */
-  int32_t recon;      /* 0 donor cell, 2 WENOZ */
+  int32_t recon;      /* 0 donor cell, 1 PLM, 2 WENOZ, 3 PPM4, 4 PPMX */
   int32_t riemann;    /* 0 LLF, 1 HLLE */
   int32_t fofc;       /* 0 off, 1 on */
   int32_t c2p_maxit;  /* iteration cap of the root solve */
@@ -612,6 +614,133 @@ static double wenoz_right(double qm2, double qm1, double q0, double qp1, double 
   return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
 }
 
+/* PLM: cell 0 is linear with van Leer's (1974) harmonic-mean slope of the
+   two one-sided differences, zero where they differ in sign. */
+static void plm_edges(double qm1, double q0, double qp1, double *lo, double *hi) {
+  double dl = q0 - qm1, dr = qp1 - q0;
+  double slope = 0.0;
+  if (dl * dr > 0.0) slope = 2.0 * dl * dr / (dl + dr);
+  *lo = q0 - 0.5 * slope;
+  *hi = q0 + 0.5 * slope;
+}
+
+/* PPM4 = the piecewise-parabolic method of Colella & Woodward (1984) on a
+   uniform grid.  Limited average slope of cell 0 (their Eq. 1.8): the
+   centred difference, bounded by twice each one-sided difference, zero at a
+   local extremum. */
+static double cw_slope(double qm1, double q0, double qp1) {
+  double dl = q0 - qm1, dr = qp1 - q0, dc = 0.5 * (qp1 - qm1);
+  if (dl * dr <= 0.0) return 0.0;
+  double m = fabs(dc);
+  if (2.0 * fabs(dl) < m) m = 2.0 * fabs(dl);
+  if (2.0 * fabs(dr) < m) m = 2.0 * fabs(dr);
+  return dc > 0.0 ? m : -m;
+}
+
+/* interface value between cells 0 and 1 (their Eqs. 1.6-1.7 with equal
+   widths): the mean of the two cells less a sixth of the change of slope */
+static double cw_interface(double qm1, double q0, double qp1, double qp2) {
+  return 0.5 * (q0 + qp1) - (cw_slope(q0, qp1, qp2) - cw_slope(qm1, q0, qp1)) / 6.0;
+}
+
+/* edge values of cell 0 from cells -2..2, after the monotonicity constraints
+   (their Eq. 1.10): flat at a local extremum; otherwise the edge on the side
+   of an overshooting parabola is moved until the parabola is monotone */
+static void ppm4_edges(const double q[5], double *lo, double *hi) {
+  double a = q[2];
+  double aL = cw_interface(q[0], q[1], q[2], q[3]);
+  double aR = cw_interface(q[1], q[2], q[3], q[4]);
+  if ((aR - a) * (a - aL) <= 0.0) {
+    aL = a;
+    aR = a;
+  } else {
+    double da = aR - aL;
+    double a6 = 6.0 * (a - 0.5 * (aL + aR));
+    if (da * a6 > da * da) aL = 3.0 * a - 2.0 * aR;
+    else if (-da * da > da * a6) aR = 3.0 * a - 2.0 * aL;
+  }
+  *lo = aL;
+  *hi = aR;
+}
+
+/* PPMX = PPM with the extremum-preserving limiter of Colella & Sekora (2008).
+   Limited second derivative: the smallest magnitude of its arguments (the
+   first unscaled, the rest scaled by C = 1.25) when all have one sign, else 0. */
+#define CS_C 1.25
+static double cs_d2lim(int n, const double *d2) {
+  int pos = 1, neg = 1;
+  for (int k = 0; k < n; ++k) {
+    if (!(d2[k] > 0.0)) pos = 0;
+    if (!(d2[k] < 0.0)) neg = 0;
+  }
+  if (!pos && !neg) return 0.0;
+  double m = fabs(d2[0]);
+  for (int k = 1; k < n; ++k)
+    if (CS_C * fabs(d2[k]) < m) m = CS_C * fabs(d2[k]);
+  return pos ? m : -m;
+}
+
+/* interface value between cells 0 and 1: the fourth-order value, and where
+   it leaves the range of the two cells, the mean of the two cells corrected
+   by a limited second derivative (an unlimited one, 3 (q0 - 2a + q1),
+   returns the fourth-order value itself) */
+static double cs_interface(double qm1, double q0, double qp1, double qp2) {
+  double a = 7.0 / 12.0 * (q0 + qp1) - 1.0 / 12.0 * (qm1 + qp2);
+  if ((a - q0) * (qp1 - a) < 0.0) {
+    double d2[3];
+    d2[0] = 3.0 * ((q0 + qp1) - 2.0 * a);
+    d2[1] = (qm1 + qp1) - 2.0 * q0;
+    d2[2] = (q0 + qp2) - 2.0 * qp1;
+    a = 0.5 * (q0 + qp1) - cs_d2lim(3, d2) / 6.0;
+  }
+  return a;
+}
+
+/* edge values of cell 0 from cells -2..2.  At a local extremum (of the
+   parabola or of the cell averages) the parabola's curvature is scaled by
+   the limited second derivative over its own; elsewhere an overshooting
+   edge is moved as in PPM.  Second differences are written as (sum of the
+   outer values) - 2 (centre), so mirrored data give mirrored edges exactly. */
+static void ppmx_edges(const double q[5], double *lo, double *hi) {
+  double a = q[2];
+  double aL = cs_interface(q[0], q[1], q[2], q[3]);
+  double aR = cs_interface(q[1], q[2], q[3], q[4]);
+  if ((aR - a) * (a - aL) <= 0.0 || (q[3] - a) * (a - q[1]) <= 0.0) {
+    double d2[4];
+    d2[0] = -2.0 * (6.0 * a - 3.0 * (aL + aR));
+    d2[1] = (q[0] + a) - 2.0 * q[1];
+    d2[2] = (q[1] + q[3]) - 2.0 * a;
+    d2[3] = (a + q[4]) - 2.0 * q[3];
+    double lim = cs_d2lim(4, d2);
+    if (d2[0] != 0.0) {
+      aL = a + (aL - a) * lim / d2[0];
+      aR = a + (aR - a) * lim / d2[0];
+    } else {
+      aL = a;
+      aR = a;
+    }
+  } else {
+    if (fabs(aR - a) >= 2.0 * fabs(aL - a)) aR = a - 2.0 * (aL - a);
+    if (fabs(aL - a) >= 2.0 * fabs(aR - a)) aL = a - 2.0 * (aR - a);
+  }
+  *lo = aL;
+  *hi = aR;
+}
+
+/* lower and upper edge values of cell 0 from the cells -2..2 around it */
+static void recon_edges(int kind, const double q[5], double *lo, double *hi) {
+  switch (kind) {
+    case 0: *lo = q[2]; *hi = q[2]; break;
+    case 1: plm_edges(q[1], q[2], q[3], lo, hi); break;
+    case 2:
+      *lo = wenoz_right(q[4], q[3], q[2], q[1], q[0]);
+      *hi = wenoz_right(q[0], q[1], q[2], q[3], q[4]);
+      break;
+    case 3: ppm4_edges(q, lo, hi); break;
+    default: ppmx_edges(q, lo, hi); break;
+  }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Block storage                                                              */
 /* ------------------------------------------------------------------------- */
@@ -684,7 +813,7 @@ static void face_floor(const eos_t *e, const or_params *p, double q[5]) {
 
 /* ------------------------------------------------------------------------- */
 /* Flux at one face (i,j,k) in direction d (face i = left face of cell i):    */
-/* reconstruction (order: 0 DC, 2 WENOZ), face metric, floors, physics,      */
+/* reconstruction (order = recon kind, 0 DC), face metric, floors, physics,  */
 /* Riemann solver.  Uses stage-input w and B~^(s).                            */
 /* ------------------------------------------------------------------------- */
 static void face_flux(const eos_t *e, const or_params *p, const or_block *b, int d, int i, int j,
@@ -725,11 +854,13 @@ static void face_flux(const eos_t *e, const or_params *p, const or_block *b, int
       qL[v] = st[v][2];
       qR[v] = st[v][3];
     } else {
-      const double *s = st[v];
-      /* s[0..5] = cells -3..2; left state = right edge of cell -1,
-         right state = left edge of cell 0 */
-      qL[v] = wenoz_right(s[0], s[1], s[2], s[3], s[4]);
-      qR[v] = wenoz_right(s[5], s[4], s[3], s[2], s[1]);
+      /* st[v][0..5] = cells -3..2; left state = upper edge of cell -1,
+         right state = lower edge of cell 0 */
+      double e_lo, e_hi;
+      recon_edges(order, st[v], &e_lo, &e_hi);
+      qL[v] = e_hi;
+      recon_edges(order, st[v] + 1, &e_lo, &e_hi);
+      qR[v] = e_lo;
     }
   }
   face_floor(e, p, qL);
@@ -1471,6 +1602,14 @@ int or_sources_point(const double *w, const double *bt, const double *u, const d
     for (int j = 0; j < 6; ++j) dg3[i][j] = dg[6 * i + j];
   }
   sources_point(&e, &m, alpha, w, bt, u, dal, dbe3, dg3, K6, G);
+  return 0;
+}
+
+/* lower and upper edge values of the middle cell of n five-point stencils
+   for reconstruction kind 0..4 (for pins) */
+int or_recon_edges(int kind, int64_t n, const double *q5, double *lo, double *hi) {
+  if (kind < 0 || kind > 4) return -1;
+  for (int64_t x = 0; x < n; ++x) recon_edges(kind, q5 + 5 * x, lo + x, hi + x);
   return 0;
 }
 

@@ -1,5 +1,5 @@
-"""Flat-space 1-D Riemann problems (B = 0): the oracle's stage (WENOZ + HLLE,
-SSP-RK2) against the exact special-relativistic solution of Marti & Mueller
+"""Flat-space 1-D Riemann problems (B = 0): the oracle's stage (WENOZ, PLM,
+PPM4 or PPMX + HLLE, SSP-RK2 or SSP-RK3) against the exact special-relativistic solution of Marti & Mueller
 (tests/exact_riemann.py), after the exact solver is itself checked against
 the conservation laws (jump conditions across its shocks) and the simple-wave
 relation of its rarefactions.  Shock-dominated solutions converge at first
@@ -90,15 +90,15 @@ def _tube(L, R, N):
     return inputs.BlockInit(N, 1, 1, g, (h, h, h), w, bf, adm, nbr, 1)
 
 
-def _l1_error(name, N, t_end=0.4):
+def _l1_error(name, N, t_end=0.4, recon=2, rk3=False):
     L, R = PROBLEMS[name]
     blk = _tube(L, R, N)
-    p = O.Params(gamma=GAM, rho_atm=1e-12, T_atm=1e-14, f_thr=1.0, recon=2, riemann=1)
+    p = O.Params(gamma=GAM, rho_atm=1e-12, T_atm=1e-14, f_thr=1.0, recon=recon, riemann=1)
     m = O.Mesh([blk], p)
     t = 0.0
     while t < t_end - 1e-14:
         dt = min(m.dt(0.25), t_end - t)
-        m.rk2_step(dt)
+        (m.rk3_step if rk3 else m.rk2_step)(dt)
         t += dt
     rho = m.interior(m.w0[0], 0)[0, 0, 0, :]
     xc = (np.arange(N) + 0.5) / N
@@ -115,3 +115,15 @@ def test_oracle_converges_to_the_exact_riemann_solution(name):
     assert order > 0.6
     bound = {"sod": 3e-3, "blast": 3.5e-2}[name]
     assert errs[2] < bound, errs
+
+
+@pytest.mark.parametrize("recon,rk3,bound", [(1, False, 5e-3), (3, False, 3.6e-3), (4, False, 3.3e-3),
+                                             (4, True, 3.3e-3)])
+def test_plm_ppm4_ppmx_and_rk3_converge_on_sod(recon, rk3, bound):
+    """The other reconstructions of Sec. III-B (PLM, PPM4, PPMX) and the SSP-RK3
+    step converge to the exact solution too; donor cell has L1 error 2.1e-2 at
+    N = 200 on this problem, the limited high-order methods 2.8e-3 to 4.5e-3."""
+    errs = [_l1_error("sod", N, recon=recon, rk3=rk3)[0] for N in (100, 200)]
+    print("recon", recon, "rk3", rk3, "L1 errors", errs)
+    assert errs[1] < 0.75 * errs[0]
+    assert errs[1] < bound, errs
