@@ -6,7 +6,8 @@
  *   conserved variables D~, S~_i, tau~ from (rho, W v^i, P, B^i)   Sec. II, Eq. 7-8
  *   fluxes                                                         Sec. II, Eq. 9
  *   metric source terms                                            Sec. II, Eq. 10
- *   reconstruction (donor cell, WENOZ) of rho, W v^i, P; HLLE/LLF   Sec. III-B
+ *   reconstruction of rho, W v^i, P (donor cell, PLM, PPM4, PPMX,
+ *   WENOZ); HLLE/LLF Riemann solvers                              Sec. III-B
  *   upwind constrained transport of the face field B~               Sec. III-B
  *   atmosphere floors, FOFC, FOFC+DMP (relaxed maximum principle)   Sec. III-C, Eq. 11-12
  *   conservative-to-primitive inversion (Kastaun et al. master
@@ -71,7 +72,10 @@ typedef struct grmhd_params {
   double c2p_tol;     /* relative bracket tolerance of the root solve */
   int32_t eos;        /* 0 ideal gas, 1 hybrid piecewise polytrope + thermal */
   int32_t npieces;    /* hybrid: cold pieces, 1..4 */
-  int32_t recon;      /* 0 donor cell, 2 WENOZ */
+  int32_t recon;      /* 0 donor cell, 1 PLM (van Leer limiter), 2 WENOZ,
+                         3 PPM4 (Colella & Woodward 1984), 4 PPMX
+                         (Colella & Sekora 2008 extremum-preserving);
+                         any other value: GRMHD_EUNSUPPORTED */
   int32_t riemann;    /* 0 LLF, 1 HLLE */
   int32_t fofc;       /* 0 off, 1 on */
   int32_t c2p_maxit;  /* iteration cap of the root solve */
@@ -122,9 +126,12 @@ int64_t grmhd_flux_offset(int32_t nx, int32_t ny, int32_t nz, int32_t ng, int32_
  * Every block-list entry point takes the descriptor table twice: blk_h in
  * host memory (launch geometry and validation) and blk_d, the same table in
  * device memory (read by the kernels).  nblk >= 1.  The RK coefficients give
- * U^out = a0 U^n + a1 U^(s) + b dt L(U^(s)); SSP-RK2 in Shu-Osher form is
- * (0, 1, 1) then (1/2, 1/2, 1/2).  dt is read from the device scalar dt_d
- * when dt_d != NULL, else the host value dt is used.
+ * U^out = a0 U^n + a1 U^(s) + b dt L(U^(s)) (Sec. III-B time integrators, in
+ * the Shu-Osher form of Gottlieb, Ketcheson & Shu 2009): SSP-RK2 is (0, 1, 1)
+ * then (1/2, 1/2, 1/2); SSP-RK3 is (0, 1, 1), (3/4, 1/4, 1/4), (1/3, 2/3,
+ * 2/3), each stage reading the previous stage's output as U^(s).  uo may
+ * alias un (the last stage), but not us.  dt is read from the device scalar
+ * dt_d when dt_d != NULL, else the host value dt is used.
  */
 
 /* Steps a1-a8 of one stage (Sec. III-B..III-D): face fluxes (reconstruction,

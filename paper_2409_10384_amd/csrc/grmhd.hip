@@ -48,10 +48,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
 // ---------------------------------------------------------------------------
 // a2 + a3: flux through one face of direction D
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int RC>
 __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
                                           const grmhd_block& b, const Geo& q, int i, int j, int k,
-                                          int order, double F[7]) {
+                                          double F[7]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
   const int64_t c0 = cell(q, i, j, k);
@@ -69,23 +69,17 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   const double* bt1 = bcc + T1 * nc;
   const double* bt2 = bcc + T2 * nc;
   double qL[7], qR[7];
-  if (order == 0) {
+  const double* src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      qL[v] = b.w[v][c0 - st];
-      qR[v] = b.w[v][c0];
-    }
-    qL[5] = bt1[c0 - st]; qR[5] = bt1[c0];
-    qL[6] = bt2[c0 - st]; qR[6] = bt2[c0];
-  } else {
-    const double* src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const double* a = src[v];
-      const double m3 = a[c0 - 3 * st], m2 = a[c0 - 2 * st], m1 = a[c0 - st];
-      const double p0 = a[c0], p1 = a[c0 + st], p2 = a[c0 + 2 * st];
-      qL[v] = wenoz(m3, m2, m1, p0, p1);
-      qR[v] = wenoz(p2, p1, p0, m1, m2);
+  for (int v = 0; v < 7; ++v) {
+    const double* a = src[v];
+    if constexpr (RC == 0) {
+      recon_face<0>(0.0, 0.0, a[c0 - st], a[c0], 0.0, 0.0, qL[v], qR[v]);
+    } else if constexpr (RC == 1) {
+      recon_face<1>(0.0, a[c0 - 2 * st], a[c0 - st], a[c0], a[c0 + st], 0.0, qL[v], qR[v]);
+    } else {
+      recon_face<RC>(a[c0 - 3 * st], a[c0 - 2 * st], a[c0 - st], a[c0], a[c0 + st],
+                     a[c0 + 2 * st], qL[v], qR[v]);
     }
   }
   floor_face(e, p, qL);
@@ -102,7 +96,7 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   riemann(p.riemann, L, R, F);
 }
 
-template <int D, int ET>
+template <int D, int ET, int RC>
 __global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restrict__ blks, Eos e_in,
                                                    grmhd_params p) {
   const Eos e = eos_fixed<ET>(e_in);
@@ -115,7 +109,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restr
   int i, j, k;
   bx.at(t, i, j, k);
   double F[7];
-  face_flux<D>(e, p, b, q, i, j, k, p.recon, F);
+  face_flux<D, RC>(e, p, b, q, i, j, k, F);
   const int64_t f = face<D>(q, i, j, k);
   const int64_t nf = n_faces(q, D);
   double* out = b.scratch + off_flux(q, D, 0);
@@ -223,7 +217,7 @@ __device__ __forceinline__ void fofc_cell_faces(const Eos& e, const grmhd_params
   double* out = b.scratch + off_flux(q, D, 0);
   double F[7];
   if (x[D] >= q.g) {
-    face_flux<D>(e, p, b, q, x[0], x[1], x[2], 0, F);
+    face_flux<D, 0>(e, p, b, q, x[0], x[1], x[2], F);
     const int64_t f = face<D>(q, x[0], x[1], x[2]);
 #pragma unroll
     for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
@@ -233,7 +227,7 @@ __device__ __forceinline__ void fofc_cell_faces(const Eos& e, const grmhd_params
     if (!(b.flags[cu] & (GRMHD_F_FOFC | GRMHD_F_DMP))) {
       int y[3] = {x[0], x[1], x[2]};
       y[D] += 1;
-      face_flux<D>(e, p, b, q, y[0], y[1], y[2], 0, F);
+      face_flux<D, 0>(e, p, b, q, y[0], y[1], y[2], F);
       const int64_t f = face<D>(q, y[0], y[1], y[2]);
 #pragma unroll
       for (int cc = 0; cc < 7; ++cc) out[cc * nf + f] = F[cc];
@@ -944,7 +938,7 @@ int check_params(const grmhd_params* p) {
   if (!p) return GRMHD_EINVAL;
   if (p->eos != 0 && p->eos != 1) return GRMHD_EINVAL;
   if (p->eos == 1 && (p->npieces < 1 || p->npieces > 4)) return GRMHD_EINVAL;
-  if (p->recon != 0 && p->recon != 2) return GRMHD_EUNSUPPORTED;
+  if (p->recon < 0 || p->recon > 4) return GRMHD_EUNSUPPORTED;
   if (p->riemann != 0 && p->riemann != 1) return GRMHD_EINVAL;
   if (p->c2p_maxit < 1) return GRMHD_EINVAL;
   return GRMHD_OK;
@@ -1039,18 +1033,27 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
   {
     TIMED(T_FLUX_X, s);
     eos_dispatch(e.type, [&](auto et) {
-      k_flux<0, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FLUX_X)), tpb(T_FLUX_X), 0, s>>>(d, e, p);
+      recon_dispatch(p.recon, [&](auto rc) {
+        k_flux<0, decltype(et)::value, decltype(rc)::value>
+            <<<grid_cls(h, nblk, S_XFACE + 0, tpb(T_FLUX_X)), tpb(T_FLUX_X), 0, s>>>(d, e, p);
+      });
     });
   }
   {
     TIMED(T_FLUX_Y, s);
     eos_dispatch(e.type, [&](auto et) {
-      k_flux<1, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FLUX_Y)), tpb(T_FLUX_Y), 0, s>>>(d, e, p);
+      recon_dispatch(p.recon, [&](auto rc) {
+        k_flux<1, decltype(et)::value, decltype(rc)::value>
+            <<<grid_cls(h, nblk, S_XFACE + 1, tpb(T_FLUX_Y)), tpb(T_FLUX_Y), 0, s>>>(d, e, p);
+      });
     });
   }
   TIMED(T_FLUX_Z, s);
   eos_dispatch(e.type, [&](auto et) {
-    k_flux<2, decltype(et)::value><<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FLUX_Z)), tpb(T_FLUX_Z), 0, s>>>(d, e, p);
+    recon_dispatch(p.recon, [&](auto rc) {
+      k_flux<2, decltype(et)::value, decltype(rc)::value>
+          <<<grid_cls(h, nblk, S_XFACE + 2, tpb(T_FLUX_Z)), tpb(T_FLUX_Z), 0, s>>>(d, e, p);
+    });
   });
 }
 

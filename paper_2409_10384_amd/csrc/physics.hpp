@@ -293,6 +293,141 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   return (w0 * p0 + w1 * p1 + w2 * p2) * rcp_nr(w0 + w1 + w2);
 }
 
+// ---------------------------------------------------------------------------
+// Reconstruction at one face (Sec. III-B).  The six cells m3, m2, m1 | p0, p1,
+// p2 straddle the face; qL is the upper edge value of cell m1 and qR the
+// lower edge value of cell p0.  RC: 0 donor cell, 1 PLM, 2 WENOZ, 3 PPM4,
+// 4 PPMX.  Every interface value and second difference is computed once per
+// face and shared by the two cells that use it.
+// ---------------------------------------------------------------------------
+
+// PLM: half of van Leer's (1974) harmonic-mean slope, 0 across an extremum
+__device__ __forceinline__ double vl_half_slope(double l, double c, double r) {
+  const double dl = c - l, dr = r - c, pr = dl * dr;
+  return pr > 0.0 ? pr * rcp_nr(dl + dr) : 0.0;
+}
+
+// Colella & Woodward (1984): the centred slope bounded by twice each
+// one-sided difference, 0 at an extremum
+__device__ __forceinline__ double cw_dm(double l, double c, double r) {
+  const double dl = c - l, dr = r - c;
+  const double dc = 0.5 * (r - l);
+  const double m = fmin(fabs(dc), 2.0 * fmin(fabs(dl), fabs(dr)));
+  return dl * dr > 0.0 ? copysign(m, dc) : 0.0;
+}
+
+// their monotonicity constraints on the edges (lo, hi) of a cell of mean a
+__device__ __forceinline__ void cw_constrain(double a, double& lo, double& hi) {
+  if ((hi - a) * (a - lo) <= 0.0) {
+    lo = a;
+    hi = a;
+    return;
+  }
+  const double da = hi - lo;
+  const double a6 = 6.0 * (a - 0.5 * (lo + hi));
+  const double da2 = da * da;
+  if (da * a6 > da2) lo = 3.0 * a - 2.0 * hi;
+  else if (-da2 > da * a6) hi = 3.0 * a - 2.0 * lo;
+}
+
+// Colella & Sekora (2008): smallest magnitude of x and C y, C z (C = 1.25)
+// when all three share a sign, else 0
+__device__ __forceinline__ double cs_lim3(double x, double y, double z) {
+  constexpr double C = 1.25;
+  const bool pos = x > 0.0 && y > 0.0 && z > 0.0;
+  const bool neg = x < 0.0 && y < 0.0 && z < 0.0;
+  const double m = fmin(fabs(x), C * fmin(fabs(y), fabs(z)));
+  return pos ? m : (neg ? -m : 0.0);
+}
+
+// fourth-order interface value between cells c0 and c1 (second differences
+// d0, d1 of those cells); limited where it leaves their range
+__device__ __forceinline__ double cs_iface(double cm, double c0, double c1, double cp, double d0,
+                                           double d1) {
+  double a = (7.0 / 12.0) * (c0 + c1) - (1.0 / 12.0) * (cm + cp);
+  if ((a - c0) * (c1 - a) < 0.0) {
+    const double d = 3.0 * ((c0 + c1) - 2.0 * a);
+    a = 0.5 * (c0 + c1) - (1.0 / 6.0) * cs_lim3(d, d0, d1);
+  }
+  return a;
+}
+
+// their cell limiter: mean a, neighbour means l and r, second differences
+// dl, dc, dr of the left, own and right cells
+__device__ __forceinline__ void cs_constrain(double a, double l, double r, double dl, double dc,
+                                             double dr, double& lo, double& hi) {
+  if ((hi - a) * (a - lo) <= 0.0 || (r - a) * (a - l) <= 0.0) {
+    const double d = -2.0 * (6.0 * a - 3.0 * (lo + hi));
+    constexpr double C = 1.25;
+    const bool pos = d > 0.0 && dl > 0.0 && dc > 0.0 && dr > 0.0;
+    const bool neg = d < 0.0 && dl < 0.0 && dc < 0.0 && dr < 0.0;
+    if (d != 0.0 && (pos || neg)) {
+      const double m = fmin(fabs(d), C * fmin(fabs(dc), fmin(fabs(dl), fabs(dr))));
+      const double s = (pos ? m : -m) / d;
+      lo = a + (lo - a) * s;
+      hi = a + (hi - a) * s;
+    } else {
+      lo = a;
+      hi = a;
+    }
+    return;
+  }
+  if (fabs(hi - a) >= 2.0 * fabs(lo - a)) hi = a - 2.0 * (lo - a);
+  if (fabs(lo - a) >= 2.0 * fabs(hi - a)) lo = a - 2.0 * (hi - a);
+}
+
+template <int RC>
+__device__ __forceinline__ void recon_face(double m3, double m2, double m1, double p0, double p1,
+                                           double p2, double& qL, double& qR) {
+  if constexpr (RC == 0) {
+    qL = m1;
+    qR = p0;
+  } else if constexpr (RC == 1) {
+    qL = m1 + vl_half_slope(m2, m1, p0);
+    qR = p0 - vl_half_slope(m1, p0, p1);
+  } else if constexpr (RC == 2) {
+    qL = wenoz(m3, m2, m1, p0, p1);
+    qR = wenoz(p2, p1, p0, m1, m2);
+  } else if constexpr (RC == 3) {
+    const double s_m2 = cw_dm(m3, m2, m1), s_m1 = cw_dm(m2, m1, p0);
+    const double s_p0 = cw_dm(m1, p0, p1), s_p1 = cw_dm(p0, p1, p2);
+    const double ia = 0.5 * (m2 + m1) - (s_m1 - s_m2) * (1.0 / 6.0);
+    double ib = 0.5 * (m1 + p0) - (s_p0 - s_m1) * (1.0 / 6.0);
+    const double ic = 0.5 * (p0 + p1) - (s_p1 - s_p0) * (1.0 / 6.0);
+    double lo = ia, hi = ib;
+    cw_constrain(m1, lo, hi);
+    qL = hi;
+    lo = ib;
+    hi = ic;
+    cw_constrain(p0, lo, hi);
+    qR = lo;
+  } else {
+    const double d_m2 = (m3 + m1) - 2.0 * m2, d_m1 = (m2 + p0) - 2.0 * m1;
+    const double d_p0 = (m1 + p1) - 2.0 * p0, d_p1 = (p0 + p2) - 2.0 * p1;
+    const double ia = cs_iface(m3, m2, m1, p0, d_m2, d_m1);
+    const double ib = cs_iface(m2, m1, p0, p1, d_m1, d_p0);
+    const double ic = cs_iface(m1, p0, p1, p2, d_p0, d_p1);
+    double lo = ia, hi = ib;
+    cs_constrain(m1, m2, p0, d_m2, d_m1, d_p0, lo, hi);
+    qL = hi;
+    lo = ib;
+    hi = ic;
+    cs_constrain(p0, m1, p1, d_m1, d_p0, d_p1, lo, hi);
+    qR = lo;
+  }
+}
+
+template <typename F>
+inline void recon_dispatch(int rc, F&& f) {
+  switch (rc) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: f(std::integral_constant<int, 4>{}); break;
+  }
+}
+
 // atmosphere rules on a reconstructed face state (Sec. III-C)
 __device__ __forceinline__ void floor_face(const Eos& e, const grmhd_params& p, double q[5]) {
   if (q[0] < p.f_thr * p.rho_atm) {

@@ -251,6 +251,7 @@ class StarSetup:
     A_b: float = 0.0              # set by calibrate_field
     pp: dict | None = None        # piecewise-polytrope gas (pp_eos); None: P = K rho^Gamma
     pp_K: tuple = ()
+    center: tuple = (0.0, 0.0, 0.0)   # star centre (the origin: mirror-symmetric about cell faces)
 
     def rho(self, r):
         return _maxs(self.rho_c * (1.0 - (r / self.radius) ** 2), self.rho_atm)
@@ -315,12 +316,14 @@ def _star_block_arrays(st: StarSetup, i0, j0, k0, n, ng, h, xmin, backend=None):
     gi = be.arange(s) - ng          # local padded -> global cell offset
     fa = be.arange(s + 1) - ng
     # 1-D coordinates, broadcast as [k, j, i]
-    xc = (xmin + (i0 + gi + 0.5) * h)[None, None, :]
-    yc = (xmin + (j0 + gi + 0.5) * h)[None, :, None]
-    zc = (xmin + (k0 + gi + 0.5) * h)[:, None, None]
-    xf = (xmin + (i0 + fa) * h)[None, None, :]
-    yf = (xmin + (j0 + fa) * h)[None, :, None]
-    zf = (xmin + (k0 + fa) * h)[:, None, None]
+    # coordinates relative to the star centre
+    cx, cy, cz = st.center
+    xc = (xmin + (i0 + gi + 0.5) * h - cx)[None, None, :]
+    yc = (xmin + (j0 + gi + 0.5) * h - cy)[None, :, None]
+    zc = (xmin + (k0 + gi + 0.5) * h - cz)[:, None, None]
+    xf = (xmin + (i0 + fa) * h - cx)[None, None, :]
+    yf = (xmin + (j0 + fa) * h - cy)[None, :, None]
+    zf = (xmin + (k0 + fa) * h - cz)[:, None, None]
     R = _sqrt(xc * xc + yc * yc + zc * zc)
     rho = st.rho(R)
     P = st.press(R)

@@ -118,7 +118,8 @@ def stream_ptr(stream=None):
 
 @dataclasses.dataclass
 class MethodParams:
-    """Method options (same meaning as the fields of grmhd_params)."""
+    """Method options (same meaning as the fields of grmhd_params); recon: 0
+    donor cell, 1 PLM, 2 WENOZ, 3 PPM4, 4 PPMX."""
 
     gamma: float = 5.0 / 3.0
     eos: int = 0
@@ -246,9 +247,20 @@ def flux_offset(nx, ny, nz, ng, d, c):
 
 
 class DeviceMesh:
-    """Blocks resident in HBM with two state sets (A: U^n side, B: stage-1
-    output) for SSP-RK2 in Shu-Osher form, the per-block scratch, and the
-    descriptor tables of both stages (host and device copies)."""
+    """Blocks resident in HBM with the state sets of the SSP Runge-Kutta
+    schemes in Shu-Osher form (A: U^n side, B: first-stage output, C: second-
+    stage output of RK3, allocated on first use), the per-block scratch, and
+    the descriptor tables of the stages (host and device copies).
+
+    A stage with coefficients (a0, a1, b) computes a0 U^n + a1 U^(s) + b dt
+    L(U^(s)) reading U^(s) from one set and writing another:
+      RK2: A -> B (0, 1, 1); B -> A (1/2, 1/2, 1/2)
+      RK3: A -> B (0, 1, 1); B -> C (3/4, 1/4, 1/4); C -> A (1/3, 2/3, 2/3)
+    (Gottlieb, Ketcheson & Shu 2009, the second- and third-order SSP schemes)."""
+
+    RK2 = ((0, 1, (0.0, 1.0, 1.0)), (1, 0, (0.5, 0.5, 0.5)))
+    RK3 = ((0, 1, (0.0, 1.0, 1.0)), (1, 2, (0.75, 0.25, 0.25)),
+           (2, 0, (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)))
 
     def __init__(self, blocks, params: MethodParams, device="cuda", stream=None):
         L = load()
@@ -259,6 +271,7 @@ class DeviceMesh:
         dev = self.device
         f64 = dict(dtype=torch.float64, device=dev)
         self.w0, self.u0, self.b0, self.w1, self.u1, self.b1 = [], [], [], [], [], []
+        self.w2, self.u2, self.b2 = None, None, None
         self.adm, self.flags, self.scratch = [], [], []
         def up(a):
             if isinstance(a, torch.Tensor):
@@ -277,10 +290,10 @@ class DeviceMesh:
             self.flags.append(torch.zeros(shp, dtype=torch.int16, device=dev))
             self.scratch.append(torch.zeros(L.grmhd_scratch_doubles(b.nx, b.ny, b.nz, b.ng), **f64))
         self.tables = {}
-        for key in ("s1", "s2", "fillA", "fillB"):
+        for key in ((0, 1), (1, 0), (0, 0), (1, 1)):
             self.tables[key] = self._make_table(key)
         # conserved state from the primitives (Eq. 7) on the device, all cells
-        check(L.grmhd_prim2con_blocks(*self._args("fillA"), C.byref(params.c()), self.sp()),
+        check(L.grmhd_prim2con_blocks(*self._args((0, 0)), C.byref(params.c()), self.sp()),
               "grmhd_prim2con_blocks")
         # set B starts as a copy of set A: frozen ghosts (bc == 0) then hold the
         # initial data in both sets (the stages write interiors only)
@@ -315,28 +328,43 @@ class DeviceMesh:
         d.bc = b.bc
         return d
 
+    def _set(self, k):
+        """(U, w, faces) lists of state set k (0 A, 1 B, 2 C)"""
+        if k == 2:
+            self._ensure_set_c()
+        return ((self.u0, self.w0, self.b0), (self.u1, self.w1, self.b1),
+                (self.u2, self.w2, self.b2))[k]
+
+    def _ensure_set_c(self):
+        """set C (RK3 only) starts as a copy of set A: frozen ghosts then hold
+        the initial data, as in the other sets"""
+        if self.u2 is not None:
+            return
+        with torch.cuda.stream(self.stream) if self.stream is not None else _nullctx():
+            self.u2 = [u.clone() for u in self.u0]
+            self.w2 = [w.clone() for w in self.w0]
+            self.b2 = [[x.clone() for x in bf] for bf in self.b0]
+
     def _make_table(self, key):
+        """key (src, dst): a stage reading w, U^(s), B^(s) from set src and
+        U^n, B^n from set A, writing U, B, w into set dst; (k, k) is the
+        table of set k alone (ghost fills, dt, mass)"""
+        src, dst = key
         n = len(self.blocks)
         arr = (GrmhdBlock * n)()
+        (us, ws, bs), (ua, _, ba), (uo, wo, bo) = self._set(src), self._set(0), self._set(dst)
+        if src == dst:
+            ua, ba = us, bs
         for ib in range(n):
-            if key == "s1":
-                arr[ib] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
-                                     self.b0[ib], self.u1[ib], self.b1[ib], self.w1[ib])
-            elif key == "s2":
-                arr[ib] = self._desc(ib, self.w1[ib], self.u0[ib], self.u1[ib], self.b0[ib],
-                                     self.b1[ib], self.u0[ib], self.b0[ib], self.w0[ib])
-            elif key == "fillA":
-                arr[ib] = self._desc(ib, self.w0[ib], self.u0[ib], self.u0[ib], self.b0[ib],
-                                     self.b0[ib], self.u0[ib], self.b0[ib], self.w0[ib])
-            else:
-                arr[ib] = self._desc(ib, self.w1[ib], self.u1[ib], self.u1[ib], self.b1[ib],
-                                     self.b1[ib], self.u1[ib], self.b1[ib], self.w1[ib])
+            arr[ib] = self._desc(ib, ws[ib], ua[ib], us[ib], ba[ib], bs[ib], uo[ib], bo[ib], wo[ib])
         check(load().grmhd_blocks_prepare(C.cast(arr, C.c_void_p), n), "grmhd_blocks_prepare")
         raw = bytes(memoryview(arr).cast("B"))
         dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
         return arr, dev
 
     def _args(self, key):
+        if key not in self.tables:
+            self.tables[key] = self._make_table(key)
         arr, dev = self.tables[key]
         return C.cast(arr, C.c_void_p), C.c_void_p(dev.data_ptr()), len(self.blocks)
 
@@ -345,12 +373,18 @@ class DeviceMesh:
 
     # --- steps --------------------------------------------------------------
     def stage(self, stage, dt=None, dt_dev=None, mlp=None, stats=None):
-        """One stage; mlp (a LearnedC2P) starts the final inversion from the
-        learned bracket, stats (a 4-element int64 device tensor) accumulates
-        its solves, evaluations, fallbacks and failures."""
+        """Stage 1 or 2 of SSP-RK2; mlp (a LearnedC2P) starts the final
+        inversion from the learned bracket, stats (a 4-element int64 device
+        tensor) accumulates its solves, evaluations, fallbacks and failures."""
+        src, dst, coef = self.RK2[stage - 1]
+        self.stage_sets(src, dst, coef, dt=dt, dt_dev=dt_dev, mlp=mlp, stats=stats)
+
+    def stage_sets(self, src, dst, coef, dt=None, dt_dev=None, mlp=None, stats=None):
+        """One stage with coefficients coef = (a0, a1, b) from set src into
+        set dst (dt from dt_dev on the device when given)."""
         L = load()
-        a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
-        key = "s1" if stage == 1 else "s2"
+        a0, a1, b = coef
+        key = (src, dst)
         dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
         dval = float(dt) if dt is not None else 0.0
         if mlp is None and stats is None:
@@ -367,30 +401,36 @@ class DeviceMesh:
         check(rc, "grmhd_stage")
 
     def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
-        key = "fillA" if which == 0 else "fillB"
-        check(load().grmhd_ghost_fill(*self._args(key), mask, self.sp()), "grmhd_ghost_fill")
+        """ghosts of state set which (0 A, 1 B, 2 C)"""
+        check(load().grmhd_ghost_fill(*self._args((which, which)), mask, self.sp()),
+              "grmhd_ghost_fill")
 
     def compute_dt(self, cfl):
         """dt on device (kept in self.dt_dev)."""
-        rc = load().grmhd_dt(*self._args("fillA"), C.byref(self.params.c()), cfl,
+        rc = load().grmhd_dt(*self._args((0, 0)), C.byref(self.params.c()), cfl,
                              C.c_void_p(self.red.data_ptr()), C.c_void_p(self.dt_dev.data_ptr()),
                              self.sp())
         check(rc, "grmhd_dt")
         return self.dt_dev
 
-    def rk2_step(self, dt=None, cfl=0.25, mlp=None, stats=None):
-        """One SSP-RK2 step; dt from the device CFL reduction when dt is None;
-        mlp/stats as for stage()."""
+    def rk_step(self, scheme, dt=None, cfl=0.25, mlp=None, stats=None):
+        """One step of `scheme` (RK2 or RK3); dt from the device CFL reduction
+        when dt is None; the ghosts of each stage's output are filled before
+        the next stage; mlp/stats as for stage()."""
         if dt is None:
             self.compute_dt(cfl)
-            self.stage(1, dt_dev=self.dt_dev, mlp=mlp, stats=stats)
-            self.ghost_fill(1)
-            self.stage(2, dt_dev=self.dt_dev, mlp=mlp, stats=stats)
+            kw = dict(dt_dev=self.dt_dev)
         else:
-            self.stage(1, dt=dt, mlp=mlp, stats=stats)
-            self.ghost_fill(1)
-            self.stage(2, dt=dt, mlp=mlp, stats=stats)
-        self.ghost_fill(0)
+            kw = dict(dt=dt)
+        for src, dst, coef in scheme:
+            self.stage_sets(src, dst, coef, mlp=mlp, stats=stats, **kw)
+            self.ghost_fill(dst)
+
+    def rk2_step(self, dt=None, cfl=0.25, mlp=None, stats=None):
+        self.rk_step(self.RK2, dt=dt, cfl=cfl, mlp=mlp, stats=stats)
+
+    def rk3_step(self, dt=None, cfl=0.25, mlp=None, stats=None):
+        self.rk_step(self.RK3, dt=dt, cfl=cfl, mlp=mlp, stats=stats)
 
     def rk2_step_per_block(self, dt=None, cfl=0.25):
         """The same RK2 step launched block by block (one-block tables): the
@@ -429,7 +469,7 @@ class DeviceMesh:
                                     dval, a0, a1, b, self.sp()), "grmhd_stage")
 
     def mass(self):
-        check(load().grmhd_mass(*self._args("fillA"), C.c_void_p(self.mass_part.data_ptr()),
+        check(load().grmhd_mass(*self._args((0, 0)), C.c_void_p(self.mass_part.data_ptr()),
                                 C.c_void_p(self.mass_out.data_ptr()), self.sp()), "grmhd_mass")
         return self.mass_out
 
@@ -438,7 +478,7 @@ class DeviceMesh:
         """mode bits: 1 fluxes, 2 FOFC, 4 CT, 8 update, 16 C2P (host dt)."""
         L = load()
         a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
-        args = self._args("s1" if stage == 1 else "s2")
+        args = self._args((0, 1) if stage == 1 else (1, 0))
         pc = C.byref(self.params.c())
         if mode & 1:
             check(L.grmhd_fluxes(*args, pc, self.sp()), "grmhd_fluxes")

@@ -165,3 +165,23 @@ def test_orders_of_accuracy_on_a_sine(kind, max_order, l1_order):
     o1 = math.log2(e[1][1] / e[2][1])
     assert max_order[0] < om < max_order[1], (e, om)
     assert l1_order[0] < o1 < l1_order[1], (e, o1)
+
+
+def test_ppmx_branch_jumps_at_an_exact_tie_and_ppm4_does_not():
+    """A plateau of two exactly equal cells S between low values (a mirror-
+    symmetric profile two cells wide, as at the rim of a star centred on a
+    cell face).  PPMX's extremum test is the sign of (q[i+1] - q[i]) (q[i] -
+    q[i-1]): at the tie the first plateau cell is an extremum and is kept flat;
+    one ulp more in its right neighbour makes the data monotone, and the
+    overshoot rule moves its lower edge to about 2/3 S.  PPM4's limited slopes
+    are continuous there, so its edges move by rounding only."""
+    low, S = 1.0e-13, 8.5e-6
+    base = np.array([low, low, S, S, low])
+    up = base.copy()
+    up[3] = np.nextafter(S, 1.0)
+    lo_tie = O.recon_edges(PPMX, base[None])[0][0]
+    lo_up = O.recon_edges(PPMX, up[None])[0][0]
+    assert lo_tie == S
+    assert abs(lo_up - 2.0 / 3.0 * S) < 0.05 * S, lo_up
+    lo4 = [O.recon_edges(PPM4, q[None])[0][0] for q in (base, up)]
+    assert abs(lo4[0] - lo4[1]) <= 4 * np.spacing(S), lo4
