@@ -58,24 +58,26 @@ inline void eos_dispatch(int type, F&& f) {
   else f(std::integral_constant<int, 1>{});
 }
 
-__device__ __forceinline__ int eos_piece(const Eos& e, double rho) {
-  int i = 0;
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-    if (t + 1 < e.n && rho >= e.rb[t]) i = t + 1;
-  return i;
-}
+struct Cold { double p, e, g; };   // P_cold, eps_cold, Gamma of the piece
 
-struct Cold { double p, e, g; };   // P_cold, eps_cold, index of the piece
-
+// The piece's constants are picked by selection, not by indexing the arrays
+// with a runtime piece number: an indexed struct member cannot live in
+// registers and would put the whole Eos in private (scratch) memory.
 __device__ __forceinline__ Cold eos_cold(const Eos& e, double rho) {
   Cold c{0.0, 0.0, 1.0};
   if (e.type == 1) {
-    int i = eos_piece(e, rho);
-    double gi = e.G[i];
-    double pr = e.K[i] * pow(rho, gi);
+    double gi = e.G[0], ki = e.K[0], ai = e.a[0];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t + 1 < e.n && rho >= e.rb[t]) {
+        gi = e.G[t + 1];
+        ki = e.K[t + 1];
+        ai = e.a[t + 1];
+      }
+    }
+    const double pr = ki * pow(rho, gi);
     c.p = pr;
-    c.e = e.a[i] + pr / (rho * (gi - 1.0));
+    c.e = ai + pr / (rho * (gi - 1.0));
     c.g = gi;
   }
   return c;
