@@ -22,6 +22,57 @@ __host__ __device__ __forceinline__ Geo geo_of(const grmhd_block& b) {
   q.sx = b.nx + 2 * b.ng; q.sy = b.ny + 2 * b.ng; q.sz = b.nz + 2 * b.ng;
   return q;
 }
+
+// A pointer into global memory (address space 1).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// Device view of a block: its sizes and arrays, with every array typed as
+// global memory.  Through the plain pointers of the C struct the compiler
+// cannot tell global memory from LDS and emits flat loads, each with its own
+// 64-bit address; through these it emits global loads from a scalar base
+// plus a 32-bit offset.  (The neighbour table and the launch layout stay in
+// the C struct, read from there where needed.)
+struct GB {
+  int nx, ny, nz, ng;
+  double dx[3];
+  gptr<double> w[5], un[5], us[5], bn[3], bs[3], uo[5], bo[3], wo[5];
+  gptr<const double> adm[16];
+  gptr<uint16_t> flags;
+  gptr<double> scratch;
+};
+
+__device__ __forceinline__ GB gview(const grmhd_block& b) {
+  GB g;
+  g.nx = b.nx; g.ny = b.ny; g.nz = b.nz; g.ng = b.ng;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g.dx[a] = b.dx[a];
+    g.bn[a] = (gptr<double>)b.bn[a];
+    g.bs[a] = (gptr<double>)b.bs[a];
+    g.bo[a] = (gptr<double>)b.bo[a];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    g.w[v] = (gptr<double>)b.w[v];
+    g.un[v] = (gptr<double>)b.un[v];
+    g.us[v] = (gptr<double>)b.us[v];
+    g.uo[v] = (gptr<double>)b.uo[v];
+    g.wo[v] = (gptr<double>)b.wo[v];
+  }
+#pragma unroll
+  for (int n = 0; n < 16; ++n) g.adm[n] = (gptr<const double>)b.adm[n];
+  g.flags = (gptr<uint16_t>)b.flags;
+  g.scratch = (gptr<double>)b.scratch;
+  return g;
+}
+
+__device__ __forceinline__ Geo geo_of(const GB& b) {
+  Geo q;
+  q.nx = b.nx; q.ny = b.ny; q.nz = b.nz; q.g = b.ng;
+  q.sx = b.nx + 2 * b.ng; q.sy = b.ny + 2 * b.ng; q.sz = b.nz + 2 * b.ng;
+  return q;
+}
 __host__ __device__ __forceinline__ int64_t n_cells(const Geo& q) {
   return (int64_t)q.sx * q.sy * q.sz;
 }
@@ -79,17 +130,17 @@ __host__ __device__ __forceinline__ int64_t off_fofc(const Geo& q) {
 __host__ __device__ __forceinline__ int64_t scratch_total(const Geo& q) {
   return off_fofc(q) + (fofc_cap(q) + 2 + 1) / 2;
 }
-__device__ __forceinline__ unsigned int* fofc_count(const grmhd_block& b, const Geo& q) {
-  return (unsigned int*)(b.scratch + off_fofc(q));
+__device__ __forceinline__ gptr<unsigned int> fofc_count(const GB& b, const Geo& q) {
+  return (gptr<unsigned int>)(b.scratch + off_fofc(q));
 }
-__device__ __forceinline__ int* fofc_list(const grmhd_block& b, const Geo& q) {
-  return (int*)(b.scratch + off_fofc(q)) + 2;
+__device__ __forceinline__ gptr<int> fofc_list(const GB& b, const Geo& q) {
+  return (gptr<int>)(b.scratch + off_fofc(q)) + 2;
 }
 
 // Sum (solves, evaluations, fallbacks, failures) over the wave and store it
 // in the block's per-wave slot (lane 0; item index t of the interior shape).
 // Inactive lanes must not call this; every lane of a live wave does.
-__device__ __forceinline__ void wave_stats_store(const grmhd_block& b, const Geo& q, int64_t t,
+__device__ __forceinline__ void wave_stats_store(const GB& b, const Geo& q, int64_t t,
                                                  unsigned long long n, unsigned long long ev,
                                                  unsigned long long fb, unsigned long long fail) {
 #pragma unroll
@@ -100,7 +151,7 @@ __device__ __forceinline__ void wave_stats_store(const grmhd_block& b, const Geo
     fail += __shfl_xor(fail, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    unsigned long long* ws = (unsigned long long*)(b.scratch + off_wstat(q)) + 4 * (t >> 6);
+    gptr<unsigned long long> ws = (gptr<unsigned long long>)(b.scratch + off_wstat(q)) + 4 * (t >> 6);
     ws[0] = n; ws[1] = ev; ws[2] = fb; ws[3] = fail;
   }
 }
@@ -108,14 +159,14 @@ __device__ __forceinline__ void wave_stats_store(const grmhd_block& b, const Geo
 // Append cell c to the block's FOFC list when `take`; all lanes of the wave
 // belong to one block.  One atomic per wave; entries beyond the capacity are
 // dropped (cannot happen when the counter is cleared every stage).
-__device__ __forceinline__ void fofc_append(const grmhd_block& b, const Geo& q, bool take,
+__device__ __forceinline__ void fofc_append(const GB& b, const Geo& q, bool take,
                                             int64_t c) {
   const unsigned long long m = __ballot(take);
   if (!m) return;
   const int lane = threadIdx.x & 63;
   const int leader = __ffsll((long long)m) - 1;
   unsigned int base = 0;
-  if (lane == leader) base = atomicAdd(fofc_count(b, q), (unsigned int)__popcll(m));
+  if (lane == leader) base = atomicAdd((unsigned int*)fofc_count(b, q), (unsigned int)__popcll(m));
   base = __shfl(base, leader, 64);
   if (take) {
     const unsigned int below = (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
@@ -171,6 +222,11 @@ __host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
 // contiguous range of tiles (its y/z stencil neighbours then share that L2):
 // L -> start(L % 8) + L / 8, a bijection of [0, N) for any N.
 constexpr int kXcds = 8;
+// rows per y tile of the stencil kernels' item order (Box::at_ytiled)
+#ifndef GRMHD_TILE_Y
+#define GRMHD_TILE_Y 16
+#endif
+constexpr int kTileY = GRMHD_TILE_Y;
 __device__ __forceinline__ int xcd_linear() {
   const int n = gridDim.x;
   const int L = blockIdx.x;
@@ -210,6 +266,29 @@ struct Box {
     j = lo[1] + (int)(r % cnt[1]);
     k = lo[2] + (int)(r / cnt[1]);
   }
+  // The same items in y-tiled order: x fastest, then y inside a tile of TY
+  // rows, then z, then the tile (the last tile may be shorter).  The rows in
+  // flight on an XCD then span many z planes of one narrow tile, so the z
+  // neighbours a stencil reads are still in L2 when they are used again.
+  // Items per block stay below 2^31, so 32-bit division suffices.
+  template <int TY>
+  __device__ __forceinline__ void at_ytiled(int64_t t64, int& i, int& j, int& k) const {
+    const int t = (int)t64;
+    const int nx = cnt[0], ny = cnt[1], nz = cnt[2];
+    const int full = ny / TY;
+    const int per_tile = TY * nz * nx;
+    int jt = full, rows = ny - full * TY, rem = t - full * per_tile;
+    if (t < full * per_tile) {
+      jt = t / per_tile;
+      rows = TY;
+      rem = t - jt * per_tile;
+    }
+    const int row = rem / nx;
+    const int kk = row / rows;
+    i = lo[0] + (rem - row * nx);
+    j = lo[1] + jt * TY + (row - kk * rows);
+    k = lo[2] + kk;
+  }
 };
 
 // extended face range of direction D: faces [g, g+n_D] along D, cells
@@ -236,12 +315,13 @@ __device__ __forceinline__ double dt_of(const double* dt_d, double dt) {
   return dt_d ? *dt_d : dt;
 }
 
-__device__ __forceinline__ void cell_metric(const grmhd_block& b, int64_t c, M3& m) {
+__device__ __forceinline__ void cell_metric(const GB& b, int64_t c, M3& m) {
   metric_build(m, b.adm[4][c], b.adm[5][c], b.adm[6][c], b.adm[7][c], b.adm[8][c], b.adm[9][c]);
 }
 
 // densitized cell-centred field from the faces of slot f
-__device__ __forceinline__ void cell_bt(const Geo& q, double* const f[3], int i, int j, int k,
+template <class P>
+__device__ __forceinline__ void cell_bt(const Geo& q, const P* f, int i, int j, int k,
                                         double Bt[3]) {
   Bt[0] = 0.5 * (f[0][face<0>(q, i, j, k)] + f[0][face<0>(q, i + 1, j, k)]);
   Bt[1] = 0.5 * (f[1][face<1>(q, i, j, k)] + f[1][face<1>(q, i, j + 1, k)]);

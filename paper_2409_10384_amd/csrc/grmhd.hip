@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
   int bi;
   int64_t t;
   if (!locate(blks, S_CELLS, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
   // face i+1 exists for every cell of the padded block
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
   cell_metric(b, t, m);
   double Bt[3];
   cell_bt(q, b.bs, i, j, k, Bt);
-  double* out = b.scratch + off_bcc(q);
+  gptr<double> out = b.scratch + off_bcc(q);
   const int64_t nc = n_cells(q);
   const double is = 1.0 / m.sg;
   out[t] = Bt[0] * is;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
 // ---------------------------------------------------------------------------
 template <int D, int RC>
 __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
-                                          const grmhd_block& b, const Geo& q, int i, int j, int k,
+                                          const GB& b, const Geo& q, int i, int j, int k,
                                           double F[7]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
@@ -59,15 +59,15 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   double gf[10];
 #pragma unroll
   for (int n = 0; n < 10; ++n) {
-    const double* a = b.adm[n];
+    gptr<const double> a = b.adm[n];
     gf[n] = (9.0 * (a[c0 - st] + a[c0]) - (a[c0 - 2 * st] + a[c0 + st])) * (1.0 / 16.0);
   }
   M3 m;
   metric_build(m, gf[4], gf[5], gf[6], gf[7], gf[8], gf[9]);
-  const double* bcc = b.scratch + off_bcc(q);
+  gptr<const double> bcc = b.scratch + off_bcc(q);
   const int64_t nc = n_cells(q);
-  const double* bt1 = bcc + T1 * nc;
-  const double* bt2 = bcc + T2 * nc;
+  const gptr<const double> bt1 = bcc + T1 * nc;
+  const gptr<const double> bt2 = bcc + T2 * nc;
   double qL[7], qR[7];
   // Donor cell is also reached at run time in the high-order variants (where
   // p.recon == RC, so it is never taken): with the reconstruction loop in a
@@ -82,10 +82,10 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
     qL[5] = bt1[c0 - st]; qR[5] = bt1[c0];
     qL[6] = bt2[c0 - st]; qR[6] = bt2[c0];
   } else {
-    const double* src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
+    gptr<const double> src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
-      const double* a = src[v];
+      const gptr<const double> a = src[v];
       recon_face<RC>(a[c0 - 3 * st], a[c0 - 2 * st], a[c0 - st], a[c0], a[c0 + st],
                      a[c0 + 2 * st], qL[v], qR[v]);
     }
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restr
   int bi;
   int64_t t;
   if (!locate(blks, S_XFACE + D, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const Box bx = face_box<D>(q);
   int i, j, k;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restr
   face_flux<D, RC>(e, p, b, q, i, j, k, F);
   const int64_t f = face<D>(q, i, j, k);
   const int64_t nf = n_faces(q, D);
-  double* out = b.scratch + off_flux(q, D, 0);
+  gptr<double> out = b.scratch + off_flux(q, D, 0);
 #pragma unroll
   for (int c = 0; c < 7; ++c) out[c * nf + f] = F[c];
 }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_clear_flags(const grmhd_block* 
   int bi;
   int64_t t;
   if (!locate(blks, S_CELLS, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   if (t < n_cells(q)) b.flags[t] = 0;
   if (t == 0) *fofc_count(b, q) = 0u;
@@ -143,11 +143,11 @@ __device__ __forceinline__ void dmp_range(double mn, double mx, double M, double
   hi = mx >= 0.0 ? mx * M : mx / M;
 }
 
-__device__ __forceinline__ double flux_div(const grmhd_block& b, const Geo& q, int v, int i, int j,
+__device__ __forceinline__ double flux_div(const GB& b, const Geo& q, int v, int i, int j,
                                            int k) {
-  const double* fx = b.scratch + off_flux(q, 0, v);
-  const double* fy = b.scratch + off_flux(q, 1, v);
-  const double* fz = b.scratch + off_flux(q, 2, v);
+  gptr<const double> fx = b.scratch + off_flux(q, 0, v);
+  gptr<const double> fy = b.scratch + off_flux(q, 1, v);
+  gptr<const double> fz = b.scratch + off_flux(q, 2, v);
   return (fx[face<0>(q, i + 1, j, k)] - fx[face<0>(q, i, j, k)]) / b.dx[0] +
          (fy[face<1>(q, i, j + 1, k)] - fy[face<1>(q, i, j, k)]) / b.dx[1] +
          (fz[face<2>(q, i, j, k + 1)] - fz[face<2>(q, i, j, k)]) / b.dx[2];
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* _
   int bi;
   int64_t t;
   if (!locate(blks, S_INTERIOR, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const Box bx = interior_box(q);
   int i, j, k;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* _
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2) {
       const int v = t2 == 0 ? 0 : 4;
-      const double* a = b.us[v];
+      gptr<const double> a = b.us[v];
       double mn = a[c], mx = a[c];
       for (int dk = -1; dk <= 1; ++dk)
         for (int dj = -1; dj <= 1; ++dj)
@@ -218,11 +218,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_flags(const grmhd_block* _
 // too (it owns that face as its lower one), so each face is written once
 template <int D>
 __device__ __forceinline__ void fofc_cell_faces(const Eos& e, const grmhd_params& p,
-                                                const grmhd_block& b, const Geo& q, int x[3]) {
+                                                const GB& b, const Geo& q, int x[3]) {
   const int n[3] = {q.nx, q.ny, q.nz};
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
   const int64_t nf = n_faces(q, D);
-  double* out = b.scratch + off_flux(q, D, 0);
+  gptr<double> out = b.scratch + off_flux(q, D, 0);
   double F[7];
   if (x[D] >= q.g) {
     face_flux<D, 0>(e, p, b, q, x[0], x[1], x[2], F);
@@ -252,11 +252,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_fofc_fix(const grmhd_block* __r
                                                        grmhd_params p, int chunks) {
   const Eos e = eos_fixed<ET>(e_in);
   const int bi = blockIdx.x / chunks, r = blockIdx.x % chunks;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int64_t cnt_raw = (int64_t)*fofc_count(b, q);
   const int64_t cnt = cnt_raw < fofc_cap(q) ? cnt_raw : fofc_cap(q);
-  const int* list = fofc_list(b, q);
+  gptr<const int> list = fofc_list(b, q);
   for (int64_t ei = (int64_t)r * blockDim.x + threadIdx.x; ei < cnt;
        ei += (int64_t)chunks * blockDim.x) {
     const int64_t c = list[ei];
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_cc(const grmhd_block* __res
   int bi;
   int64_t t;
   if (!locate(blks, S_EXT, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   Box bx;
   bx.lo[0] = bx.lo[1] = bx.lo[2] = q.g - 1;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_cc(const grmhd_block* __res
   const double vz = uz * iW - b.adm[3][c] * ia;
   double Bt[3];
   cell_bt(q, b.bs, i, j, k, Bt);
-  double* E = b.scratch + off_ecc(q);
+  gptr<double> E = b.scratch + off_ecc(q);
   const int64_t nc = n_cells(q);
   E[c] = -al * (vy * Bt[2] - vz * Bt[1]);
   E[nc + c] = -al * (vz * Bt[0] - vx * Bt[2]);
@@ -312,11 +312,11 @@ __device__ __forceinline__ double upwind(double mflux, double from_neg, double f
 
 // EMF component C on a face of direction FD (from the stored transverse-field fluxes)
 template <int FD, int C>
-__device__ __forceinline__ double face_emf(const double* sc, const Geo& q, int64_t f) {
+__device__ __forceinline__ double face_emf(gptr<const double> sc, const Geo& q, int64_t f) {
   constexpr int T1 = (FD + 1) % 3, T2 = (FD + 2) % 3;
   static_assert(C == T1 || C == T2, "EMF component must be transverse to the face");
   const int64_t nf = n_faces(q, FD);
-  const double* F = sc + off_flux(q, FD, 0);
+  const gptr<const double> F = sc + off_flux(q, FD, 0);
   if (C == T2) return -F[5 * nf + f];
   return F[6 * nf + f];
 }
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_edge(const grmhd_block* __r
   int bi;
   int64_t t;
   if (!locate(blks, S_XEDGE + C, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int n[3] = {q.nx, q.ny, q.nz};
   Box bx;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_edge(const grmhd_block* __r
   }
   int x[3];
   bx.at(t, x[0], x[1], x[2]);
-  const double* sc = b.scratch;
+  gptr<const double> sc = b.scratch;
   // cells (a,b), (a-1,b), (a,b-1), (a-1,b-1)
   int p00[3] = {x[0], x[1], x[2]};
   int p10[3] = {x[0], x[1], x[2]};
@@ -357,10 +357,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_edge(const grmhd_block* __r
   const double EA_bm = face_emf<A, C>(sc, q, fa_bm);
   const double EB_a = face_emf<BX, C>(sc, q, fb_a);
   const double EB_am = face_emf<BX, C>(sc, q, fb_am);
-  const double* mA = sc + off_flux(q, A, 0);
-  const double* mB = sc + off_flux(q, BX, 0);
+  gptr<const double> mA = sc + off_flux(q, A, 0);
+  gptr<const double> mB = sc + off_flux(q, BX, 0);
   const double mA_b = mA[fa_b], mA_bm = mA[fa_bm], mB_a = mB[fb_a], mB_am = mB[fb_am];
-  const double* Ec = sc + off_ecc(q) + C * n_cells(q);
+  gptr<const double> Ec = sc + off_ecc(q) + C * n_cells(q);
   const double E00 = Ec[cell(q, p00[0], p00[1], p00[2])];
   const double E10 = Ec[cell(q, p10[0], p10[1], p10[2])];
   const double E01 = Ec[cell(q, p01[0], p01[1], p01[2])];
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_edge(const grmhd_block* __r
   const double db_lo = upwind(mA_bm, EB_am - E11, EB_a - E01);
   const double da_hi = upwind(mB_a, E01 - EA_bm, E00 - EA_b);
   const double da_lo = upwind(mB_am, EA_bm - E11, EA_b - E10);
-  double* Ee = b.scratch + off_edge(q) + C * n_edges(q);
+  gptr<double> Ee = b.scratch + off_edge(q) + C * n_edges(q);
   Ee[edge(q, x[0], x[1], x[2])] =
       0.25 * (EA_b + EA_bm + EB_a + EB_am) + 0.25 * (db_lo - db_hi + da_lo - da_hi);
 }
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_ct_face(const grmhd_block* __re
   int bi;
   int64_t t;
   if (!locate(blks, S_XIFACE + D, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int n[3] = {q.nx, q.ny, q.nz};
   Box bx;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_ct_face(const grmhd_block* __re
   int x[3];
   bx.at(t, x[0], x[1], x[2]);
   const double dt = dt_of(dt_d, dt_h);
-  const double* Ee = b.scratch + off_edge(q);
+  gptr<const double> Ee = b.scratch + off_edge(q);
   const int64_t ne = n_edges(q);
   int x1[3] = {x[0], x[1], x[2]}, x2[3] = {x[0], x[1], x[2]};
   x1[D1] += 1;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_ct_face(const grmhd_block* __re
 // ---------------------------------------------------------------------------
 // a6: update with the Eq. 10 sources of the stage input
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double dcen(const double* a, int64_t c, int64_t st, double idx12) {
+__device__ __forceinline__ double dcen(gptr<const double> a, int64_t c, int64_t st, double idx12) {
   return ((a[c - 2 * st] - a[c + 2 * st]) - 8.0 * (a[c - st] - a[c + st])) * idx12;
 }
 
@@ -422,13 +422,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
   int bi;
   int64_t t;
   if (!locate(blks, S_INTERIOR, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
-  const Box bx = interior_box(q);
   int i, j, k;
-  bx.at(t, i, j, k);
-  const double dt = dt_of(dt_d, dt_h);
+  interior_box(q).at(t, i, j, k);
   const int64_t c = cell(q, i, j, k);
+  const double dt = dt_of(dt_d, dt_h);
   const int64_t strides[3] = {1, (int64_t)q.sx, (int64_t)q.sx * q.sy};
   M3 m;
   cell_metric(b, c, m);
@@ -473,23 +472,37 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
   const double Et = Us[4] + Us[0];
   double G[5];
   G[0] = 0.0;
+  G[1] = G[2] = G[3] = 0.0;
   double gt = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int64_t st = strides[d];
-    const double idx12 = 1.0 / (12.0 * b.dx[d]);
-    const double dal = dcen(b.adm[0], c, st, idx12);
-    double t1 = 0.0;
-#pragma unroll
-    for (int s6 = 0; s6 < 6; ++s6) {
-      const double w6 = (s6 == 1 || s6 == 2 || s6 == 4) ? 2.0 : 1.0;
-      t1 += w6 * S[s6] * dcen(b.adm[4 + s6], c, st, idx12);
+  const double idx12[3] = {1.0 / (12.0 * b.dx[0]), 1.0 / (12.0 * b.dx[1]), 1.0 / (12.0 * b.dx[2])};
+  // One metric field at a time, in a loop that is not unrolled: unrolled, the
+  // compiler issues the 120 stencil loads of the ten fields together and
+  // holds them in registers (two waves per SIMD instead of four).  Field f's
+  // gradient enters G[1..3] with coefficient -E (alpha), S~_a (beta^a) or
+  // alpha S~^{jk}/2 (gamma_jk, the off-diagonal ones twice); the alpha
+  // gradient also enters the tau source.
+#pragma unroll 1
+  for (int f = 0; f < 10; ++f) {
+    double cf;
+    if (f == 0) {
+      cf = -Et;
+    } else if (f < 4) {
+      cf = f == 1 ? Us[1] : (f == 2 ? Us[2] : Us[3]);
+    } else {
+      const int s6 = f - 4;
+      const double Sv = s6 == 0 ? S[0] : s6 == 1 ? S[1] : s6 == 2 ? S[2] : s6 == 3 ? S[3]
+                                                                        : s6 == 4 ? S[4] : S[5];
+      cf = 0.5 * alpha * ((s6 == 1 || s6 == 2 || s6 == 4) ? 2.0 : 1.0) * Sv;
     }
-    double t2 = 0.0;
+    const gptr<const double> a = (gptr<const double>)blks[bi].adm[f];
+    double gr[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) t2 += Us[1 + a] * dcen(b.adm[1 + a], c, st, idx12);
-    G[1 + d] = 0.5 * alpha * t1 + t2 - Et * dal;
-    gt -= Su[d] * dal;
+    for (int d = 0; d < 3; ++d) gr[d] = dcen(a, c, strides[d], idx12[d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      G[1 + d] += cf * gr[d];
+      if (f == 0) gt -= Su[d] * gr[d];
+    }
   }
   double kS = 0.0;
 #pragma unroll
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __
   const bool live = locate(blks, S_INTERIOR, bi, t);   // no early return: wave sums below
   unsigned long long c_n = 0, c_ev = 0, c_fail = 0;
   if (live) {
-    const grmhd_block& b = blks[bi];
+    const GB b = gview(blks[bi]);
     const Geo q = geo_of(b);
     const Box bx = interior_box(q);
     int i, j, k;
@@ -564,7 +577,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_stage_c2p(const grmhd_block* __
   // per-wave sums into the block's scratch (summed by k_stats_sum): no
   // global atomics per wave
   if (stats && __shfl((int)live, 0, 64)) {
-    const grmhd_block& b = blks[bi];
+    const GB b = gview(blks[bi]);
     wave_stats_store(b, geo_of(b), t, c_n, c_ev, 0ull, c_fail);
   }
 }
@@ -663,15 +676,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* 
   int ib;
   int64_t t;
   if (!locate(blks, S_CELLS, ib, t)) return;
-  const grmhd_block& b = blks[ib];
-  if (b.bc == 0) return;
+  const GB b = gview(blks[ib]);
+  if (blks[ib].bc == 0) return;
   const Geo q = geo_of(b);
   int x[3] = {(int)(t % q.sx), (int)((t / q.sx) % q.sy), (int)(t / ((int64_t)q.sx * q.sy))};
   const bool shell = x[0] >= q.g - 1 && x[0] <= q.g + q.nx && x[1] >= q.g - 1 &&
                      x[1] <= q.g + q.ny && x[2] >= q.g - 1 && x[2] <= q.g + q.nz;
   int sb;
   if (!ghost_src(blks, ib, -1, x, sb)) return;
-  const grmhd_block& s = blks[sb];
+  const GB s = gview(blks[sb]);
   const Geo qs = geo_of(s);
   const int64_t src = cell(qs, x[0], x[1], x[2]);
   if (mask & 1)
@@ -692,16 +705,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_ghost_faces(const grmhd_block* 
   int ib;
   int64_t t;
   if (!locate(blks, S_XPFACE + d, ib, t)) return;
-  const grmhd_block& b = blks[ib];
-  if (b.bc == 0) return;
-  const Geo q = geo_of(b);
+  if (blks[ib].bc == 0) return;
+  const Geo q = geo_of(blks[ib]);
   const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
   int x[3] = {(int)(t % ex), (int)((t / ex) % ey), (int)(t / ((int64_t)ex * ey))};
   int sb;
   if (!ghost_src(blks, ib, d, x, sb)) return;
-  const grmhd_block& s = blks[sb];
-  const Geo qs = geo_of(s);
-  b.bs[d][t] = s.bs[d][face_rt(qs, d, x[0], x[1], x[2])];
+  // the face direction is a runtime value: index the C struct's arrays
+  // (an indexed copy of the view would live in scratch memory)
+  const Geo qs = geo_of(blks[sb]);
+  const gptr<const double> src = (gptr<const double>)blks[sb].bs[d];
+  ((gptr<double>)blks[ib].bs[d])[t] = src[face_rt(qs, d, x[0], x[1], x[2])];
 }
 
 // ---------------------------------------------------------------------------
@@ -726,7 +740,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restric
   const bool live = locate(blks, S_INTERIOR, bi, t);   // no early return: barrier below
   double s = 0.0;
   if (live) {
-    const grmhd_block& b = blks[bi];
+    const GB b = gview(blks[bi]);
     const Geo q = geo_of(b);
     const Box bx = interior_box(q);
     int i, j, k;
@@ -806,7 +820,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_p2c_block(const grmhd_block* __
   int bi;
   int64_t t;
   if (!locate(blks, S_CELLS, bi, t)) return;
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
   M3 m;

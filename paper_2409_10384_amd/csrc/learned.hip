@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kT) void k_stage_c2p_learned(const grmhd_block* __r
   int bi = 0;
   int64_t t = 0;
   const bool live = locate(blks, S_INTERIOR, bi, t);
-  const grmhd_block& b = blks[bi];
+  const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   int i = 0, j = 0, k = 0;
   int64_t c = 0;

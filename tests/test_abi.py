@@ -131,3 +131,4 @@ def test_launch_layout_covers_every_item_once():
                     seen[b][t] += 1
             for s in seen:
                 assert np.all(s == 1), cls
+
