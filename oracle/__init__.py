@@ -22,7 +22,7 @@ _lib = None
 
 # flag bits (per-cell uint16)
 F_C2P_FAIL, F_DFLOOR, F_TAUFLOOR, F_MAGCAP, F_TFLOOR, F_RHOFLOOR, F_FOFC, F_DMP, \
-    F_BRACKET_FALLBACK, F_MAXIT = [1 << b for b in range(10)]
+    F_BRACKET_FALLBACK, F_MAXIT, F_EXCISED = [1 << b for b in range(11)]
 F_FLOORS = F_C2P_FAIL | F_DFLOOR | F_TAUFLOOR | F_MAGCAP | F_TFLOOR | F_RHOFLOOR | F_MAXIT
 GF_W, GF_US, GF_BS, GF_FLAGS = 1, 2, 4, 8
 
@@ -156,6 +156,20 @@ def c2p(u, bt, gam, params: Params, blo=None, bhi=None):
                  flags.ctypes.data_as(C.POINTER(C.c_uint16)), C.byref(params.c()), lo, hi,
                  nev.ctypes.data_as(C.POINTER(C.c_int32)), _pd(mu))
     return u, w, flags, nev, mu
+
+
+def matter_sources(w, bt, gam, params: Params):
+    """ADM matter sources (E, S_x, S_y, S_z, S_xx, S_xy, S_xz, S_yy, S_yz, S_zz)
+    of n points: w (5, n), densitized cell-centred field bt (3, n), gamma_ij
+    (6, n); returns (10, n), not densitized."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    bt = np.ascontiguousarray(bt, dtype=np.float64)
+    gam = np.ascontiguousarray(gam, dtype=np.float64)
+    n = w.shape[1]
+    out = np.zeros((10, n))
+    lib().or_matter_sources(C.c_int64(n), _ptrs(w), _ptrs(bt), _ptrs(gam), _ptrs(out),
+                            C.byref(params.c()))
+    return out
 
 
 def master(u, bt, gam, mu, params: Params):
@@ -341,11 +355,23 @@ class Mesh:
         src, dst, (a0, a1, b) = self.RK2[stage - 1]
         self.stage_sets(src, dst, dt, a0, a1, b)
 
+    # lapse below which the stage output is excised (0: no excision)
+    alpha_excise = 0.0
+
+    def excise(self, which, alpha_min):
+        """atmosphere in the interior cells of state set `which` where the lapse
+        is below alpha_min (field unchanged; flagged F_EXCISED)"""
+        arr = self.stage_descs(which, which)
+        lib().or_excise(arr, len(self.blocks), C.byref(self.params.c()), C.c_double(alpha_min))
+
     def rk_step(self, scheme, dt):
-        """one step of the Shu-Osher scheme `scheme` (RK2 or RK3), ghosts of
-        each stage's output filled before the next stage"""
+        """one step of the Shu-Osher scheme `scheme` (RK2 or RK3), each stage's
+        output excised (when alpha_excise > 0) and its ghosts filled before the
+        next stage"""
         for src, dst, (a0, a1, b) in scheme:
             self.stage_sets(src, dst, dt, a0, a1, b)
+            if self.alpha_excise > 0.0:
+                self.excise(dst, self.alpha_excise)
             self.ghost_fill_state(dst)
 
     def rk3_step(self, dt=None, cfl=0.25):

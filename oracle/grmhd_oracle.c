@@ -31,6 +31,9 @@
  *                      maximum principle, Eq. 12 (Sec. III-C)
  *   C2P                master function of Kastaun et al. 2021 in mu = 1/(hW),
  *                      bracketed with Brent's method (Sec. III-D)
+ *   matter sources     E, S_i, S_ij of the stress-energy tensor for the
+ *                      spacetime coupling (Sec. III-A, Eq. 2, 5, 8)
+ *   excision           atmosphere where alpha < alpha_min (Sec. IV)
  *
  * Readings where the paper is silent are listed in the design notes of the
  * repository (face metric by 4th-order Lagrange interpolation, 4th-order
@@ -68,7 +71,7 @@ typedef struct {
 enum {
   F_C2P_FAIL = 1 << 0, F_DFLOOR = 1 << 1, F_TAUFLOOR = 1 << 2, F_MAGCAP = 1 << 3,
   F_TFLOOR = 1 << 4, F_RHOFLOOR = 1 << 5, F_FOFC = 1 << 6, F_DMP = 1 << 7,
-  F_BRACKET_FALLBACK = 1 << 8, F_MAXIT = 1 << 9
+  F_BRACKET_FALLBACK = 1 << 8, F_MAXIT = 1 << 9, F_EXCISED = 1 << 10
 };
 #define F_FLOORS (F_C2P_FAIL | F_DFLOOR | F_TAUFLOOR | F_MAGCAP | F_TFLOOR | F_RHOFLOOR | F_MAXIT)
 
@@ -236,6 +239,49 @@ static void p2c_point(const eos_t *e, const met3 *m, const double w[5], const do
   U[2] = m->sg * S[1];
   U[3] = m->sg * S[2];
   U[4] = m->sg * tau;
+}
+
+/* ------------------------------------------------------------------------- */
+/* ADM matter sources of the spacetime coupling (Sec. III-A: the Z4c          */
+/* equations are driven by the fluid's stress-energy tensor, Eq. 2 with the   */
+/* metric of Eq. 5 and b^mu of Eq. 8, projected on the slice with the unit    */
+/* normal n):                                                                 */
+/*   E    = n_mu n_nu T^{mu nu}            energy density of the normal frame */
+/*   S_i  = -gamma_i^mu n^nu T_{mu nu}     momentum density                   */
+/*   S_ij = gamma_i^mu gamma_j^nu T_{mu nu} stress                            */
+/* With n_mu u^mu = -W, n_mu b^mu = -W (B.v) and the projection of b on the   */
+/* slice b_i = B_i / W + W (B.v) v_i:                                         */
+/*   E    = (rho h + b^2) W^2 - (P + b^2/2) - W^2 (B.v)^2                     */
+/*   S_i  = (rho h + b^2) W^2 v_i - W (B.v) b_i                               */
+/*   S_ij = (rho h + b^2) W^2 v_i v_j + (P + b^2/2) gamma_ij - b_i b_j        */
+/* out = (E, S_x, S_y, S_z, S_xx, S_xy, S_xz, S_yy, S_yz, S_zz), not          */
+/* densitized.                                                                */
+/* ------------------------------------------------------------------------- */
+static void matter_point(const eos_t *e, const met3 *m, const double w[5], const double Bt[3],
+                         double out[10]) {
+  double rho = w[0], P = w[4];
+  double u[3] = {w[1], w[2], w[3]};
+  double B[3] = {Bt[0] / m->sg, Bt[1] / m->sg, Bt[2] / m->sg};
+  double ul[3];
+  lower3(m, u, ul);
+  double W = sqrt(1.0 + dot3(u, ul));
+  double vl[3] = {ul[0] / W, ul[1] / W, ul[2] / W};
+  double Bl[3];
+  lower3(m, B, Bl);
+  double B2 = dot3(B, Bl), Bv = dot3(B, vl);
+  double h = 1.0 + eos_eps_P(e, rho, P) + P / rho;
+  double b2 = B2 / (W * W) + Bv * Bv;
+  double ew = (rho * h + b2) * W * W;
+  double pt = P + 0.5 * b2;
+  double bl[3];
+  for (int i = 0; i < 3; ++i) bl[i] = Bl[i] / W + W * Bv * vl[i];
+  out[0] = ew - pt - W * W * Bv * Bv;
+  for (int i = 0; i < 3; ++i) out[1 + i] = ew * vl[i] - W * Bv * bl[i];
+  static const int sym[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  for (int s6 = 0; s6 < 6; ++s6) {
+    int i = sym[s6][0], j = sym[s6][1];
+    out[4 + s6] = ew * vl[i] * vl[j] + pt * m->g[i][j] - bl[i] * bl[j];
+  }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1383,6 +1429,34 @@ int or_stage_c2p(or_block *blks, int nblk, const or_params *p) {
   return 0;
 }
 
+/* Lapse excision (Sec. IV, the collapse runs): interior cells of the stage
+   output with alpha < alpha_min get the atmosphere primitives (rho_atm, v = 0,
+   T_atm) and the conserved state of those primitives with the unchanged
+   field; flagged F_EXCISED. */
+int or_excise(or_block *blks, int nblk, const or_params *p, double alpha_min) {
+  eos_t e;
+  eos_setup(p, &e);
+  for (int ib = 0; ib < nblk; ++ib) {
+    or_block *b = &blks[ib];
+    int g = b->ng;
+    for (int k = g; k < g + b->nz; ++k)
+      for (int j = g; j < g + b->ny; ++j)
+        for (int i = g; i < g + b->nx; ++i) {
+          int64_t c = cidx(b, i, j, k);
+          if (!(b->adm[0][c] < alpha_min)) continue;
+          met3 m;
+          cell_metric(b, c, &m);
+          double w[5], Bt[3], U[5];
+          atmosphere_prims(&e, p, w);
+          cell_bt(b, b->bo, i, j, k, Bt);
+          p2c_point(&e, &m, w, Bt, U);
+          for (int v = 0; v < 5; ++v) { b->uo[v][c] = U[v]; b->wo[v][c] = w[v]; }
+          b->flags[c] = (uint16_t)(b->flags[c] | F_EXCISED);
+        }
+  }
+  return 0;
+}
+
 /* flux workspace of a block list: 21 face arrays per block */
 static double **alloc_fluxes(const or_block *blks, int nblk) {
   double **F = (double **)calloc((size_t)nblk * 21, sizeof(double *));
@@ -1501,6 +1575,24 @@ int or_prim2con(int64_t n, double *const w[5], double *const bt[3], double *cons
     met_set(&m, s);
     p2c_point(&e, &m, ww, B, U);
     for (int q = 0; q < 5; ++q) u[q][x] = U[q];
+  }
+  return 0;
+}
+
+/* ADM matter sources of n points (see matter_point); out[10] arrays */
+int or_matter_sources(int64_t n, double *const w[5], double *const bt[3], double *const gam[6],
+                      double *out[10], const or_params *p) {
+  eos_t e;
+  eos_setup(p, &e);
+  for (int64_t x = 0; x < n; ++x) {
+    double s[6], ww[5], B[3], o[10];
+    for (int q = 0; q < 6; ++q) s[q] = gam[q][x];
+    for (int q = 0; q < 5; ++q) ww[q] = w[q][x];
+    for (int q = 0; q < 3; ++q) B[q] = bt[q][x];
+    met3 m;
+    met_set(&m, s);
+    matter_point(&e, &m, ww, B, o);
+    for (int q = 0; q < 10; ++q) out[q][x] = o[q];
   }
   return 0;
 }

@@ -79,3 +79,18 @@ def fluxes(st, d):
     dual = np.outer(b, u) - np.outer(u, b)
     FB = sg4 * dual[1:, j]   # flux of B~^i in direction j: sqrt(-g) *F^{ij}
     return F, FB
+
+
+def adm_projections(st):
+    """E = n_mu n_nu T^{mu nu}, S_i = -gamma_i^mu n^nu T_{mu nu} and
+    S_ij = gamma_i^mu gamma_j^nu T_{mu nu}, by 4x4 algebra with n_mu = (-alpha, 0)."""
+    g, T = st["g"], st["T"]
+    alpha = 1.0 / st["n_up"][0]
+    n_dn = np.array([-alpha, 0.0, 0.0, 0.0])
+    n_up = st["n_up"]
+    T_dn = g @ T @ g
+    proj = np.eye(4) + np.outer(n_up, n_dn)          # gamma^mu_nu
+    E = n_dn @ T @ n_dn
+    S = -(proj.T @ T_dn @ n_up)[1:]
+    Sij = (proj.T @ T_dn @ proj)[1:, 1:]
+    return E, S, Sij
