@@ -56,6 +56,7 @@ extern "C" {
 #define GRMHD_F_DMP             (1u << 7)  /* trial D~ or tau~ broke Eq. 12 */
 #define GRMHD_F_BRACKET_FALLBACK (1u << 8) /* learned bracket missed -> full bracket */
 #define GRMHD_F_MAXIT           (1u << 9)  /* root solve hit the iteration cap */
+#define GRMHD_F_EXCISED         (1u << 10) /* lapse below alpha_min -> atmosphere (grmhd_excise) */
 
 /* Method options (Sec. III-B..III-D). */
 typedef struct grmhd_params {
@@ -251,6 +252,28 @@ int grmhd_stage_c2p_learned(const grmhd_block *blk_h, const grmhd_block *blk_d, 
                             const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
                             void *stream);
 
+/* ADM matter sources for the spacetime coupling (Sec. III-A): the fluid's
+   stress-energy tensor (Eq. 2 with Eq. 5 and 8) projected on the slice with
+   the unit normal n,
+     E = n_mu n_nu T^{mu nu}, S_i = -gamma_i^mu n^nu T_{mu nu},
+     S_ij = gamma_i^mu gamma_j^nu T_{mu nu}   (lower indices, not densitized),
+   at the interior cells of every block from its stage-input primitives w and
+   face field bs.  out_d: device array of 10 * nblk device pointers; entry
+   10 * b + n is a padded cell array of block b (layout of w) that receives
+   component n of (E, S_x, S_y, S_z, S_xx, S_xy, S_xz, S_yy, S_yz, S_zz) at
+   the interior cells; ghost cells are not written.  GRMHD_EINVAL if out_d is
+   NULL. */
+int grmhd_matter_sources(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                         const grmhd_params *p, double *const *out_d, void *stream);
+
+/* Lapse excision (Sec. IV, the collapse runs): interior cells with alpha <
+   alpha_min get the atmosphere primitives (rho_atm, v = 0, T_atm) in wo and
+   the conserved state of those primitives with the unchanged field bo in uo;
+   flag bit 10 is set.  Meant right after a stage, on its outputs.  Does
+   nothing when alpha_min <= 0. */
+int grmhd_excise(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                 const grmhd_params *p, double alpha_min, void *stream);
+
 /* Learned-bracket training support (device memory throughout).
    c2p_mlp_features: standardised features [5][n] (fp32) of the conserved
    states u after the conserved-floor rules and, when w_true != NULL, the
@@ -288,10 +311,11 @@ const char *grmhd_version(void);
    face fluxes x/y/z, 3 FOFC flags, 4 FOFC refluxing, 5 CT, 6 update with
    sources, 7 stage C2P, 8 ghost fill, 9 dt, 10 cell-centred field,
    11 c2p_batch plain, 12 c2p_batch learned, 13 MLP training, 14 MLP
-   bracket kernel, 15 stage C2P with the learned bracket. */
+   bracket kernel, 15 stage C2P with the learned bracket, 16 matter sources,
+   17 excision. */
 int grmhd_timing(int32_t on);
 /* Workgroup size (64..512, a multiple of 64) of a kernel family of the stage
-   (families as for grmhd_timing, 0..10); default 256.  Set by the
+   (families as for grmhd_timing, 0..17); default 256.  Set by the
    autotuner; applies to subsequent launches in this process. */
 int grmhd_set_threads(int32_t family, int32_t threads);
 int grmhd_timing_read(int32_t family, double *ms, int64_t *launches);

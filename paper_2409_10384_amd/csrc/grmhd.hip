@@ -614,6 +614,62 @@ __global__ __launch_bounds__(kThreads) void k_stats_sum(const grmhd_block* __res
 }
 
 // ---------------------------------------------------------------------------
+// ADM matter sources of the interior cells (stage-input w and faces bs) into
+// out[10 * block + n], padded cell arrays
+// ---------------------------------------------------------------------------
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_matter(const grmhd_block* __restrict__ blks, Eos e_in,
+                                                     double* const* __restrict__ out) {
+  const Eos e = eos_fixed<ET>(e_in);
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  const GB b = gview(blks[bi]);
+  const Geo q = geo_of(b);
+  int i, j, k;
+  interior_box(q).at(t, i, j, k);
+  const int64_t c = cell(q, i, j, k);
+  M3 m;
+  cell_metric(b, c, m);
+  double w[5], Bt[3], o[10];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[v] = b.w[v][c];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  matter_sources(e, m, w, Bt, o);
+#pragma unroll
+  for (int n = 0; n < 10; ++n) ((gptr<double>)out[10 * bi + n])[c] = o[n];
+}
+
+// lapse excision of the stage output: atmosphere where alpha < alpha_min,
+// conserved state rebuilt with the unchanged field (Sec. IV)
+template <int ET>
+__global__ __launch_bounds__(kMaxThreads) void k_excise(const grmhd_block* __restrict__ blks, Eos e_in,
+                                                     grmhd_params p, double alpha_min) {
+  const Eos e = eos_fixed<ET>(e_in);
+  int bi;
+  int64_t t;
+  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  const GB b = gview(blks[bi]);
+  const Geo q = geo_of(b);
+  int i, j, k;
+  interior_box(q).at(t, i, j, k);
+  const int64_t c = cell(q, i, j, k);
+  if (!(b.adm[0][c] < alpha_min)) return;
+  M3 m;
+  cell_metric(b, c, m);
+  double w[5], Bt[3], U[5];
+  atmosphere(e, p, w);
+  cell_bt(q, b.bo, i, j, k, Bt);
+  prim_to_cons(e, m, w, Bt, U);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    b.uo[v][c] = U[v];
+    b.wo[v][c] = w[v];
+  }
+  b.flags[c] = (uint16_t)(b.flags[c] | GRMHD_F_EXCISED);
+}
+
+// ---------------------------------------------------------------------------
 // ghost fill (same-level copy, periodic self-neighbour, outflow)
 // ---------------------------------------------------------------------------
 // source of ghost entry x[] of block ib; fd = -1 for cells, else the face
@@ -1006,7 +1062,8 @@ dim3 grid_cls(const grmhd_block* h, int nblk, int cls, int threads) {
 
 // workgroup size per kernel family (64..512, multiple of 64), set by the
 // autotuner through grmhd_set_threads
-int g_threads[kFamilies] = {256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 256};
+int g_threads[kFamilies] = {256, 256, 256, 256, 256, 256, 256, 256, 256,
+                             256, 256, 256, 256, 256, 256, 256, 256, 256};
 inline int tpb(int fam) { return g_threads[fam]; }
 
 // launch layout of a block table: first wave of each block per shape
@@ -1254,6 +1311,39 @@ int grmhd_stage_c2p(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t 
   if (r) return r;
   if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
   run_c2p(blk_h, blk_d, nblk, *p, make_eos(*p), (hipStream_t)stream);
+  return last_err();
+}
+
+int grmhd_matter_sources(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                         const grmhd_params* p, double* const* out_d, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if (!out_d) return GRMHD_EINVAL;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  const Eos e = make_eos(*p);
+  hipStream_t s = (hipStream_t)stream;
+  TIMED(T_MATTER, s);
+  eos_dispatch(e.type, [&](auto et) {
+    k_matter<decltype(et)::value>
+        <<<grid_cls(blk_h, nblk, S_INTERIOR, tpb(T_MATTER)), tpb(T_MATTER), 0, s>>>(blk_d, e, out_d);
+  });
+  return last_err();
+}
+
+int grmhd_excise(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                 const grmhd_params* p, double alpha_min, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  if (!(alpha_min > 0.0)) return GRMHD_OK;
+  const Eos e = make_eos(*p);
+  hipStream_t s = (hipStream_t)stream;
+  TIMED(T_EXCISE, s);
+  eos_dispatch(e.type, [&](auto et) {
+    k_excise<decltype(et)::value>
+        <<<grid_cls(blk_h, nblk, S_INTERIOR, tpb(T_EXCISE)), tpb(T_EXCISE), 0, s>>>(blk_d, e, *p,
+                                                                                    alpha_min);
+  });
   return last_err();
 }
 

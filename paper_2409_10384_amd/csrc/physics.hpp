@@ -430,6 +430,45 @@ inline void recon_dispatch(int rc, F&& f) {
   }
 }
 
+// ADM matter sources for the spacetime coupling (Sec. III-A): the
+// stress-energy tensor of Eq. 2 projected on the slice, from the primitives
+// and the densitized cell-centred field.  out = (E, S_x, S_y, S_z, S_xx,
+// S_xy, S_xz, S_yy, S_yz, S_zz), lower indices, not densitized; with the
+// slice projection of b^mu, b_i = B_i / W + W (B.v) v_i:
+//   E = (rho h + b^2) W^2 - (P + b^2/2) - W^2 (B.v)^2,
+//   S_i = (rho h + b^2) W^2 v_i - W (B.v) b_i,
+//   S_ij = (rho h + b^2) W^2 v_i v_j + (P + b^2/2) gamma_ij - b_i b_j.
+__device__ __forceinline__ void matter_sources(const Eos& e, const M3& m, const double w[5],
+                                               const double Bt[3], double out[10]) {
+  const double is = 1.0 / m.sg;
+  const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+  double ul[3], Bl[3];
+  lower(m.g, w[1], w[2], w[3], ul[0], ul[1], ul[2]);
+  lower(m.g, B[0], B[1], B[2], Bl[0], Bl[1], Bl[2]);
+  const double W = sqrt(1.0 + w[1] * ul[0] + w[2] * ul[1] + w[3] * ul[2]);
+  const double iW = 1.0 / W;
+  const double vl[3] = {ul[0] * iW, ul[1] * iW, ul[2] * iW};
+  const double B2 = B[0] * Bl[0] + B[1] * Bl[1] + B[2] * Bl[2];
+  const double Bv = B[0] * vl[0] + B[1] * vl[1] + B[2] * vl[2];
+  const double rho = w[0], P = w[4];
+  const double h = 1.0 + eos_eps_from_P(e, rho, P) + P / rho;
+  const double b2 = B2 * iW * iW + Bv * Bv;
+  const double ew = (rho * h + b2) * W * W;
+  const double pt = P + 0.5 * b2;
+  const double wbv = W * Bv;
+  double bl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) bl[a] = Bl[a] * iW + wbv * vl[a];
+  out[0] = ew - pt - wbv * wbv;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[1 + a] = ew * vl[a] - wbv * bl[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = a; c < 3; ++c)
+      out[4 + sym(a, c)] = ew * vl[a] * vl[c] + pt * m.g[sym(a, c)] - bl[a] * bl[c];
+}
+
 // atmosphere rules on a reconstructed face state (Sec. III-C)
 __device__ __forceinline__ void floor_face(const Eos& e, const grmhd_params& p, double q[5]) {
   if (q[0] < p.f_thr * p.rho_atm) {

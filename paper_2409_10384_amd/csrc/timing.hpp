@@ -6,13 +6,14 @@
 
 namespace gk {
 
-constexpr int kFamilies = 16;
+constexpr int kFamilies = 18;
 constexpr int kEventPool = 8192;
 
 // kernel families
 enum {
   T_FLUX_X = 0, T_FLUX_Y, T_FLUX_Z, T_FOFC_FLAGS, T_FOFC_FIX, T_CT, T_UPDATE, T_C2P, T_GHOST,
-  T_DT, T_BCC, T_C2P_BATCH, T_C2P_LEARNED, T_MLP_TRAIN, T_MLP_BRACKET, T_STAGE_C2P_LEARNED
+  T_DT, T_BCC, T_C2P_BATCH, T_C2P_LEARNED, T_MLP_TRAIN, T_MLP_BRACKET, T_STAGE_C2P_LEARNED,
+  T_MATTER, T_EXCISE
 };
 
 struct Timing {

@@ -19,7 +19,7 @@ _lib = None
 
 # flag bits
 F_C2P_FAIL, F_DFLOOR, F_TAUFLOOR, F_MAGCAP, F_TFLOOR, F_RHOFLOOR, F_FOFC, F_DMP, \
-    F_BRACKET_FALLBACK, F_MAXIT = [1 << b for b in range(10)]
+    F_BRACKET_FALLBACK, F_MAXIT, F_EXCISED = [1 << b for b in range(11)]
 GF_W, GF_US, GF_BS, GF_FLAGS = 1, 2, 4, 8
 
 
@@ -79,6 +79,8 @@ def load():
     L.grmhd_stage_c2p.argtypes = blk + [C.c_void_p, C.c_void_p]
     L.grmhd_stage_learned.argtypes = stage[:-1] + [C.c_void_p, C.c_void_p, C.c_void_p]
     L.grmhd_stage_c2p_learned.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.grmhd_matter_sources.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.grmhd_excise.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p]
     L.grmhd_prim2con_blocks.argtypes = blk + [C.c_void_p, C.c_void_p]
     L.grmhd_ghost_fill.argtypes = blk + [C.c_int32, C.c_void_p]
     L.grmhd_dt.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -166,7 +168,7 @@ def _ptr_array(ts):
 # ---------------------------------------------------------------------------
 FAMILIES = ["flux_x", "flux_y", "flux_z", "fofc_flags", "fofc_fix", "ct", "update", "stage_c2p",
             "ghost", "dt", "bcc", "c2p_batch", "c2p_learned", "mlp_train", "mlp_bracket",
-            "stage_c2p_learned"]
+            "stage_c2p_learned", "matter", "excise"]
 KERNEL_OF_FAMILY = {"flux_x": "k_flux<0>", "flux_y": "k_flux<1>", "flux_z": "k_flux<2>",
                     "fofc_flags": "k_fofc_flags", "update": "k_update", "stage_c2p": "k_stage_c2p",
                     "dt": "k_dt", "bcc": "k_bcc", "c2p_batch": "k_c2p_batch",
@@ -424,7 +426,32 @@ class DeviceMesh:
             kw = dict(dt=dt)
         for src, dst, coef in scheme:
             self.stage_sets(src, dst, coef, mlp=mlp, stats=stats, **kw)
+            if self.alpha_excise > 0.0:
+                self.excise(dst, self.alpha_excise)
             self.ghost_fill(dst)
+
+    # lapse below which each stage's output is excised (0: no excision)
+    alpha_excise = 0.0
+
+    def excise(self, which, alpha_min):
+        """atmosphere in the interior cells of state set `which` where the lapse
+        is below alpha_min (field unchanged; flag bit F_EXCISED)"""
+        check(load().grmhd_excise(*self._args((which, which)), C.byref(self.params.c()),
+                                  float(alpha_min), self.sp()), "grmhd_excise")
+
+    def matter_sources(self, which=0):
+        """ADM matter sources (E, S_i, S_ij; not densitized) of state set
+        `which` at the interior cells: per block a (10, sz, sy, sx) tensor whose
+        ghost cells are zero"""
+        if getattr(self, "_matter", None) is None:
+            f64 = dict(dtype=torch.float64, device=self.device)
+            self._matter = [torch.zeros((10,) + b.shape, **f64) for b in self.blocks]
+            ptrs = [t[n].data_ptr() for t in self._matter for n in range(10)]
+            self._matter_ptrs = torch.tensor(ptrs, dtype=torch.int64).to(self.device)
+        check(load().grmhd_matter_sources(*self._args((which, which)), C.byref(self.params.c()),
+                                          C.c_void_p(self._matter_ptrs.data_ptr()), self.sp()),
+              "grmhd_matter_sources")
+        return self._matter
 
     def rk2_step(self, dt=None, cfl=0.25, mlp=None, stats=None):
         self.rk_step(self.RK2, dt=dt, cfl=cfl, mlp=mlp, stats=stats)
