@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6          # MI355X FP64 vector peak
+# ADM matter sources per interior cell: w (5), two faces per direction (6) and
+# gamma_ij (6) read, E, S_i, S_ij (10) written
+MATTER_BYTES_PER_CELL = (5 + 6 + 6 + 10) * 8
 
 
 def log(*a):
@@ -208,8 +211,54 @@ def star_section(args, torch, inputs, lib):
             "achieved": sb / (ms / args.steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     path["frac"] = path["achieved"] / HBM_PEAK_GBS
     mass = float(mesh.mass().item())
+    variants = variant_section(args, torch, lib, mesh, params, ncell)
     return dict(value=value, ms=ms, ncell=ncell, roofline=roof, path=path, breakdown=breakdown,
-                st=st, mass=mass, fp64=fp64)
+                st=st, mass=mass, fp64=fp64, variants=variants)
+
+
+def variant_section(args, torch, lib, mesh, params, ncell, steps=3):
+    """After the timed run, on the same resident star: the other
+    reconstructions (flux kernel times and RK2 step rate), the SSP-RK3 step,
+    and the ADM matter-source kernel with its HBM roofline"""
+    import dataclasses
+    out = {"steps": steps, "recon": {}}
+
+    def run(fn, n):
+        lib.timing(True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        fam = lib.timing_read()
+        lib.timing(False)
+        return e0.elapsed_time(e1) / n, fam
+
+    names = {0: "donor_cell", 1: "plm", 2: "wenoz", 3: "ppm4", 4: "ppmx"}
+    for rc in (0, 1, 3, 4, 2):
+        mesh.params = dataclasses.replace(params, recon=rc)
+        mesh.rk2_step(cfl=0.25)
+        ms, fam = run(lambda: mesh.rk2_step(cfl=0.25), steps)
+        flux = {k: fam[k][0] / fam[k][1] for k in ("flux_x", "flux_y", "flux_z") if k in fam}
+        out["recon"][names[rc]] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3),
+                                   "flux_ms_per_launch": flux}
+        log(f"variant {names[rc]}: {ms:.2f} ms per RK2 step, flux {flux}")
+    mesh.params = params
+    ms, _ = run(lambda: mesh.rk3_step(cfl=0.25), steps)
+    out["rk3"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3), "recon": "wenoz"}
+    log(f"variant SSP-RK3: {ms:.2f} ms per step, {ncell / (ms * 1e-3):.3e} zone-updates/s")
+    mesh.matter_sources(0)
+    ms, fam = run(lambda: mesh.matter_sources(0), 10)
+    mms = fam["matter"][0] / fam["matter"][1]
+    nbytes = MATTER_BYTES_PER_CELL * ncell
+    ach = nbytes / (mms * 1e-3) / 1e9
+    out["matter_sources"] = {"ms_per_launch": mms, "bytes_per_launch": nbytes, "achieved": ach,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    log(f"matter sources: {mms:.3f} ms per launch, {ach:.0f} GB/s")
+    return out
 
 
 def refined_section(args, torch, inputs, lib):
@@ -594,6 +643,7 @@ def main():
         "path_roofline": star["path"],
         "fp64_rate": star["fp64"],
         "kernel_breakdown": star["breakdown"],
+        "variants": star["variants"],
     }
     if not args.no_refined:
         out["refined"] = refined_section(args, torch, inputs, lib)
