@@ -211,7 +211,7 @@ def star_section(args, torch, inputs, lib):
             "achieved": sb / (ms / args.steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     path["frac"] = path["achieved"] / HBM_PEAK_GBS
     mass = float(mesh.mass().item())
-    variants = variant_section(args, torch, lib, mesh, params, ncell)
+    variants = None if args.no_variants else variant_section(args, torch, lib, mesh, params, ncell)
     return dict(value=value, ms=ms, ncell=ncell, roofline=roof, path=path, breakdown=breakdown,
                 st=st, mass=mass, fp64=fp64, variants=variants)
 
@@ -583,6 +583,8 @@ def main():
     ap.add_argument("--refined-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the end-to-end refined star section")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the reconstruction / RK3 / matter-source measurements on the star")
     ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")
     ap.add_argument("--c5-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
