@@ -162,6 +162,11 @@ def star_section(args, torch, inputs, lib):
     torch.cuda.synchronize()
     log(f"mesh resident in HBM ({time.perf_counter() - t0:.1f} s)")
     ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2409_10384_amd import autotune
+        dt0 = float(mesh.compute_dt(0.25).item())
+        tuned = {k: v["best"] for k, v in autotune.autotune(mesh, dt0, log=log).items()}
     for _ in range(args.warmup):
         mesh.rk2_step(cfl=0.25)
     torch.cuda.synchronize()
@@ -212,8 +217,10 @@ def star_section(args, torch, inputs, lib):
     path["frac"] = path["achieved"] / HBM_PEAK_GBS
     mass = float(mesh.mass().item())
     variants = None if args.no_variants else variant_section(args, torch, lib, mesh, params, ncell)
+    if tuned:
+        autotune.reset()
     return dict(value=value, ms=ms, ncell=ncell, roofline=roof, path=path, breakdown=breakdown,
-                st=st, mass=mass, fp64=fp64, variants=variants)
+                st=st, mass=mass, fp64=fp64, variants=variants, workgroup_sizes=tuned)
 
 
 def variant_section(args, torch, lib, mesh, params, ncell, steps=3):
@@ -583,6 +590,8 @@ def main():
     ap.add_argument("--refined-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the end-to-end refined star section")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default workgroup size (256) for the star instead of autotuning it")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the reconstruction / RK3 / matter-source measurements on the star")
     ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")
@@ -640,7 +649,7 @@ def main():
         "config": {"workload": f"star {args.blocks_per_side * args.block}^3 as "
                                f"{args.blocks_per_side ** 3} MeshBlocks of {args.block}^3 (+3 ghosts), "
                                f"Gamma=2, WENOZ+HLLE, FOFC+DMP M=1.1, SSP-RK2 CFL 0.25",
-                   "cells": star["ncell"]},
+                   "cells": star["ncell"], "workgroup_sizes": star["workgroup_sizes"]},
         "roofline": star["roofline"],
         "path_roofline": star["path"],
         "fp64_rate": star["fp64"],
