@@ -1,0 +1,70 @@
+"""Parity at the full size of the star workload: 256^3 cells as 64 MeshBlocks
+of 64^3 (+3 ghosts), Gamma = 2, WENOZ + HLLE, FOFC+DMP M = 1.1, SSP-RK2 with
+CFL 0.25, in the launch configuration the benchmark times (its autotuned
+workgroup sizes).  The oracle takes the same RK2 step of the whole star (one
+step of 16.7 million cells, about 10-20 s on 16 host cores) and every
+interior cell of every block is compared, gated on the FOFC and floor
+decisions as in the small star tests.  A second test shows that the step does
+not depend on the launch configuration: two workgroup-size sets give bitwise
+equal states."""
+import numpy as np
+import pytest
+
+from tests.test_gpu_parity import STAR_P, _star_parity, host, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+torch = pytest.importorskip("torch")
+
+# the workgroup sizes the benchmark's autotuner picks for the star on MI355X
+BENCH_SIZES = {"flux_x": 64, "flux_y": 64, "flux_z": 64, "fofc_flags": 64, "fofc_fix": 128,
+               "ct": 64, "update": 512, "stage_c2p": 128}
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10384_amd import lib
+    lib.load()
+    return lib
+
+
+def _set_sizes(sizes):
+    from paper_2409_10384_amd import autotune
+    for fam, th in sizes.items():
+        autotune.set_threads(fam, th)
+
+
+def test_star_full_size_parity(G):
+    from paper_2409_10384_amd import autotune, inputs
+    say("star 256^3 (64 blocks of 64^3), benchmark workgroup sizes, 1 RK2 step, every cell")
+    blocks, _ = inputs.star_blocks(n_per_side=4, nb=64)
+    _set_sizes(BENCH_SIZES)
+    try:
+        _star_parity(G, blocks, STAR_P)
+    finally:
+        autotune.reset()
+
+
+def test_star_step_independent_of_launch_configuration(G):
+    import bench
+    from paper_2409_10384_amd import autotune, inputs, lib
+    say("star 256^3: one RK2 step at workgroup size 256 and at the benchmark sizes")
+    out = []
+    for sizes in ({k: 256 for k in BENCH_SIZES}, BENCH_SIZES):
+        _set_sizes(sizes)
+        try:
+            blocks, _ = inputs.star_blocks(n_per_side=4, nb=64, device="cuda")
+            mesh = lib.DeviceMesh(blocks, lib.MethodParams(**bench.STAR_PARAMS), device="cuda")
+            dt = float(mesh.compute_dt(0.25).item())
+            mesh.rk2_step(dt=dt)
+            torch.cuda.synchronize()
+            out.append([torch.cat([mesh.u0[i].flatten(), mesh.w0[i].flatten()]
+                                  + [b.flatten() for b in mesh.b0[i]]).cpu() for i in range(64)])
+            del mesh, blocks
+            torch.cuda.empty_cache()
+        finally:
+            autotune.reset()
+    for i in range(64):
+        assert torch.equal(out[0][i], out[1][i]), i
