@@ -163,7 +163,17 @@ def star_section(args, torch, inputs, lib):
     log(f"mesh resident in HBM ({time.perf_counter() - t0:.1f} s)")
     ncell = sum(b.nx * b.ny * b.nz for b in blocks)
     tuned = None
-    if not args.no_autotune:
+    if args.threads:
+        # fixed workgroup sizes (profiled runs: the autotuner's timings are not
+        # meaningful under counter collection)
+        from paper_2409_10384_amd import autotune
+        tuned = {}
+        for item in args.threads.split(","):
+            fam, th = item.split("=")
+            autotune.set_threads(fam, int(th))
+            tuned[fam] = int(th)
+        log(f"workgroup sizes set: {tuned}")
+    elif not args.no_autotune:
         from paper_2409_10384_amd import autotune
         dt0 = float(mesh.compute_dt(0.25).item())
         tuned = {k: v["best"] for k, v in autotune.autotune(mesh, dt0, log=log).items()}
@@ -592,6 +602,8 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the end-to-end refined star section")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default workgroup size (256) for the star instead of autotuning it")
+    ap.add_argument("--threads", default="",
+                    help="fixed star workgroup sizes instead of autotuning, e.g. update=512,flux_x=64")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the reconstruction / RK3 / matter-source measurements on the star")
     ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")

@@ -222,11 +222,6 @@ __host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
 // contiguous range of tiles (its y/z stencil neighbours then share that L2):
 // L -> start(L % 8) + L / 8, a bijection of [0, N) for any N.
 constexpr int kXcds = 8;
-// rows per y tile of the stencil kernels' item order (Box::at_ytiled)
-#ifndef GRMHD_TILE_Y
-#define GRMHD_TILE_Y 16
-#endif
-constexpr int kTileY = GRMHD_TILE_Y;
 __device__ __forceinline__ int xcd_linear() {
   const int n = gridDim.x;
   const int L = blockIdx.x;
@@ -265,29 +260,6 @@ struct Box {
     const int64_t r = t / cnt[0];
     j = lo[1] + (int)(r % cnt[1]);
     k = lo[2] + (int)(r / cnt[1]);
-  }
-  // The same items in y-tiled order: x fastest, then y inside a tile of TY
-  // rows, then z, then the tile (the last tile may be shorter).  The rows in
-  // flight on an XCD then span many z planes of one narrow tile, so the z
-  // neighbours a stencil reads are still in L2 when they are used again.
-  // Items per block stay below 2^31, so 32-bit division suffices.
-  template <int TY>
-  __device__ __forceinline__ void at_ytiled(int64_t t64, int& i, int& j, int& k) const {
-    const int t = (int)t64;
-    const int nx = cnt[0], ny = cnt[1], nz = cnt[2];
-    const int full = ny / TY;
-    const int per_tile = TY * nz * nx;
-    int jt = full, rows = ny - full * TY, rem = t - full * per_tile;
-    if (t < full * per_tile) {
-      jt = t / per_tile;
-      rows = TY;
-      rem = t - jt * per_tile;
-    }
-    const int row = rem / nx;
-    const int kk = row / rows;
-    i = lo[0] + (rem - row * nx);
-    j = lo[1] + jt * TY + (row - kk * rows);
-    k = lo[2] + kk;
   }
 };
 

@@ -414,18 +414,60 @@ __device__ __forceinline__ double dcen(gptr<const double> a, int64_t c, int64_t 
   return ((a[c - 2 * st] - a[c + 2 * st]) - 8.0 * (a[c - st] - a[c + st])) * idx12;
 }
 
-template <int ET>
+// Brick layout of the update, for block lists whose blocks are all kBrickW
+// cells wide with ny a multiple of kBrickY and nz a multiple of kBrickZ,
+// launched with kMaxThreads-thread workgroups: a workgroup is a brick of
+// kBrickY x kBrickZ x rows (wave w on row j0 + w % kBrickY of plane
+// k0 + w / kBrickY, lane = x), bricks ordered y fastest, then z.  The metric
+// fields pass through LDS one at a time: each wave stores its own row with
+// its four x ghosts and three of the brick's 24 halo rows (two rows beyond it
+// in y on each of its planes, two planes beyond it in z on each of its rows),
+// so every neighbour of the gradient stencil is read from LDS: the stencils
+// take 5 vector-memory loads per field and wave instead of 10.
+constexpr int kBrickW = 64;
+constexpr int kBrickY = 2;
+constexpr int kBrickZ = kMaxThreads / 64 / kBrickY;
+constexpr int kBrickPitch = kBrickW + 4;
+constexpr int kBrickPlane = (kBrickY + 4) * kBrickPitch;
+constexpr int kBrickHalo = 4 * kBrickZ + 4 * kBrickY;   // y halo rows + z halo rows
+static_assert(kBrickHalo == 3 * (kMaxThreads / 64), "three halo rows per wave");
+
+// block and brick of this workgroup in the brick layout (uniform over it)
+__device__ __forceinline__ void locate_brick(const grmhd_block* __restrict__ blks, int& bi,
+                                             int& brick) {
+  const int w = __builtin_amdgcn_readfirstlane(xcd_linear() * (kMaxThreads / 64));
+  const int nb = blks[0].nblk;
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blks[mid].wave0[S_INTERIOR] <= w) lo = mid; else hi = mid - 1;
+  }
+  bi = lo;
+  brick = (w - blks[bi].wave0[S_INTERIOR]) / (kMaxThreads / 64);
+}
+
+template <int ET, bool BRICK>
 __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __restrict__ blks, Eos e_in,
                                                      const double* dt_d, double dt_h, double a0,
                                                      double a1, double bb) {
   const Eos e = eos_fixed<ET>(e_in);
   int bi;
-  int64_t t;
-  if (!locate(blks, S_INTERIOR, bi, t)) return;
+  int i, j, k;
+  if constexpr (BRICK) {
+    int brick;
+    locate_brick(blks, bi, brick);
+    const int by = blks[bi].ny / kBrickY, g0 = blks[bi].ng;
+    const int w = (int)(threadIdx.x >> 6);
+    i = g0 + (int)(threadIdx.x & 63);
+    j = g0 + (brick % by) * kBrickY + w % kBrickY;
+    k = g0 + (brick / by) * kBrickZ + w / kBrickY;
+  } else {
+    int64_t t;
+    if (!locate(blks, S_INTERIOR, bi, t)) return;
+    interior_box(geo_of(blks[bi])).at(t, i, j, k);
+  }
   const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
-  int i, j, k;
-  interior_box(q).at(t, i, j, k);
   const int64_t c = cell(q, i, j, k);
   const double dt = dt_of(dt_d, dt_h);
   const int64_t strides[3] = {1, (int64_t)q.sx, (int64_t)q.sx * q.sy};
@@ -496,8 +538,57 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
     }
     const gptr<const double> a = (gptr<const double>)blks[bi].adm[f];
     double gr[3];
+    if constexpr (BRICK) {
+      // tile[z][y][x] over planes k0-2..k0+kBrickZ+1, rows j0-2..j0+kBrickY+1
+      __shared__ double tile[(kBrickZ + 4) * kBrickPlane];
+      const int lane = threadIdx.x & 63;
+      const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+      const int wy = w % kBrickY, wz = w / kBrickY;
+      const int64_t py = strides[1], pz = strides[2];
+      const int64_t c0 = c - wy * py - wz * pz;   // the brick's first row, this lane's x
+      const double v0 = a[c];
+      double vx = 0.0;
+      // lanes 0..3 fetch the row's x ghosts -2, -1, 64, 65
+      const int xo = lane < 2 ? lane - 2 : kBrickW - 2 + lane;
+      if (lane < 4) vx = a[c - lane + xo];
+      // three halo rows: h < 4 kBrickZ are the y halo (plane h / 4, rows
+      // -2, -1, kBrickY, kBrickY + 1), the rest the z halo (row (h - 4 kBrickZ)
+      // % kBrickY, planes -2, -1, kBrickZ, kBrickZ + 1)
+      double vh[3];
+      int th[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) gr[d] = dcen(a, c, strides[d], idx12[d]);
+      for (int r = 0; r < 3; ++r) {
+        const int h = w + r * (kMaxThreads / 64);
+        int hy, hz;
+        if (h < 4 * kBrickZ) {
+          const int m = h % 4;
+          hz = h / 4;
+          hy = m < 2 ? m - 2 : kBrickY - 2 + m;
+        } else {
+          const int m = (h - 4 * kBrickZ) / kBrickY;
+          hy = (h - 4 * kBrickZ) % kBrickY;
+          hz = m < 2 ? m - 2 : kBrickZ - 2 + m;
+        }
+        vh[r] = a[c0 + hz * pz + hy * py];
+        th[r] = (hz + 2) * kBrickPlane + (hy + 2) * kBrickPitch + lane + 2;
+      }
+      __syncthreads();  // the previous field's reads of the tile are done
+      double* row = tile + (wz + 2) * kBrickPlane + (wy + 2) * kBrickPitch;
+      row[lane + 2] = v0;
+      if (lane < 4) row[xo + 2] = vx;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) tile[th[r]] = vh[r];
+      __syncthreads();
+      const double* p = row + lane + 2;
+      gr[0] = ((p[-2] - p[2]) - 8.0 * (p[-1] - p[1])) * idx12[0];
+      gr[1] = ((p[-2 * kBrickPitch] - p[2 * kBrickPitch]) -
+               8.0 * (p[-kBrickPitch] - p[kBrickPitch])) * idx12[1];
+      gr[2] = ((p[-2 * kBrickPlane] - p[2 * kBrickPlane]) -
+               8.0 * (p[-kBrickPlane] - p[kBrickPlane])) * idx12[2];
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gr[d] = dcen(a, c, strides[d], idx12[d]);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       G[1 + d] += cf * gr[d];
@@ -1173,11 +1264,32 @@ void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* 
   k_ct_face<2><<<grid_cls(h, nblk, S_XIFACE + 2, tpb(T_CT)), tpb(T_CT), 0, s>>>(d, dt_d, dt, a0, a1, b);
 }
 
+// every block kBrickW cells wide with ny a multiple of kBrickY and nz of
+// kBrickZ (then every block's interior waves, and so every block's first
+// wave, are multiples of the waves per workgroup, and the bricks tile the
+// launch exactly)
+bool brick_layout_fits(const grmhd_block* h, int nblk) {
+  for (int i = 0; i < nblk; ++i)
+    if (h[i].nx != kBrickW || h[i].ny % kBrickY != 0 || h[i].nz % kBrickZ != 0 || h[i].ny < 1 ||
+        h[i].ng < 2)
+      return false;
+  return true;
+}
+
 void run_update(const grmhd_block* h, const grmhd_block* d, int nblk, const Eos& e,
                 const double* dt_d, double dt, double a0, double a1, double b, hipStream_t s) {
   TIMED(T_UPDATE, s);
+  const bool brick = tpb(T_UPDATE) == kMaxThreads && brick_layout_fits(h, nblk);
   eos_dispatch(e.type, [&](auto et) {
-    k_update<decltype(et)::value><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(d, e, dt_d, dt, a0, a1, b);
+    if (brick) {
+      const int64_t waves = (int64_t)h[nblk - 1].wave0[S_INTERIOR] +
+                            shape_items(geo_of(h[nblk - 1]), S_INTERIOR) / 64;
+      k_update<decltype(et)::value, true><<<(unsigned)(waves / (kMaxThreads / 64)), kMaxThreads, 0, s>>>(
+          d, e, dt_d, dt, a0, a1, b);
+    } else {
+      k_update<decltype(et)::value, false><<<grid_cls(h, nblk, S_INTERIOR, tpb(T_UPDATE)), tpb(T_UPDATE), 0, s>>>(
+          d, e, dt_d, dt, a0, a1, b);
+    }
   });
 }
 
