@@ -5,8 +5,9 @@ workgroup sizes).  The oracle takes the same RK2 step of the whole star (one
 step of 16.7 million cells, about 10-20 s on 16 host cores) and every
 interior cell of every block is compared, gated on the FOFC and floor
 decisions as in the small star tests.  A second test shows that the step does
-not depend on the launch configuration: two workgroup-size sets give bitwise
-equal states."""
+not depend on the launch configuration: the row layout at workgroup size 256,
+the brick layout of the update, and the benchmark's sizes give bitwise equal
+states."""
 import numpy as np
 import pytest
 
@@ -47,12 +48,17 @@ def test_star_full_size_parity(G):
         autotune.reset()
 
 
+# the brick layout of the update (512-thread workgroups), the rest at 256
+BRICK_SIZES = {**{k: 256 for k in BENCH_SIZES}, "update": 512}
+
+
 def test_star_step_independent_of_launch_configuration(G):
     import bench
     from paper_2409_10384_amd import autotune, inputs, lib
-    say("star 256^3: one RK2 step at workgroup size 256 and at the benchmark sizes")
+    say("star 256^3: one RK2 step at workgroup size 256, with the brick update and at the "
+        "benchmark sizes")
     out = []
-    for sizes in ({k: 256 for k in BENCH_SIZES}, BENCH_SIZES):
+    for sizes in ({k: 256 for k in BENCH_SIZES}, BRICK_SIZES, BENCH_SIZES):
         _set_sizes(sizes)
         try:
             blocks, _ = inputs.star_blocks(n_per_side=4, nb=64, device="cuda")
@@ -66,5 +72,6 @@ def test_star_step_independent_of_launch_configuration(G):
             torch.cuda.empty_cache()
         finally:
             autotune.reset()
-    for i in range(64):
-        assert torch.equal(out[0][i], out[1][i]), i
+    for other in (1, 2):
+        for i in range(64):
+            assert torch.equal(out[0][i], out[other][i]), (other, i)
