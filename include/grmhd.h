@@ -316,7 +316,11 @@ const char *grmhd_version(void);
 int grmhd_timing(int32_t on);
 /* Workgroup size (64..512, a multiple of 64) of a kernel family of the stage
    (families as for grmhd_timing, 0..17); default 256.  Set by the
-   autotuner; applies to subsequent launches in this process. */
+   autotuner; applies to subsequent launches in this process.  The update
+   (family 6) at 512 on a block list whose blocks are all 64 cells wide, with
+   ny even and nz a multiple of 4, runs in the brick layout (2 rows x 4 planes
+   per workgroup, metric stencils through LDS); its results are bitwise equal
+   to those of any other size. */
 int grmhd_set_threads(int32_t family, int32_t threads);
 int grmhd_timing_read(int32_t family, double *ms, int64_t *launches);
 
