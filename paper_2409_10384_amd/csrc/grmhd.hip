@@ -457,6 +457,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_update(const grmhd_block* __res
     int brick;
     locate_brick(blks, bi, brick);
     const int by = blks[bi].ny / kBrickY, g0 = blks[bi].ng;
+    // uniform over the workgroup: a launch that does not match the layout
+    // returns before any memory access or barrier
+    if (blockDim.x != kMaxThreads || brick < 0 || brick >= by * (blks[bi].nz / kBrickZ)) return;
     const int w = (int)(threadIdx.x >> 6);
     i = g0 + (int)(threadIdx.x & 63);
     j = g0 + (brick % by) * kBrickY + w % kBrickY;
