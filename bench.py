@@ -153,6 +153,26 @@ def cpu_baseline(st, n_per_side, nb, params_kw, target_s=12.0):
                       f"{el:.1f} s, OpenMP over k-slabs"}
 
 
+def copy_bandwidth(torch, lib, n=1 << 27, reps=10):
+    """HBM bandwidth a plain streaming copy reaches here: 1 GiB read and 1 GiB
+    written per k_copy launch, HIP events over `reps` launches (GB/s of bytes
+    read plus written)"""
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    lib.copy(a, b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lib.copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def star_section(args, torch, inputs, lib):
     t0 = time.perf_counter()
     log(f"building inputs: star, {args.blocks_per_side}^3 blocks of {args.block}^3")
@@ -207,6 +227,12 @@ def star_section(args, torch, inputs, lib):
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": pmc_traffic(dom, None), "bytes_per_launch": nbytes,
                 "avg_launch_ms": dms}
+        copy = copy_bandwidth(torch, lib)
+        roof["copy_GBps_measured"] = copy
+        if roof["traffic"]:
+            # the dominant kernel's counted bytes over its launch time, beside
+            # what a plain copy reaches on this GPU
+            roof["traffic_GBps"] = roof["traffic"] / (dms * 1e-3) / 1e9
     # FP64 rate of every stage kernel from the committed FP64 instruction
     # counters (operations per launch) and the launch times measured here
     fp64 = None
