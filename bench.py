@@ -638,8 +638,9 @@ def main():
                     help="run one 1 GiB plain copy first (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the stage shards by MeshBlocks; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the stage would shard by MeshBlocks, with a halo exchange per stage)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

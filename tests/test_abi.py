@@ -132,3 +132,15 @@ def test_launch_layout_covers_every_item_once():
             for s in seen:
                 assert np.all(s == 1), cls
 
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """the benchmark measures one GPU: --gpus above 1 exits with a message
+    (before touching torch or the GPU)"""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
