@@ -100,17 +100,22 @@ typedef struct grmhd_block {
   int32_t nbr[27];         /* neighbour block per offset (ox+1)+3(oy+1)+9(oz+1); -1: none */
   int32_t bc;              /* 0 ghosts frozen (untouched); 1 filled from nbr, outflow if -1 */
   /* launch layout, filled by grmhd_blocks_prepare (do not set by hand):
-     first 64-item wave of this block in each of the 15 launch shapes, and
-     the number of blocks in the table */
-  int32_t wave0[16];
+     first 64-item wave of this block in each of the grmhd_launch_shapes()
+     launch shapes (unused slots zero), and the number of blocks in the
+     table */
+  int32_t wave0[24];
   int32_t nblk;
   int32_t reserved;
 } grmhd_block;
 
-/* Fill the launch-layout fields (wave0, nblk) of a host descriptor table in
-   place.  Call once after the table is built and before it is copied to the
-   device; every block-list entry point checks that the layout is current. */
+/* Fill the launch-layout fields (wave0, nblk, reserved) of a host
+   descriptor table in place; writes nothing else.  Call once after the table
+   is built and before it is copied to the device; every block-list entry
+   point checks that the layout is current.  GRMHD_EINVAL for a NULL table,
+   nblk < 1, a block with a size below 1, or more waves than fit in int32. */
 int grmhd_blocks_prepare(grmhd_block *blk_h, int32_t nblk);
+/* Number of launch shapes, i.e. of used wave0 slots (at most 24). */
+int32_t grmhd_launch_shapes(void);
 
 /* Doubles of per-block scratch needed by the stage: the 21 face-flux arrays
    (7 components D~, S~_xyz, tau~, F(B~^{t1}), F(B~^{t2}) per direction, t1 =
@@ -181,12 +186,16 @@ int grmhd_ghost_fill(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t
 
 /* Step a9: dt_out[0] = cfl / max over interior cells and directions of
    |lambda_+-| / dx_d from the w and bs slots (fast magnetosonic speeds).
-   red: device scratch of one double (overwritten). */
+   red: device scratch of one double (overwritten).  GRMHD_EINVAL for a NULL
+   red or dt_out, cfl <= 0, a stale layout, or a block without w, bs or the
+   metric (adm[0..9]). */
 int grmhd_dt(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
              const grmhd_params *p, double cfl, double *red, double *dt_out, void *stream);
 
 /* Baryon mass sum D~ dV over the interiors of the us slot (deterministic
-   order).  partial: device scratch of nblk doubles; out: one device double. */
+   order).  partial: device scratch of nblk doubles; out: one device double.
+   GRMHD_EINVAL for a NULL partial or out, a stale layout, or a block without
+   us[0]. */
 int grmhd_mass(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
                double *partial, double *out, void *stream);
 

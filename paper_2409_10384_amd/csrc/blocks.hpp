@@ -191,11 +191,100 @@ enum {
   S_XIFACE,       // interior faces of direction x, y, z (CT update)
   S_YIFACE,
   S_ZIFACE,
-  S_XPFACE,       // padded faces of direction x, y, z (ghost fill)
+  S_XPFACE,       // padded faces of direction x, y, z
   S_YPFACE,
   S_ZPFACE,
+  S_GCELLS,       // ghost cells: padded cells minus the interior (ghost fill)
+  S_GSHELL,       // first ghost shell [g-1, g+n]^3 minus the interior (flag exchange)
+  S_GXFACE,       // ghost faces of direction x, y, z: padded faces minus the
+  S_GYFACE,       // interior ones (faces g..g+n along the direction, cells
+  S_GZFACE,       // g..g+n-1 across; ghost-face fill)
   S_COUNT
 };
+// the descriptor's wave0 table has one slot per launch shape
+static_assert(S_COUNT <= (int)(sizeof(((grmhd_block*)0)->wave0) / sizeof(int32_t)),
+              "grmhd_block.wave0 needs a slot for every launch shape");
+
+// A box with a box-shaped hole: the extents e[3] of an outer box, and the
+// hole at offset l[3] (relative to the outer origin) with counts c[3] inside
+// it.  Items run over the outer box minus the hole, x fastest: the planes
+// below the hole, then each plane through the hole (rows below it, the rows
+// through it without the hole's cells, rows above it), then the planes
+// above it.
+struct Ring {
+  int e[3], l[3], c[3];
+  __host__ __device__ __forceinline__ int64_t size() const {
+    return (int64_t)e[0] * e[1] * e[2] - (int64_t)c[0] * c[1] * c[2];
+  }
+  // position (i, j, k) relative to the outer origin of item t < size()
+  __host__ __device__ __forceinline__ void at(int64_t t, int& i, int& j, int& k) const {
+    const int64_t plane = (int64_t)e[0] * e[1];
+    const int64_t below = (int64_t)l[2] * plane;
+    if (t < below) {
+      k = (int)(t / plane);
+      const int64_t r = t - (int64_t)k * plane;
+      j = (int)(r / e[0]);
+      i = (int)(r - (int64_t)j * e[0]);
+      return;
+    }
+    t -= below;
+    const int64_t ring = plane - (int64_t)c[0] * c[1];
+    const int64_t mid = (int64_t)c[2] * ring;
+    if (t >= mid) {
+      t -= mid;
+      const int kk = (int)(t / plane);
+      const int64_t r = t - (int64_t)kk * plane;
+      k = l[2] + c[2] + kk;
+      j = (int)(r / e[0]);
+      i = (int)(r - (int64_t)j * e[0]);
+      return;
+    }
+    const int kk = (int)(t / ring);
+    int64_t r = t - (int64_t)kk * ring;
+    k = l[2] + kk;
+    const int64_t rows_lo = (int64_t)l[1] * e[0];
+    if (r < rows_lo) {
+      j = (int)(r / e[0]);
+      i = (int)(r - (int64_t)j * e[0]);
+      return;
+    }
+    r -= rows_lo;
+    const int side = e[0] - c[0];
+    const int64_t rows_mid = (int64_t)c[1] * side;
+    if (r < rows_mid) {
+      const int jj = (int)(r / side);
+      const int s = (int)(r - (int64_t)jj * side);
+      j = l[1] + jj;
+      i = s < l[0] ? s : s + c[0];
+      return;
+    }
+    r -= rows_mid;
+    const int jj = (int)(r / e[0]);
+    j = l[1] + c[1] + jj;
+    i = (int)(r - (int64_t)jj * e[0]);
+  }
+};
+
+// the ghost region of launch shape cls (S_GCELLS .. S_GZFACE), in padded
+// cell or face coordinates
+__host__ __device__ __forceinline__ Ring ghost_ring(const Geo& q, int cls) {
+  Ring r;
+  const int n[3] = {q.nx, q.ny, q.nz};
+  const int s[3] = {q.sx, q.sy, q.sz};
+  if (cls == S_GSHELL) {
+    // offset g-1 is added by the caller
+    for (int a = 0; a < 3; ++a) { r.e[a] = n[a] + 2; r.l[a] = 1; r.c[a] = n[a]; }
+    return r;
+  }
+  const int d = cls - S_GXFACE;   // -1.. for S_GCELLS: no face direction
+  for (int a = 0; a < 3; ++a) {
+    const int f = (cls != S_GCELLS && a == d) ? 1 : 0;
+    r.e[a] = s[a] + f;
+    r.l[a] = q.g;
+    r.c[a] = n[a] + f;
+  }
+  return r;
+}
 
 __host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
   const int n[3] = {q.nx, q.ny, q.nz};
@@ -213,7 +302,8 @@ __host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
     case S_XIFACE: case S_YIFACE: case S_ZIFACE:
       for (int a = 0; a < 3; ++a) c *= a == cls - S_XIFACE ? n[a] + 1 : n[a];
       return c;
-    default: return n_faces(q, cls - S_XPFACE);
+    case S_XPFACE: case S_YPFACE: case S_ZPFACE: return n_faces(q, cls - S_XPFACE);
+    default: return ghost_ring(q, cls).size();
   }
 }
 

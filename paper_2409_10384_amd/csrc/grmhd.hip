@@ -821,51 +821,61 @@ __device__ __forceinline__ bool ghost_src(const grmhd_block* blks, int ib, int f
 
 // list != 0 (flags exchange of a stage): flagged cells of the first ghost
 // shell [g-1, g+n]^3 are appended to the block's FOFC list
+// Items are the ghost cells only (launch shape S_GCELLS), or, for the flag
+// exchange of a stage (list != 0, flags only), the first ghost shell
+// [g-1, g+n]^3 (S_GSHELL), whose flagged cells are appended to the block's
+// FOFC list; the refluxing reads no flag farther out.
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells(const grmhd_block* __restrict__ blks,
                                                           int mask, int list) {
   int ib;
   int64_t t;
-  if (!locate(blks, S_CELLS, ib, t)) return;
-  const GB b = gview(blks[ib]);
+  const int cls = list ? S_GSHELL : S_GCELLS;
+  if (!locate(blks, cls, ib, t)) return;
   if (blks[ib].bc == 0) return;
+  const GB b = gview(blks[ib]);
   const Geo q = geo_of(b);
-  int x[3] = {(int)(t % q.sx), (int)((t / q.sx) % q.sy), (int)(t / ((int64_t)q.sx * q.sy))};
-  const bool shell = x[0] >= q.g - 1 && x[0] <= q.g + q.nx && x[1] >= q.g - 1 &&
-                     x[1] <= q.g + q.ny && x[2] >= q.g - 1 && x[2] <= q.g + q.nz;
+  int x[3];
+  ghost_ring(q, cls).at(t, x[0], x[1], x[2]);
+  if (list) {
+    x[0] += q.g - 1; x[1] += q.g - 1; x[2] += q.g - 1;
+  }
+  const int64_t c = cell(q, x[0], x[1], x[2]);
   int sb;
-  if (!ghost_src(blks, ib, -1, x, sb)) return;
+  if (!ghost_src(blks, ib, -1, x, sb)) return;   // never taken: every item is a ghost
   const GB s = gview(blks[sb]);
   const Geo qs = geo_of(s);
   const int64_t src = cell(qs, x[0], x[1], x[2]);
   if (mask & 1)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) b.w[v][t] = s.w[v][src];
+    for (int v = 0; v < 5; ++v) b.w[v][c] = s.w[v][src];
   if (mask & 2)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) b.us[v][t] = s.us[v][src];
+    for (int v = 0; v < 5; ++v) b.us[v][c] = s.us[v][src];
   if (mask & 8) {
     const uint16_t f = s.flags[src];
-    b.flags[t] = f;
-    if (list) fofc_append(b, q, shell && (f & (GRMHD_F_FOFC | GRMHD_F_DMP)), t);
+    b.flags[c] = f;
+    if (list) fofc_append(b, q, (f & (GRMHD_F_FOFC | GRMHD_F_DMP)) != 0, c);
   }
 }
 
+// ghost faces of direction d (launch shape S_GXFACE + d)
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_faces(const grmhd_block* __restrict__ blks,
                                                           int d) {
   int ib;
   int64_t t;
-  if (!locate(blks, S_XPFACE + d, ib, t)) return;
+  if (!locate(blks, S_GXFACE + d, ib, t)) return;
   if (blks[ib].bc == 0) return;
   const Geo q = geo_of(blks[ib]);
-  const int ex = q.sx + (d == 0), ey = q.sy + (d == 1);
-  int x[3] = {(int)(t % ex), (int)((t / ex) % ey), (int)(t / ((int64_t)ex * ey))};
+  int x[3];
+  ghost_ring(q, S_GXFACE + d).at(t, x[0], x[1], x[2]);
+  const int64_t f = face_rt(q, d, x[0], x[1], x[2]);
   int sb;
-  if (!ghost_src(blks, ib, d, x, sb)) return;
+  if (!ghost_src(blks, ib, d, x, sb)) return;   // never taken: every item is a ghost
   // the face direction is a runtime value: index the C struct's arrays
   // (an indexed copy of the view would live in scratch memory)
   const Geo qs = geo_of(blks[sb]);
   const gptr<const double> src = (gptr<const double>)blks[sb].bs[d];
-  ((gptr<double>)blks[ib].bs[d])[t] = src[face_rt(qs, d, x[0], x[1], x[2])];
+  ((gptr<double>)blks[ib].bs[d])[f] = src[face_rt(qs, d, x[0], x[1], x[2])];
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,6 +1158,29 @@ int check_blocks(const grmhd_block* h, const grmhd_block* d, int nblk) {
 }
 
 
+// Arrays a pointwise block-list call reads: the layout must be current and
+// every block at least one cell wide with the arrays in `need` set
+// (bits: 1 w, 2 us[0] only, 4 bs, 8 metric adm[0..9], 16 all of us).
+enum { NEED_W = 1, NEED_D = 2, NEED_BS = 4, NEED_ADM = 8, NEED_US = 16 };
+int check_reads(const grmhd_block* h, const grmhd_block* d, int nblk, int need) {
+  if (!h || !d || nblk < 1) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(h), nblk, false) != 0) return GRMHD_EINVAL;
+  for (int i = 0; i < nblk; ++i) {
+    const grmhd_block& b = h[i];
+    if (b.nx < 1 || b.ny < 1 || b.nz < 1 || b.ng < 0) return GRMHD_EINVAL;
+    for (int v = 0; v < 5; ++v) {
+      if ((need & NEED_W) && !b.w[v]) return GRMHD_EINVAL;
+      if ((need & NEED_US) && !b.us[v]) return GRMHD_EINVAL;
+    }
+    if ((need & NEED_D) && !b.us[0]) return GRMHD_EINVAL;
+    for (int v = 0; v < 3; ++v)
+      if ((need & NEED_BS) && !b.bs[v]) return GRMHD_EINVAL;
+    for (int v = 0; v < 10; ++v)
+      if ((need & NEED_ADM) && !b.adm[v]) return GRMHD_EINVAL;
+  }
+  return GRMHD_OK;
+}
+
 // 1-D grid over all 64-item waves of launch shape cls in the block list
 dim3 grid_cls(const grmhd_block* h, int nblk, int cls, int threads) {
   const int64_t waves = (int64_t)h[nblk - 1].wave0[cls] + (shape_items(geo_of(h[nblk - 1]), cls) + 63) / 64;
@@ -1161,6 +1194,7 @@ int g_threads[kFamilies] = {256, 256, 256, 256, 256, 256, 256, 256, 256,
 inline int tpb(int fam) { return g_threads[fam]; }
 
 // launch layout of a block table: first wave of each block per shape
+constexpr int kWaveSlots = (int)(sizeof(((grmhd_block*)0)->wave0) / sizeof(int32_t));
 int64_t prepare_layout(grmhd_block* h, int nblk, bool write) {
   int64_t wave[S_COUNT] = {0};
   for (int i = 0; i < nblk; ++i) {
@@ -1171,8 +1205,13 @@ int64_t prepare_layout(grmhd_block* h, int nblk, bool write) {
       wave[c] += (shape_items(q, c) + 63) / 64;
       if (wave[c] > 0x3fffffff) return -1;
     }
-    if (write) { h[i].wave0[S_COUNT] = 0; h[i].nblk = nblk; h[i].reserved = 0; }
-    else if (h[i].nblk != nblk) return -1;
+    if (write) {
+      for (int c = S_COUNT; c < kWaveSlots; ++c) h[i].wave0[c] = 0;
+      h[i].nblk = nblk;
+      h[i].reserved = 0;
+    } else if (h[i].nblk != nblk) {
+      return -1;
+    }
   }
   return 0;
 }
@@ -1245,7 +1284,7 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   for (int i = 0; i < nblk; ++i) exchange = exchange || h[i].bc == 1;
   if (exchange) {
     TIMED(T_GHOST, s);
-    k_ghost_cells<<<grid_cls(h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8, 1);
+    k_ghost_cells<<<grid_cls(h, nblk, S_GSHELL, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8, 1);
   }
   TIMED(T_FOFC_FIX, s);
   const int chunks = nblk >= 4096 ? 1 : (4096 + nblk - 1) / nblk;
@@ -1526,9 +1565,9 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
   if (!any) return GRMHD_OK;   // every block's ghosts are frozen: nothing to launch
   hipStream_t s = (hipStream_t)stream;
   TIMED(T_GHOST, s);
-  if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11, 0);
+  if (mask & 11) k_ghost_cells<<<grid_cls(blk_h, nblk, S_GCELLS, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, mask & 11, 0);
   if (mask & 4) {
-    for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_cls(blk_h, nblk, S_XPFACE + d, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, d);
+    for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_cls(blk_h, nblk, S_GXFACE + d, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, d);
   }
   return last_err();
 }
@@ -1537,8 +1576,8 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
              const grmhd_params* p, double cfl, double* red, double* dt_out, void* stream) {
   int r = check_params(p);
   if (r) return r;
-  if (!blk_h || !blk_d || nblk < 1 || !red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
-  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
+  if (!red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
+  if ((r = check_reads(blk_h, blk_d, nblk, NEED_W | NEED_BS | NEED_ADM))) return r;
   hipStream_t s = (hipStream_t)stream;
   k_zero1<<<1, 64, 0, s>>>(red);
   {
@@ -1554,7 +1593,9 @@ int grmhd_dt(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
 
 int grmhd_mass(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk, double* partial,
                double* out, void* stream) {
-  if (!blk_h || !blk_d || nblk < 1 || !partial || !out) return GRMHD_EINVAL;
+  if (!partial || !out) return GRMHD_EINVAL;
+  int r = check_reads(blk_h, blk_d, nblk, NEED_D);
+  if (r) return r;
   hipStream_t s = (hipStream_t)stream;
   k_mass_block<<<nblk, kThreads, 0, s>>>(blk_d, partial);
   k_mass_final<<<1, 64, 0, s>>>(partial, nblk, out);
@@ -1601,8 +1642,7 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
                           const grmhd_params* p, void* stream) {
   int r = check_params(p);
   if (r) return r;
-  if (!blk_h || !blk_d || nblk < 1) return GRMHD_EINVAL;
-  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
+  if ((r = check_reads(blk_h, blk_d, nblk, NEED_W | NEED_BS | NEED_ADM | NEED_US))) return r;
   const Eos e = make_eos(*p);
   eos_dispatch(e.type, [&](auto et) {
     k_p2c_block<decltype(et)::value><<<grid_cls(blk_h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0,
@@ -1611,7 +1651,9 @@ int grmhd_prim2con_blocks(const grmhd_block* blk_h, const grmhd_block* blk_d, in
   return last_err();
 }
 
-const char* grmhd_version(void) { return "grmhd 0.1 gfx950 fp64"; }
+const char* grmhd_version(void) { return "grmhd 0.2 gfx950 fp64"; }
+
+int32_t grmhd_launch_shapes(void) { return (int32_t)S_COUNT; }
 
 int grmhd_timing(int32_t on) {
   if (on) {

@@ -48,7 +48,7 @@ class GrmhdBlock(C.Structure):
         ("w", VP * 5), ("un", VP * 5), ("us", VP * 5), ("bn", VP * 3), ("bs", VP * 3),
         ("adm", VP * 16), ("uo", VP * 5), ("bo", VP * 3), ("wo", VP * 5),
         ("flags", VP), ("scratch", VP), ("nbr", C.c_int32 * 27), ("bc", C.c_int32),
-        ("wave0", C.c_int32 * 16), ("nblk", C.c_int32), ("reserved", C.c_int32),
+        ("wave0", C.c_int32 * 24), ("nblk", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

@@ -64,9 +64,60 @@ def test_host_side_argument_checks_reject_bad_input():
     assert L.grmhd_scratch_doubles(n, n, n, g) == expect
 
 
+def test_pointwise_block_calls_reject_missing_arrays():
+    """grmhd_mass, grmhd_dt and grmhd_prim2con_blocks check the arrays their
+    kernels read before launching anything (no GPU is touched)"""
+    from paper_2409_10384_amd import lib
+    L = lib.load()
+    p = lib.MethodParams().c()
+    arr = (lib.GrmhdBlock * 1)()
+    arr[0].nx = arr[0].ny = arr[0].nz = 4
+    arr[0].ng = 3
+    assert L.grmhd_blocks_prepare(ctypes.cast(arr, ctypes.c_void_p), 1) == 0
+    h, d = ctypes.cast(arr, ctypes.c_void_p), ctypes.c_void_p(8)
+    one = ctypes.c_void_p(16)
+    # no us[0]
+    assert L.grmhd_mass(h, d, 1, one, one, None) == -1
+    # no w / bs / metric
+    assert L.grmhd_dt(h, d, 1, ctypes.byref(p), 0.25, one, one, None) == -1
+    for v in range(5):
+        arr[0].w[v] = 64
+    assert L.grmhd_dt(h, d, 1, ctypes.byref(p), 0.25, one, one, None) == -1
+    for v in range(3):
+        arr[0].bs[v] = 64
+    assert L.grmhd_dt(h, d, 1, ctypes.byref(p), 0.25, one, one, None) == -1
+    assert L.grmhd_prim2con_blocks(h, d, 1, ctypes.byref(p), None) == -1
+    # NULL outputs
+    arr[0].us[0] = 64
+    assert L.grmhd_mass(h, d, 1, None, one, None) == -1
+    assert L.grmhd_dt(h, d, 1, ctypes.byref(p), 0.25, None, one, None) == -1
+    assert L.grmhd_dt(h, d, 1, ctypes.byref(p), 0.0, one, one, None) == -1
+    # a stale layout (block 0 resized after prepare, so block 1's first waves
+    # no longer follow) is refused, with every array present
+    two = (lib.GrmhdBlock * 2)()
+    for b in two:
+        b.nx = b.ny = b.nz = 4
+        b.ng = 3
+        b.us[0] = 64
+    assert L.grmhd_blocks_prepare(ctypes.cast(two, ctypes.c_void_p), 2) == 0
+    two[0].nx = 5
+    assert L.grmhd_mass(ctypes.cast(two, ctypes.c_void_p), d, 2, one, one, None) == -1
+
+
 def _shape_items(nx, ny, nz, g, cls):
     n = (nx, ny, nz)
     s = tuple(v + 2 * g for v in n)
+    if cls == 15:   # ghost cells
+        return s[0] * s[1] * s[2] - nx * ny * nz
+    if cls == 16:   # first ghost shell
+        return (nx + 2) * (ny + 2) * (nz + 2) - nx * ny * nz
+    if 17 <= cls <= 19:   # ghost faces
+        d = cls - 17
+        pad = inner = 1
+        for a in range(3):
+            pad *= s[a] + (1 if a == d else 0)
+            inner *= n[a] + (1 if a == d else 0)
+        return pad - inner
     if cls == 0:
         return s[0] * s[1] * s[2]
     if cls == 1:
@@ -106,7 +157,10 @@ def test_launch_layout_covers_every_item_once():
         arr[i].nx, arr[i].ny, arr[i].nz, arr[i].ng = n[0], n[1], n[2], 3
         dims.append(n)
     assert L.grmhd_blocks_prepare(ctypes.cast(arr, ctypes.c_void_p), nb) == 0
-    for cls in range(15):
+    L.grmhd_launch_shapes.restype = ctypes.c_int32
+    nshape = L.grmhd_launch_shapes()
+    assert nshape == 20 and nshape <= len(arr[0].wave0)
+    for cls in range(nshape):
         wave0 = [arr[i].wave0[cls] for i in range(nb)]
         assert arr[0].nblk == nb
         items = [_shape_items(*dims[i], 3, cls) for i in range(nb)]
@@ -132,6 +186,110 @@ def test_launch_layout_covers_every_item_once():
             for s in seen:
                 assert np.all(s == 1), cls
 
+
+
+def test_prepare_writes_only_the_layout_fields():
+    """grmhd_blocks_prepare writes wave0, nblk and reserved of each
+    descriptor and nothing else: every other byte of the table, the next
+    descriptor's sizes included, is unchanged (a layout with more launch
+    shapes than wave0 slots would spill into nblk and the next block)"""
+    import numpy as np
+    from paper_2409_10384_amd import lib
+    L = lib.load()
+    nb = 5
+    arr = (lib.GrmhdBlock * nb)()
+    rng = np.random.default_rng(3)
+    for i in range(nb):
+        arr[i].nx, arr[i].ny, arr[i].nz = (int(x) for x in rng.integers(1, 40, 3))
+        arr[i].ng = 3
+        arr[i].dx = (ctypes.c_double * 3)(0.1 * i, 0.2, 0.3)
+        arr[i].flags = 1000 + i
+        arr[i].scratch = 2000 + i
+        arr[i].nbr = (ctypes.c_int32 * 27)(*[(i + k) % nb for k in range(27)])
+        arr[i].bc = 1
+        for s in range(len(arr[i].wave0)):
+            arr[i].wave0[s] = -7
+        arr[i].nblk = -7
+        arr[i].reserved = -7
+    before = bytearray(memoryview(arr).cast("B"))
+    assert L.grmhd_blocks_prepare(ctypes.cast(arr, ctypes.c_void_p), nb) == 0
+    after = bytearray(memoryview(arr).cast("B"))
+    size = ctypes.sizeof(lib.GrmhdBlock)
+    off_w = lib.GrmhdBlock.wave0.offset
+    end_w = lib.GrmhdBlock.reserved.offset + 4
+    for i in range(nb):
+        b0, a0 = before[i * size:(i + 1) * size], after[i * size:(i + 1) * size]
+        assert b0[:off_w] == a0[:off_w]
+        assert b0[end_w:] == a0[end_w:]
+        assert arr[i].nblk == nb and arr[i].reserved == 0
+        L.grmhd_launch_shapes.restype = ctypes.c_int32
+        ns = L.grmhd_launch_shapes()
+        assert all(arr[i].wave0[s] == 0 for s in range(ns, len(arr[i].wave0)))
+        assert arr[0].wave0[0] == 0
+
+
+_RING_HARNESS = r"""
+#include "blocks.hpp"
+#include <cstdio>
+#include <vector>
+// every item of the ghost launch shapes lies in the padded range, is a
+// ghost entry, and every ghost entry is reached exactly once
+int main() {
+  const int sizes[][3] = {{1, 1, 1}, {2, 5, 3}, {3, 3, 3}, {5, 6, 7}, {16, 16, 16}, {64, 4, 2}};
+  int bad = 0;
+  for (auto& n : sizes) {
+    gk::Geo q;
+    q.nx = n[0]; q.ny = n[1]; q.nz = n[2]; q.g = 3;
+    q.sx = q.nx + 6; q.sy = q.ny + 6; q.sz = q.nz + 6;
+    for (int cls = gk::S_GCELLS; cls <= gk::S_GZFACE; ++cls) {
+      const gk::Ring r = gk::ghost_ring(q, cls);
+      const int d = cls - gk::S_GXFACE;
+      const bool face = cls >= gk::S_GXFACE;
+      int e[3], lo[3], hi[3];   // box of the items; interior [lo, hi]
+      for (int a = 0; a < 3; ++a) {
+        const int f = face && a == d ? 1 : 0;
+        const int na = a == 0 ? q.nx : a == 1 ? q.ny : q.nz;
+        if (cls == gk::S_GSHELL) { e[a] = na + 2; lo[a] = 1; hi[a] = na; }
+        else { e[a] = na + 6 + f; lo[a] = 3; hi[a] = 3 + na - 1 + f; }
+      }
+      std::vector<int> seen((size_t)e[0] * e[1] * e[2], 0);
+      if (r.size() != gk::shape_items(q, cls)) ++bad;
+      for (int64_t t = 0; t < r.size(); ++t) {
+        int i, j, k;
+        r.at(t, i, j, k);
+        if (i < 0 || j < 0 || k < 0 || i >= e[0] || j >= e[1] || k >= e[2]) { ++bad; continue; }
+        const bool in = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1] && k >= lo[2] && k <= hi[2];
+        if (in) ++bad;
+        seen[((size_t)k * e[1] + j) * e[0] + i] += 1;
+      }
+      for (int k = 0; k < e[2]; ++k)
+        for (int j = 0; j < e[1]; ++j)
+          for (int i = 0; i < e[0]; ++i) {
+            const bool in = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1] && k >= lo[2] && k <= hi[2];
+            if (seen[((size_t)k * e[1] + j) * e[0] + i] != (in ? 0 : 1)) ++bad;
+          }
+    }
+  }
+  printf("bad %d\n", bad);
+  return bad != 0;
+}
+"""
+
+
+def test_ghost_launch_shapes_cover_each_ghost_once(tmp_path):
+    """the ghost-only launch shapes (host build of the same header): each
+    item is an in-range ghost cell or face, each ghost reached once"""
+    import subprocess
+    src = tmp_path / "ring.cpp"
+    src.write_text(_RING_HARNESS)
+    exe = tmp_path / "ring"
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    subprocess.check_call([hipcc, "-x", "hip", "--offload-host-only", "-std=c++17", "-O1",
+                           "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2409_10384_amd", "csrc"),
+                           str(src), "-o", str(exe)])
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
 
 
 def test_bench_refuses_more_than_one_gpu():
