@@ -243,6 +243,20 @@ def riemann(riemann_kind, UL, FL, lmL, lpL, UR, FR, lmR, lpR):
     return F
 
 
+def corner_emf(EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a, mB_am, E00, E10, E01, E11):
+    """upwind corner EMF of constrained transport at n points (arrays or
+    scalars): face EMFs and mass fluxes of the two a-faces (at b and b-1) and
+    the two b-faces (at a and a-1), cell-centre EMFs of cells (a, b),
+    (a-1, b), (a, b-1), (a-1, b-1)"""
+    args = [np.atleast_1d(np.asarray(x, dtype=np.float64)) for x in
+            (EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a, mB_am, E00, E10, E01, E11)]
+    args = [np.ascontiguousarray(a) for a in np.broadcast_arrays(*args)]
+    n = args[0].size
+    out = np.zeros(n)
+    lib().or_corner_emf(C.c_int64(n), _ptrs([a.ravel() for a in args]), _pd(out))
+    return out
+
+
 def eos(mode, rho, x, y, params: Params):
     arr = lambda a: np.ascontiguousarray(np.broadcast_to(a, np.shape(rho)), dtype=np.float64)
     rho_a, x_a, y_a = arr(rho), arr(x), arr(y)

@@ -1188,6 +1188,24 @@ static double upwind_pick(double mflux, double up_neg_side, double up_pos_side) 
   return 0.5 * (up_neg_side + up_pos_side);
 }
 
+/* Corner EMF of component c at the edge shared by the cells (a-1, b-1),
+   (a, b-1), (a-1, b), (a, b) of the (a, b) plane ((a, b, c) cyclic).
+   Face EMFs: EA_b, EA_bm on the a-faces at (a-1/2, b) and (a-1/2, b-1);
+   EB_a, EB_am on the b-faces at (a, b-1/2) and (a-1, b-1/2); mA_*, mB_*
+   the mass fluxes through those faces.  Cell-centre EMFs E00 (a, b),
+   E10 (a-1, b), E01 (a, b-1), E11 (a-1, b-1). */
+static double corner_emf(double EA_b, double EA_bm, double EB_a, double EB_am, double mA_b,
+                         double mA_bm, double mB_a, double mB_am, double E00, double E10,
+                         double E01, double E11) {
+  /* half-cell gradients of E along b at the a-faces, from the upwind cell */
+  double db_hi = upwind_pick(mA_b, E10 - EB_am, E00 - EB_a);     /* between b-1/2 and b */
+  double db_lo = upwind_pick(mA_bm, EB_am - E11, EB_a - E01);    /* between b-1 and b-1/2 */
+  /* half-cell gradients of E along a at the b-faces */
+  double da_hi = upwind_pick(mB_a, E01 - EA_bm, E00 - EA_b);     /* between a-1/2 and a */
+  double da_lo = upwind_pick(mB_am, EA_bm - E11, EA_b - E10);    /* between a-1 and a-1/2 */
+  return 0.25 * (EA_b + EA_bm + EB_a + EB_am) + 0.25 * (db_lo - db_hi + da_lo - da_hi);
+}
+
 int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1, double bb,
           double **Fall) {
   eos_t e;
@@ -1261,16 +1279,8 @@ int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, do
             double Ec10 = E[cidx(b, p10[0], p10[1], p10[2])];
             double Ec01 = E[cidx(b, p01[0], p01[1], p01[2])];
             double Ec11 = E[cidx(b, p11[0], p11[1], p11[2])];
-            /* upper half along b (between b-1/2 and b), upwind by a-flux at b */
-            double db_hi = upwind_pick(mA_b, Ec10 - EB_am, Ec00 - EB_a);
-            /* lower half along b, upwind by a-flux at b-1 */
-            double db_lo = upwind_pick(mA_bm, EB_am - Ec11, EB_a - Ec01);
-            /* right half along a (between a-1/2 and a), upwind by b-flux at a */
-            double da_hi = upwind_pick(mB_a, Ec01 - EA_bm, Ec00 - EA_b);
-            /* left half along a, upwind by b-flux at a-1 */
-            double da_lo = upwind_pick(mB_am, EA_bm - Ec11, EA_b - Ec10);
-            Ec[comp][eidx(b, i, j, k)] =
-                0.25 * (EA_b + EA_bm + EB_a + EB_am) + 0.25 * (db_lo - db_hi + da_lo - da_hi);
+            Ec[comp][eidx(b, i, j, k)] = corner_emf(EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a,
+                                                    mB_am, Ec00, Ec10, Ec01, Ec11);
           }
     }
     /* face update on interior faces */
@@ -1747,5 +1757,14 @@ int or_eos(int64_t n, int mode, const double *rho, const double *x, const double
 }
 
 /* size of the structs, for the Python side to check its layout */
+/* test entry: corner_emf at n points; in[12][n] in the argument order of
+   corner_emf */
+int or_corner_emf(int64_t n, double *const in[12], double *out) {
+  for (int64_t t = 0; t < n; ++t)
+    out[t] = corner_emf(in[0][t], in[1][t], in[2][t], in[3][t], in[4][t], in[5][t], in[6][t],
+                        in[7][t], in[8][t], in[9][t], in[10][t], in[11][t]);
+  return 0;
+}
+
 int or_sizeof_params(void) { return (int)sizeof(or_params); }
 int or_sizeof_block(void) { return (int)sizeof(or_block); }

@@ -103,6 +103,47 @@ def test_mfma_gradients_match_oracle(G):
     assert torch.equal(grad, grad2)
 
 
+def test_adam_steps_match_oracle(G):
+    """two training steps on the GPU (c2p_mlp_train_step with step >= 1) move
+    the fp32 parameters and moments as the FP64 Adam of the oracle does with
+    the same two gradients (learning rate 2e-3, bias correction of steps 1
+    and 2)"""
+    say("learned: two GPU Adam steps vs the oracle's Adam")
+    net = G.LearnedC2P(seed=5)
+    rng = np.random.default_rng(9)
+    theta0 = net.theta.cpu().numpy().astype(np.float64)
+    lr = 2e-3
+    grads = []
+    for step in range(2):
+        x = rng.normal(size=(5, 512)).astype(np.float32)
+        t = rng.normal(size=512).astype(np.float32)
+        _, g = net.train_step(torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda(), lr=lr,
+                              want_grad=True)
+        grads.append(g.cpu().numpy().astype(np.float64))
+    assert net.step == 2
+    ps = [[theta0.copy()]]
+    opt = M.Adam([[theta0.copy(), np.zeros(1)]], lr=lr)
+    params = [[theta0.copy(), np.zeros(1)]]
+    for g in grads:
+        opt.step(params, [[g, np.zeros(1)]])
+    del ps
+    th = net.theta.cpu().numpy().astype(np.float64)
+    m = net.m.cpu().numpy().astype(np.float64)
+    v = net.v.cpu().numpy().astype(np.float64)
+    upd, upd_ref = th - theta0, params[0][0] - theta0
+    live = np.abs(grads[0]) + np.abs(grads[1]) > 1e-20     # both moments resolved in fp32
+    e_upd = float(np.max(np.abs(upd - upd_ref)[live]))
+    say(f"  max |update - oracle update| {e_upd:.2e} (lr {lr}), {int(live.sum())} live parameters")
+    assert int(live.sum()) > 8000
+    assert e_upd <= 1e-4 * lr
+    assert np.max(np.abs(upd_ref[live])) > 0.5 * lr          # the steps are not trivially small
+    np.testing.assert_allclose(m[live], opt.m[0][0][live], rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(v[live], opt.v[0][0][live], rtol=1e-5, atol=1e-20)
+    # the bf16 copy follows the updated fp32 parameters
+    tb = net.theta_h.cpu().numpy().astype(np.int16).view(np.uint16).astype(np.uint32) << 16
+    np.testing.assert_array_equal(tb.view(np.float32).astype(np.float64), bf16(th))
+
+
 C4P = dict(gamma=5.0 / 3.0, rho_atm=1e-20, T_atm=1e-30, f_thr=1.0, M_max=1e30, c2p_tol=1e-12)
 
 
