@@ -473,8 +473,10 @@ def c5_section(args, torch, inputs, lib):
            "note": "ghosts frozen at the analytic data, so mass also flows through block faces"}
     # the oracle check runs on the host in the cpu leg, from these
     sub = {"subset": subset, "init": init_sub, "dts": dts_p.cpu().numpy(),
-           "gpu_plain": [(plain.u0[i].cpu().numpy(), plain.w0[i].cpu().numpy()) for i in subset],
-           "gpu_learned": [(learned.u0[i].cpu().numpy(), learned.w0[i].cpu().numpy()) for i in subset],
+           "gpu_plain": [(plain.u0[i].cpu().numpy(), plain.w0[i].cpu().numpy(),
+                          [f.cpu().numpy() for f in plain.b0[i]]) for i in subset],
+           "gpu_learned": [(learned.u0[i].cpu().numpy(), learned.w0[i].cpu().numpy(),
+                            [f.cpu().numpy() for f in learned.b0[i]]) for i in subset],
            "params": params_kw}
     del plain, learned
     torch.cuda.synchronize()
@@ -483,8 +485,14 @@ def c5_section(args, torch, inputs, lib):
 
 def c5_oracle_check(sub):
     """The FP64 oracle (plain C2P) on the seeded 16-block subset with the GPU
-    run's dt sequence; max deviation of the GPU's final state from it."""
+    run's dt sequence; max deviation of the GPU's final state from it: the
+    five conserved fields, the five primitives and the three face-field
+    components, each over every interior cell (face) of the 16 blocks, in
+    the pointwise metric (positive fields |d|/|x|; signed fields against
+    max(|x|, 1e-3 max|x| of the block)), and D~ also relative to the
+    block's largest D~ and over the star's cells alone."""
     import oracle as O
+    from tests import parity as PM
     out = {"blocks": sub["subset"]}
     m = O.Mesh([_copy_np(b) for b in sub["init"]], O.Params(**sub["params"]))
     t0 = time.perf_counter()
@@ -492,18 +500,32 @@ def c5_oracle_check(sub):
         m.rk2_step(float(dt))
     el = time.perf_counter() - t0
     out["oracle_s"] = el
+    names_u = ("D", "S_x", "S_y", "S_z", "tau")
+    names_w = ("rho", "u_x", "u_y", "u_z", "P")
     for kind in ("learned", "plain"):
         worst_all, worst_star = 0.0, 0.0
-        for j, (gu, gw) in enumerate(sub["gpu_" + kind]):
+        fields = {}
+        for j, (gu, gw, gb) in enumerate(sub["gpu_" + kind]):
+            blk = sub["init"][j]
             ou, ow = m.interior(m.u0[j], j), m.interior(m.w0[j], j)
-            gu_i = m.interior(gu, j)
+            gu_i, gw_i = m.interior(gu, j), m.interior(gw, j)
             scale = np.max(np.abs(ou[0]))
             worst_all = max(worst_all, float(np.max(np.abs(gu_i[0] - ou[0])) / scale))
             star = ow[0] > 1e-6 * 1.28e-3
             if star.any():
                 worst_star = max(worst_star, float(np.max(np.abs(gu_i[0][star] - ou[0][star]) / ou[0][star])))
-        out[kind] = {"max_dev_D_over_block_max": worst_all, "max_rel_dev_D_star": worst_star}
-        log(f"c5 oracle check ({kind}): max |dD|/max D {worst_all:.2e}, star rel {worst_star:.2e}")
+            errs = list(zip(names_u, PM.cons_errors(gu_i, ou))) + list(zip(names_w, PM.prim_errors(gw_i, ow)))
+            g = blk.ng
+            for d in range(3):
+                sl = [slice(g, g + blk.nz), slice(g, g + blk.ny), slice(g, g + blk.nx)]
+                sl[2 - d] = slice(g, g + (blk.nx, blk.ny, blk.nz)[d] + 1)
+                errs.append(("B" + "xyz"[d], PM.rel_signed(gb[d][tuple(sl)], m.b0[j][d][tuple(sl)])))
+            for name, e in errs:
+                fields[name] = max(fields.get(name, 0.0), float(e))
+        out[kind] = {"max_dev_D_over_block_max": worst_all, "max_rel_dev_D_star": worst_star,
+                     "max_dev_by_field": fields, "max_dev_all_fields": max(fields.values())}
+        log(f"c5 oracle check ({kind}): max |dD|/max D {worst_all:.2e}, star rel {worst_star:.2e}, "
+            f"all fields {max(fields.values()):.2e} ({ {k: float('%.1e' % v) for k, v in fields.items()} })")
     cells = sum(b.nx * b.ny * b.nz for b in sub["init"])
     out["oracle_zone_updates_per_s"] = cells * len(sub["dts"]) / el
     log(f"c5 oracle: {len(sub['dts'])} steps of {len(sub['init'])} blocks in {el:.1f} s")

@@ -72,6 +72,13 @@ def lib():
     return _lib
 
 
+def set_decision_margin(m: float):
+    """Move every threshold test of the method by the relative amount m
+    (test instrument; 0 restores the method exactly).  Oracle runs at +m and
+    -m differ exactly where a decision lies within m of its threshold."""
+    lib().or_set_decision_margin(C.c_double(m))
+
+
 @dataclasses.dataclass
 class Params:
     """Method options: EOS, atmosphere (rho_atm, T_atm, f_thr, M_max),
@@ -170,6 +177,23 @@ def matter_sources(w, bt, gam, params: Params):
     lib().or_matter_sources(C.c_int64(n), _ptrs(w), _ptrs(bt), _ptrs(gam), _ptrs(out),
                             C.byref(params.c()))
     return out
+
+
+def recover(u, bt, gam, mu, params: Params, eps_terms=False):
+    """the primitives (rho, W v^i, P) the inversion recovers at the root mu
+    (the recovery step of c2p, without the floors); with eps_terms also the
+    magnitude of the terms the specific internal energy is summed from, the
+    scale of its rounding error"""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    bt = np.ascontiguousarray(bt, dtype=np.float64)
+    gam = np.ascontiguousarray(gam, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    n = u.shape[1]
+    w = np.zeros((5, n))
+    te = np.zeros(n)
+    lib().or_recover(C.c_int64(n), _ptrs(u), _ptrs(bt), _ptrs(gam), _pd(mu), _ptrs(w), _pd(te),
+                     C.byref(params.c()))
+    return (w, te) if eps_terms else w
 
 
 def master(u, bt, gam, mu, params: Params):
@@ -360,10 +384,31 @@ class Mesh:
         arr = self.descs(1)
         return lib().or_dt(arr, len(self.blocks), C.byref(self.params.c()), C.c_double(cfl))
 
-    def stage_sets(self, src, dst, dt, a0, a1, b):
+    def stage_sets(self, src, dst, dt, a0, a1, b, term_scales=False):
+        """one stage; with term_scales, also returns per block the magnitudes
+        of the terms each interior value of U (5 cell arrays) and of the faces
+        (3 face arrays) is summed from (or_set_term_scales)"""
         arr = self.stage_descs(src, dst)
-        lib().or_stage(arr, len(self.blocks), C.byref(self.params.c()), C.c_double(dt),
-                       C.c_double(a0), C.c_double(a1), C.c_double(b))
+        nb = len(self.blocks)
+        out = None
+        if term_scales:
+            tu = [np.zeros((5,) + blk.shape) for blk in self.blocks]
+            tb = [[np.zeros(f.shape) for f in self.b0[ib]] for ib in range(nb)]
+            pu, pb = (PD * (5 * nb))(), (PD * (3 * nb))()
+            for ib in range(nb):
+                for v in range(5):
+                    pu[ib * 5 + v] = _pd(tu[ib][v])
+                for d in range(3):
+                    pb[ib * 3 + d] = _pd(tb[ib][d])
+            lib().or_set_term_scales(pu, pb)
+            out = (tu, tb)
+        try:
+            lib().or_stage(arr, nb, C.byref(self.params.c()), C.c_double(dt), C.c_double(a0),
+                           C.c_double(a1), C.c_double(b))
+        finally:
+            if term_scales:
+                lib().or_set_term_scales(None, None)
+        return out
 
     def stage(self, stage, dt):
         src, dst, (a0, a1, b) = self.RK2[stage - 1]
@@ -414,19 +459,30 @@ class Mesh:
         return a[..., g:g + b.nz, g:g + b.ny, g:g + b.nx]
 
 
-def stage_steps(mesh: Mesh, stage, dt, fluxes, mode):
+def stage_steps(mesh: Mesh, stage, dt, fluxes, mode, flux_scales=None):
     """Run selected steps of one stage with caller-provided flux arrays
-    fluxes[ib][d][c] (face arrays); see or_stage_steps for the mode bits."""
+    fluxes[ib][d][c] (face arrays); see or_stage_steps for the mode bits.
+    flux_scales (same layout as fluxes): filled with the magnitudes of the
+    terms of every flux the steps compute (or_set_flux_term_scales)."""
     arr = mesh.descs(stage)
     a0, a1, b = (0.0, 1.0, 1.0) if stage == 1 else (0.5, 0.5, 0.5)
     nb = len(mesh.blocks)
     ptrs = (PD * (21 * nb))()
+    sptrs = (PD * (21 * nb))() if flux_scales is not None else None
     for ib in range(nb):
         for d in range(3):
             for c in range(7):
                 ptrs[ib * 21 + d * 7 + c] = _pd(fluxes[ib][d][c])
-    lib().or_stage_steps(arr, nb, C.byref(mesh.params.c()), C.c_double(dt), C.c_double(a0),
-                         C.c_double(a1), C.c_double(b), ptrs, C.c_int(mode))
+                if sptrs is not None:
+                    sptrs[ib * 21 + d * 7 + c] = _pd(flux_scales[ib][d][c])
+    if sptrs is not None:
+        lib().or_set_flux_term_scales(sptrs)
+    try:
+        lib().or_stage_steps(arr, nb, C.byref(mesh.params.c()), C.c_double(dt), C.c_double(a0),
+                             C.c_double(a1), C.c_double(b), ptrs, C.c_int(mode))
+    finally:
+        if sptrs is not None:
+            lib().or_set_flux_term_scales(None)
 
 
 def alloc_fluxes(mesh: Mesh):

@@ -82,6 +82,41 @@ enum {
    count as needing the floor (and be FOFC-flagged) on rounding alone. */
 #define FLOOR_MARGIN 1e-10
 
+/* Decision margin (test instrument, 0 in every ordinary run): each threshold
+   test of the method -- the face and inversion floors, the magnetisation cap,
+   the relaxed DMP bounds of Eq. 12 and the vanishing-mass-flux test of the
+   Riemann flux -- is taken against its threshold moved by the relative amount
+   g_margin (floors and the cap: thr (1 + m); DMP: [lo - m|lo|, hi + m|hi|];
+   mass flux: 1e-12 scale (1 + m)).  With m = 0 each moved threshold is the
+   threshold itself, bit for bit.  Runs at m = +delta and m = -delta differ
+   exactly where some decision lies within a relative delta of its threshold,
+   which is how the parity tests find the cells a rounding-level difference
+   could send the other way. */
+static double g_margin = 0.0;
+void or_set_decision_margin(double m) { g_margin = m; }
+#define THR(x) ((x) * (1.0 + g_margin))
+
+/* Term magnitudes (test instrument, off unless set).  When set, the update
+   writes for every interior cell and component the sum of the magnitudes of
+   the terms it adds up, |a0 U^n| + |a1 U^(s)| + |b| dt (sum_d (|F_hi| +
+   |F_lo|) / dx_d + the magnitudes of the source terms), and CT does the same
+   for every interior face, with the magnitudes of the terms of the corner
+   EMFs and of the cell-centre EMFs they use.  Those are the scales of the
+   rounding errors of the two sums: a value formed by cancellation (momentum
+   near hydrostatic balance, a face field under a nearly vanishing curl) is
+   rounded relative to them, not to itself.  u: nblk x 5 padded cell arrays,
+   bf: nblk x 3 face arrays (interiors written). */
+static double **g_tscale_u = NULL;
+static double **g_tscale_b = NULL;
+static double **g_tscale_f = NULL;   /* flux-term magnitudes, nblk x 21, set by or_stage */
+void or_set_term_scales(double **u, double **bf) {
+  g_tscale_u = u;
+  g_tscale_b = bf;
+}
+/* the flux-term magnitudes alone (nblk x 21 face arrays, as the flux
+   workspace of or_stage_steps), for tests of the face fluxes */
+void or_set_flux_term_scales(double **f) { g_tscale_f = f; }
+
 /* ------------------------------------------------------------------------- */
 /* equation of state                                                          */
 /* ------------------------------------------------------------------------- */
@@ -424,19 +459,19 @@ static int c2p_point(const eos_t *e, const or_params *p, const met3 *m, double U
     return F_C2P_FAIL;
   }
   /* rule: D below the threshold -> atmosphere */
-  if (D < p->f_thr * p->rho_atm) {
+  if (D < THR(p->f_thr * p->rho_atm)) {
     atmosphere_prims(e, p, w);
     p2c_point(e, m, w, Bt, U);
     return F_DFLOOR;
   }
   /* rule: magnetisation cap B^2/D <= M_max by raising D */
-  if (B2 / D > p->M_max) {
+  if (B2 / D > THR(p->M_max)) {
     D = B2 / p->M_max;
     flags |= F_MAGCAP;
   }
   /* rule: tau floor for a fluid at rest at T_atm:  tau_atm = D eps(D,T_atm) + B^2/2 */
   double tau_atm = D * eos_eps_T(e, D, p->T_atm) + 0.5 * B2;
-  if (tau < tau_atm * (1.0 - FLOOR_MARGIN)) {
+  if (tau < THR(tau_atm * (1.0 - FLOOR_MARGIN))) {
     tau = tau_atm;
     flags |= F_TAUFLOOR;
   }
@@ -525,10 +560,10 @@ static int c2p_point(const eos_t *e, const or_params *p, const met3 *m, double U
   }
   /* primitive floors (Sec. III-C): rho below threshold -> atmosphere;
      T below T_atm -> reset T, keep rho and W v^i */
-  if (w[0] < p->f_thr * p->rho_atm) {
+  if (w[0] < THR(p->f_thr * p->rho_atm)) {
     atmosphere_prims(e, p, w);
     flags |= F_RHOFLOOR;
-  } else if (eos_T(e, w[0], w[4]) < p->T_atm * (1.0 - FLOOR_MARGIN)) {
+  } else if (eos_T(e, w[0], w[4]) < THR(p->T_atm * (1.0 - FLOOR_MARGIN))) {
     w[4] = eos_P_T(e, w[0], p->T_atm);
     flags |= F_TFLOOR;
   }
@@ -544,7 +579,7 @@ static int c2p_point(const eos_t *e, const or_params *p, const met3 *m, double U
 /* ------------------------------------------------------------------------- */
 static void face_physics(const eos_t *e, const met3 *m, double alpha, const double beta[3], int d,
                          const double q[5], const double B[3], double U[7], double F[7],
-                         double *lm, double *lp) {
+                         double *lm, double *lp, double *Fs) {
   double rho = q[0], P = q[4];
   double u[3] = {q[1], q[2], q[3]};
   double ul[3];
@@ -584,6 +619,16 @@ static void face_physics(const eos_t *e, const met3 *m, double alpha, const doub
   int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   F[5] = alpha * (Bt[t1] * vh[d] - Bt[d] * vh[t1]);
   F[6] = alpha * (Bt[t2] * vh[d] - Bt[d] * vh[t2]);
+  if (Fs) {
+    /* magnitudes of the terms of each flux (term-scale instrument) */
+    double aa = fabs(alpha);
+    Fs[0] = fabs(F[0]);
+    for (int i = 0; i < 3; ++i)
+      Fs[1 + i] = aa * (fabs(St[i] * vh[d]) + fabs(bl[i] * Bt[d] / W)) + (i == d ? aa * fabs(Ptt) : 0.0);
+    Fs[4] = aa * (fabs(taut * vh[d]) + aa * fabs(b0 * Bt[d] / W) + fabs(Ptt * v[d]));
+    Fs[5] = aa * (fabs(Bt[t1] * vh[d]) + fabs(Bt[d] * vh[t1]));
+    Fs[6] = aa * (fabs(Bt[t2] * vh[d]) + fabs(Bt[d] * vh[t2]));
+  }
   U[0] = Dt; U[1] = St[0]; U[2] = St[1]; U[3] = St[2]; U[4] = taut;
   U[5] = Bt[t1]; U[6] = Bt[t2];
   /* fast magnetosonic speeds: c^2 = cs^2 + ca^2 - cs^2 ca^2 */
@@ -636,7 +681,33 @@ static void riemann_solve(int riemann, const double UL[7], const double FL[7], d
               (lr - ll);
     }
   }
-  if (fabs(F[0]) <= MASS_FLUX_ZERO * scale) F[0] = 0.0;
+  if (fabs(F[0]) <= THR(MASS_FLUX_ZERO * scale)) F[0] = 0.0;
+}
+
+/* the magnitudes of the terms of the Riemann flux (term-scale instrument):
+   the same combination over the sides' flux-term magnitudes and |U| */
+static void riemann_scale(int riemann, const double UL[7], const double FLs[7], double lmL,
+                          double lpL, const double UR[7], const double FRs[7], double lmR,
+                          double lpR, double Fs[7]) {
+  if (riemann == 0) {
+    double a = fabs(lmL);
+    if (fabs(lpL) > a) a = fabs(lpL);
+    if (fabs(lmR) > a) a = fabs(lmR);
+    if (fabs(lpR) > a) a = fabs(lpR);
+    for (int c = 0; c < 7; ++c) Fs[c] = 0.5 * (FLs[c] + FRs[c]) + 0.5 * a * (fabs(UR[c]) + fabs(UL[c]));
+    return;
+  }
+  double lr = 0.0, ll = 0.0;
+  if (lpL > lr) lr = lpL;
+  if (lpR > lr) lr = lpR;
+  if (lmL < ll) ll = lmL;
+  if (lmR < ll) ll = lmR;
+  if (lr - ll == 0.0) {
+    for (int c = 0; c < 7; ++c) Fs[c] = 0.5 * (FLs[c] + FRs[c]);
+    return;
+  }
+  for (int c = 0; c < 7; ++c)
+    Fs[c] = (lr * FLs[c] - ll * FRs[c] - lr * ll * (fabs(UR[c]) + fabs(UL[c]))) / (lr - ll);
 }
 
 /* WENOZ (Borges et al. 2008), value at the right interface of cell 0 from
@@ -848,11 +919,11 @@ static void cell_bt(const or_block *b, double *const f[3], int i, int j, int k, 
 
 /* primitive floors on a reconstructed face state (Sec. III-C) */
 static void face_floor(const eos_t *e, const or_params *p, double q[5]) {
-  if (q[0] < p->f_thr * p->rho_atm) {
+  if (q[0] < THR(p->f_thr * p->rho_atm)) {
     q[0] = p->rho_atm;
     q[1] = q[2] = q[3] = 0.0;
     q[4] = eos_P_T(e, p->rho_atm, p->T_atm);
-  } else if (eos_T(e, q[0], q[4]) < p->T_atm) {
+  } else if (eos_T(e, q[0], q[4]) < THR(p->T_atm)) {
     q[4] = eos_P_T(e, q[0], p->T_atm);
   }
 }
@@ -863,7 +934,7 @@ static void face_floor(const eos_t *e, const or_params *p, double q[5]) {
 /* Riemann solver.  Uses stage-input w and B~^(s).                            */
 /* ------------------------------------------------------------------------- */
 static void face_flux(const eos_t *e, const or_params *p, const or_block *b, int d, int i, int j,
-                      int k, int order, double F[7]) {
+                      int k, int order, double F[7], double *Fs) {
   int off[3] = {0, 0, 0};
   off[d] = 1;
   /* cell index of the cell n steps along d from cell (i,j,k), n in -3..2 */
@@ -917,9 +988,11 @@ static void face_flux(const eos_t *e, const or_params *p, const or_block *b, int
   BL[t1] = qL[5]; BL[t2] = qL[6];
   BR[t1] = qR[5]; BR[t2] = qR[6];
   double UL[7], FL[7], UR[7], FR[7], lmL, lpL, lmR, lpR;
-  face_physics(e, &m, alpha, beta, d, qL, BL, UL, FL, &lmL, &lpL);
-  face_physics(e, &m, alpha, beta, d, qR, BR, UR, FR, &lmR, &lpR);
+  double FLs[7], FRs[7];
+  face_physics(e, &m, alpha, beta, d, qL, BL, UL, FL, &lmL, &lpL, Fs ? FLs : NULL);
+  face_physics(e, &m, alpha, beta, d, qR, BR, UR, FR, &lmR, &lpR, Fs ? FRs : NULL);
   riemann_solve(p->riemann, UL, FL, lmL, lpL, UR, FR, lmR, lpR, F);
+  if (Fs) riemann_scale(p->riemann, UL, FLs, lmL, lpL, UR, FRs, lmR, lpR, Fs);
 }
 
 /* extended face range of direction d: faces [g, g+n_d] along d, cells
@@ -947,10 +1020,12 @@ int or_fluxes(or_block *blks, int nblk, const or_params *p, double **Fall) {
       for (int k = lo[2]; k <= hi[2]; ++k)
         for (int j = lo[1]; j <= hi[1]; ++j)
           for (int i = lo[0]; i <= hi[0]; ++i) {
-            double f[7];
-            face_flux(&e, p, b, d, i, j, k, p->recon, f);
+            double f[7], fs[7];
+            face_flux(&e, p, b, d, i, j, k, p->recon, f, g_tscale_f ? fs : NULL);
             int64_t x = fidx(b, d, i, j, k);
             for (int c = 0; c < 7; ++c) F[c][x] = f[c];
+            if (g_tscale_f)
+              for (int c = 0; c < 7; ++c) g_tscale_f[(int64_t)ib * 21 + d * 7 + c][x] = fs[c];
           }
     }
   }
@@ -1114,6 +1189,8 @@ int or_fofc_flags(or_block *blks, int nblk, const or_params *p, double dt, doubl
                   }
               double lo, hi;
               dmp_bounds(mn, mx, p->dmp_M, &lo, &hi);
+              lo -= g_margin * fabs(lo);
+              hi += g_margin * fabs(hi);
               if (!(U[v] >= lo && U[v] <= hi)) fl |= F_DMP;
             }
           }
@@ -1150,10 +1227,12 @@ int or_fofc_fix(or_block *blks, int nblk, const or_params *p, double **Fall) {
             uint16_t fl = b->flags[cidx(b, i, j, k)] |
                           b->flags[cidx(b, i - off[0], j - off[1], k - off[2])];
             if (!(fl & (F_FOFC | F_DMP))) continue;
-            double f[7];
-            face_flux(&e, p, b, d, i, j, k, 0, f);
+            double f[7], fs[7];
+            face_flux(&e, p, b, d, i, j, k, 0, f, g_tscale_f ? fs : NULL);
             int64_t x = fidx(b, d, i, j, k);
             for (int c = 0; c < 7; ++c) F[c][x] = f[c];
+            if (g_tscale_f)
+              for (int c = 0; c < 7; ++c) g_tscale_f[(int64_t)ib * 21 + d * 7 + c][x] = fs[c];
           }
     }
   }
@@ -1206,6 +1285,19 @@ static double corner_emf(double EA_b, double EA_bm, double EB_a, double EB_am, d
   return 0.25 * (EA_b + EA_bm + EB_a + EB_am) + 0.25 * (db_lo - db_hi + da_lo - da_hi);
 }
 
+/* the magnitudes of the terms of corner_emf (term-scale instrument): the
+   same upwind picks over |E_cc| + |E_face| in place of their differences */
+static double corner_emf_scale(double EA_b, double EA_bm, double EB_a, double EB_am, double mA_b,
+                               double mA_bm, double mB_a, double mB_am, double E00, double E10,
+                               double E01, double E11) {
+  double db_hi = upwind_pick(mA_b, fabs(E10) + fabs(EB_am), fabs(E00) + fabs(EB_a));
+  double db_lo = upwind_pick(mA_bm, fabs(EB_am) + fabs(E11), fabs(EB_a) + fabs(E01));
+  double da_hi = upwind_pick(mB_a, fabs(E01) + fabs(EA_bm), fabs(E00) + fabs(EA_b));
+  double da_lo = upwind_pick(mB_am, fabs(EA_bm) + fabs(E11), fabs(EA_b) + fabs(E10));
+  return 0.25 * (fabs(EA_b) + fabs(EA_bm) + fabs(EB_a) + fabs(EB_am)) +
+         0.25 * (db_lo + db_hi + da_lo + da_hi);
+}
+
 int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1, double bb,
           double **Fall) {
   eos_t e;
@@ -1217,10 +1309,14 @@ int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, do
     int g = b->ng;
     int n[3] = {b->nx, b->ny, b->nz};
     int64_t nc = ncell(b), ne = nedge(b);
-    double *Ecc[3], *Ec[3];
+    double *Ecc[3], *Ec[3], *Eccs[3] = {NULL, NULL, NULL}, *Ecs[3] = {NULL, NULL, NULL};
     for (int a = 0; a < 3; ++a) {
       Ecc[a] = (double *)calloc((size_t)nc, sizeof(double));
       Ec[a] = (double *)calloc((size_t)ne, sizeof(double));
+      if (g_tscale_b) {
+        Eccs[a] = (double *)calloc((size_t)nc, sizeof(double));
+        Ecs[a] = (double *)calloc((size_t)ne, sizeof(double));
+      }
     }
     /* cell-centre EMF on cells [g-1, g+n] */
     for (int k = g - 1; k <= g + n[2]; ++k)
@@ -1241,6 +1337,11 @@ int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, do
           Ecc[0][c] = -al * (vh[1] * Bt[2] - vh[2] * Bt[1]);
           Ecc[1][c] = -al * (vh[2] * Bt[0] - vh[0] * Bt[2]);
           Ecc[2][c] = -al * (vh[0] * Bt[1] - vh[1] * Bt[0]);
+          if (g_tscale_b) {
+            Eccs[0][c] = fabs(al) * (fabs(vh[1] * Bt[2]) + fabs(vh[2] * Bt[1]));
+            Eccs[1][c] = fabs(al) * (fabs(vh[2] * Bt[0]) + fabs(vh[0] * Bt[2]));
+            Eccs[2][c] = fabs(al) * (fabs(vh[0] * Bt[1]) + fabs(vh[1] * Bt[0]));
+          }
         }
     /* corner EMFs.  For component c with plane axes (a, bx) cyclic, the edge
        (ia-1/2, ib-1/2) is stored at edge index with face indices on a and bx */
@@ -1281,6 +1382,17 @@ int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, do
             double Ec11 = E[cidx(b, p11[0], p11[1], p11[2])];
             Ec[comp][eidx(b, i, j, k)] = corner_emf(EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a,
                                                     mB_am, Ec00, Ec10, Ec01, Ec11);
+            if (g_tscale_b && g_tscale_f) {
+              double *Es = Eccs[comp];
+              double **Sb = g_tscale_f + (int64_t)ib * 21;
+              Ecs[comp][eidx(b, i, j, k)] = corner_emf_scale(
+                  face_emf(b, Sb, A, comp, p00[0], p00[1], p00[2]),
+                  face_emf(b, Sb, A, comp, p01[0], p01[1], p01[2]),
+                  face_emf(b, Sb, Bx, comp, p00[0], p00[1], p00[2]),
+                  face_emf(b, Sb, Bx, comp, p10[0], p10[1], p10[2]), mA_b, mA_bm, mB_a, mB_am,
+                  Es[cidx(b, p00[0], p00[1], p00[2])], Es[cidx(b, p10[0], p10[1], p10[2])],
+                  Es[cidx(b, p01[0], p01[1], p01[2])], Es[cidx(b, p11[0], p11[1], p11[2])]);
+            }
           }
     }
     /* face update on interior faces */
@@ -1302,11 +1414,19 @@ int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, do
             double c2 = (Ec[d1][eidx(b, x2[0], x2[1], x2[2])] - Ec[d1][eidx(b, i, j, k)]) / b->dx[d2];
             int64_t f = fidx(b, d, i, j, k);
             b->bo[d][f] = a0 * b->bn[d][f] + a1 * b->bs[d][f] - bb * dt * (c1 - c2);
+            if (g_tscale_b && g_tscale_f) {
+              double s1 = (Ecs[d2][eidx(b, x1[0], x1[1], x1[2])] + Ecs[d2][eidx(b, i, j, k)]) / b->dx[d1];
+              double s2 = (Ecs[d1][eidx(b, x2[0], x2[1], x2[2])] + Ecs[d1][eidx(b, i, j, k)]) / b->dx[d2];
+              g_tscale_b[ib * 3 + d][f] = fabs(a0 * b->bn[d][f]) + fabs(a1 * b->bs[d][f]) +
+                                          fabs(bb) * dt * (s1 + s2);
+            }
           }
     }
     for (int a = 0; a < 3; ++a) {
       free(Ecc[a]);
       free(Ec[a]);
+      free(Eccs[a]);
+      free(Ecs[a]);
     }
   }
   return 0;
@@ -1332,7 +1452,8 @@ static double dcen(const double *a, const or_block *b, int d, int i, int j, int 
    K6 extrinsic curvature.  Output G[5] (0 for D~). */
 static void sources_point(const eos_t *e, const met3 *m, double alpha, const double w[5],
                           const double Bt[3], const double U[5], const double dal[3],
-                          double dbe[3][3], double dg[3][6], const double K6[6], double G[5]) {
+                          double dbe[3][3], double dg[3][6], const double K6[6], double G[5],
+                          double *Gs) {
   double rho = w[0], P = w[4];
   double u[3] = {w[1], w[2], w[3]};
   double ul[3];
@@ -1372,6 +1493,22 @@ static void sources_point(const eos_t *e, const met3 *m, double alpha, const dou
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) kS += K6[sidx[i][j]] * Sij[i][j];
   G[4] = alpha * kS - dot3(Su, dal);
+  if (Gs) {
+    /* the same sums over the magnitudes of their terms (instrument) */
+    Gs[0] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      double a1 = 0.0, a2 = 0.0;
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) a1 += fabs(Sij[j][k] * dg[i][sidx[j][k]]);
+      for (int j = 0; j < 3; ++j) a2 += fabs(Sl[j] * dbe[i][j]);
+      Gs[1 + i] = 0.5 * fabs(alpha) * a1 + a2 + fabs(Et * dal[i]);
+    }
+    double ak = 0.0, ad = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) ak += fabs(K6[sidx[i][j]] * Sij[i][j]);
+    for (int i = 0; i < 3; ++i) ad += fabs(Su[i] * dal[i]);
+    Gs[4] = fabs(alpha) * ak + ad;
+  }
 }
 
 int or_update(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1,
@@ -1400,12 +1537,22 @@ int or_update(or_block *blks, int nblk, const or_params *p, double dt, double a0
           double w[5], Us[5], Bt[3], G[5];
           for (int v = 0; v < 5; ++v) { w[v] = b->w[v][c]; Us[v] = b->us[v][c]; }
           cell_bt(b, b->bs, i, j, k, Bt);
-          sources_point(&e, &m, b->adm[0][c], w, Bt, Us, dal, dbe, dg, K6, G);
+          double Gs[5];
+          sources_point(&e, &m, b->adm[0][c], w, Bt, Us, dal, dbe, dg, K6, G,
+                        g_tscale_u ? Gs : NULL);
           for (int v = 0; v < 5; ++v) {
             double div = (F[0 * 7 + v][fidx(b, 0, i + 1, j, k)] - F[0 * 7 + v][fidx(b, 0, i, j, k)]) / b->dx[0] +
                          (F[1 * 7 + v][fidx(b, 1, i, j + 1, k)] - F[1 * 7 + v][fidx(b, 1, i, j, k)]) / b->dx[1] +
                          (F[2 * 7 + v][fidx(b, 2, i, j, k + 1)] - F[2 * 7 + v][fidx(b, 2, i, j, k)]) / b->dx[2];
             b->uo[v][c] = a0 * b->un[v][c] + a1 * Us[v] + bb * dt * (-div + G[v]);
+            if (g_tscale_u && g_tscale_f) {
+              double **S = g_tscale_f + (int64_t)ib * 21;
+              double fs = (S[0 * 7 + v][fidx(b, 0, i + 1, j, k)] + S[0 * 7 + v][fidx(b, 0, i, j, k)]) / b->dx[0] +
+                          (S[1 * 7 + v][fidx(b, 1, i, j + 1, k)] + S[1 * 7 + v][fidx(b, 1, i, j, k)]) / b->dx[1] +
+                          (S[2 * 7 + v][fidx(b, 2, i, j, k + 1)] + S[2 * 7 + v][fidx(b, 2, i, j, k)]) / b->dx[2];
+              g_tscale_u[ib * 5 + v][c] = fabs(a0 * b->un[v][c]) + fabs(a1 * Us[v]) +
+                                          fabs(bb) * dt * (fs + Gs[v]);
+            }
           }
         }
   }
@@ -1488,6 +1635,7 @@ static void free_fluxes(double **F, int nblk) {
 int or_stage(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1,
              double bb) {
   double **F = alloc_fluxes(blks, nblk);
+  if (g_tscale_u || g_tscale_b) g_tscale_f = alloc_fluxes(blks, nblk);
   or_fluxes(blks, nblk, p, F);
   if (p->fofc) {
     or_fofc_flags(blks, nblk, p, dt, a0, a1, bb, F);
@@ -1503,6 +1651,10 @@ int or_stage(or_block *blks, int nblk, const or_params *p, double dt, double a0,
   or_update(blks, nblk, p, dt, a0, a1, bb, F);
   or_stage_c2p(blks, nblk, p);
   free_fluxes(F, nblk);
+  if (g_tscale_f) {
+    free_fluxes(g_tscale_f, nblk);
+    g_tscale_f = NULL;
+  }
   return 0;
 }
 
@@ -1544,7 +1696,7 @@ double or_dt(or_block *blks, int nblk, const or_params *p, double cfl) {
           for (int a = 0; a < 3; ++a) B[a] = Bt[a] / m.sg;
           for (int d = 0; d < 3; ++d) {
             double U[7], F[7], lm, lp;
-            face_physics(&e, &m, b->adm[0][c], beta, d, q, B, U, F, &lm, &lp);
+            face_physics(&e, &m, b->adm[0][c], beta, d, q, B, U, F, &lm, &lp, NULL);
             double s = fabs(lm) > fabs(lp) ? fabs(lm) : fabs(lp);
             s /= b->dx[d];
             if (s > mx) mx = s;
@@ -1669,6 +1821,54 @@ int or_master(int64_t n, double *const u[5], double *const bt[3], double *const 
   return 0;
 }
 
+/* test entry: the primitives the inversion recovers at a given root mu
+   (no floors), n points; the recovery of c2p_point at mu */
+int or_recover(int64_t n, double *const u[5], double *const bt[3], double *const gam[6],
+               const double *mu, double *w[5], double *teps, const or_params *p) {
+  eos_t e;
+  eos_setup(p, &e);
+  for (int64_t x = 0; x < n; ++x) {
+    double s[6];
+    for (int q = 0; q < 6; ++q) s[q] = gam[q][x];
+    met3 m;
+    met_set(&m, s);
+    double D = u[0][x] / m.sg, Sl[3] = {u[1][x] / m.sg, u[2][x] / m.sg, u[3][x] / m.sg};
+    double tau = u[4][x] / m.sg;
+    double B[3] = {bt[0][x] / m.sg, bt[1][x] / m.sg, bt[2][x] / m.sg}, Bl[3];
+    lower3(&m, B, Bl);
+    kctx k;
+    k.e = &e;
+    k.D = D;
+    k.q = tau / D;
+    double rl[3] = {Sl[0] / D, Sl[1] / D, Sl[2] / D}, ru[3];
+    raise3(&m, rl, ru);
+    k.r2 = dot3(rl, ru);
+    double sD = sqrt(D);
+    double bu[3] = {B[0] / sD, B[1] / sD, B[2] / sD};
+    k.b2 = dot3(B, Bl) / D;
+    k.s = dot3(rl, bu);
+    k.h0 = eos_h0(&e);
+    double z0 = sqrt(k.r2) / k.h0;
+    k.v0sq = z0 * z0 / (1.0 + z0 * z0);
+    kstate st;
+    kastaun_eval(&k, mu[x], &st);
+    double vu[3];
+    for (int i = 0; i < 3; ++i) vu[i] = mu[x] * st.chi * (ru[i] + mu[x] * k.s * bu[i]);
+    w[0][x] = st.rho;
+    w[1][x] = st.W * vu[0];
+    w[2][x] = st.W * vu[1];
+    w[3][x] = st.W * vu[2];
+    w[4][x] = st.P;
+    if (teps) {
+      /* magnitude of the terms eps is summed from (its rounding scale) */
+      double m2c2 = mu[x] * mu[x] * st.chi * st.chi;
+      double qbs = fabs(k.q) + 0.5 * k.b2 + 0.5 * m2c2 * (k.b2 * k.r2 + k.s * k.s);
+      teps[x] = st.W * (qbs + mu[x] * st.rb2) + st.vsq * st.W * st.W / (1.0 + st.W);
+    }
+  }
+  return 0;
+}
+
 /* Eq. 9 + wave speeds at n points for direction d (for pins).  q prims,
    B un-densitized, metric fields al, be[3], gam[6].  U[7], F[7], lm, lp out. */
 int or_face_physics(int64_t n, int d, double *const q[5], double *const B[3],
@@ -1683,7 +1883,7 @@ int or_face_physics(int64_t n, int d, double *const q[5], double *const B[3],
     for (int c = 0; c < 3; ++c) { BB[c] = B[c][x]; beta[c] = be[c][x]; }
     met3 m;
     met_set(&m, s);
-    face_physics(&e, &m, al[x], beta, d, qq, BB, UU, FF, &lm[x], &lp[x]);
+    face_physics(&e, &m, al[x], beta, d, qq, BB, UU, FF, &lm[x], &lp[x], NULL);
     for (int c = 0; c < 7; ++c) { U[c][x] = UU[c]; F[c][x] = FF[c]; }
   }
   return 0;
@@ -1703,7 +1903,7 @@ int or_sources_point(const double *w, const double *bt, const double *u, const d
     for (int j = 0; j < 3; ++j) dbe3[i][j] = dbe[3 * i + j];
     for (int j = 0; j < 6; ++j) dg3[i][j] = dg[6 * i + j];
   }
-  sources_point(&e, &m, alpha, w, bt, u, dal, dbe3, dg3, K6, G);
+  sources_point(&e, &m, alpha, w, bt, u, dal, dbe3, dg3, K6, G, NULL);
   return 0;
 }
 
