@@ -530,9 +530,11 @@ __global__ __launch_bounds__(kT) void k_mlp_adam(int nwg, const float* partial, 
   for (int w = 0; w < nwg; ++w) g += partial[(int64_t)w * kNParam + x];
   if (grad_out) grad_out[x] = g;
   if (!apply) return;
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float a = b1 * m1[x] + (1.f - b1) * g;
-  const float v = b2 * m2[x] + (1.f - b2) * g * g;
+  // decay rates 0.9 and 0.999 with their complements written out: 1.f - 0.999f
+  // would be 1.3e-5 off 0.001 (0.999 is not exact in fp32)
+  const float b1 = 0.9f, b2 = 0.999f, ob1 = 0.1f, ob2 = 0.001f, eps = 1e-8f;
+  const float a = b1 * m1[x] + ob1 * g;
+  const float v = b2 * m2[x] + ob2 * g * g;
   m1[x] = a;
   m2[x] = v;
   const float th = theta[x] - lr * (a / c1) / (sqrtf(v / c2) + eps);
@@ -687,8 +689,9 @@ int c2p_mlp_train_step(float* theta, float* adam_m, float* adam_v, uint16_t* the
   hipStream_t s = (hipStream_t)stream;
   TIMED(T_MLP_TRAIN, s);
   k_mlp_train<<<nwg, 64, 0, s>>>(nbatch, feats, target, theta_bf16, theta, partial, loss_part);
-  const float c1 = apply ? 1.0f - powf(0.9f, (float)step) : 1.f;
-  const float c2 = apply ? 1.0f - powf(0.999f, (float)step) : 1.f;
+  // bias corrections 1 - 0.9^t and 1 - 0.999^t in double, then rounded once
+  const float c1 = apply ? (float)(1.0 - pow(0.9, (double)step)) : 1.f;
+  const float c2 = apply ? (float)(1.0 - pow(0.999, (double)step)) : 1.f;
   k_mlp_adam<<<(kNParam + kT - 1) / kT, kT, 0, s>>>(nwg, partial, theta, adam_m, adam_v, theta_bf16,
                                                    lr, c1, c2, apply, grad_out);
   if (loss_part && loss_out) k_sum_loss<<<1, 64, 0, s>>>(nwg, loss_part, loss_out);

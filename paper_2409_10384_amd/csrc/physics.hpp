@@ -243,7 +243,15 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
 // following the noise's sign.
 constexpr double kMassFluxZero = 1e-12;
 
+// No contraction to FMA here (the library is built without it, and this
+// function says so on its own): the two sides enter the flux formula as
+// mirror images (L <-> R with the normal components negated), and a fused
+// product keeps one side's product exact while the other's is rounded, so a
+// mirror-symmetric state would get fluxes that are not mirror images bit for
+// bit.  With every product rounded, the flux of the mirrored state is the
+// mirrored flux exactly.
 __device__ __forceinline__ void riemann(int kind, const Side& L, const Side& R, double F[7]) {
+#pragma clang fp contract(off)
   double scale;
   if (kind == 0) {
     double a = fmax(fmax(fabs(L.lm), fabs(L.lp)), fmax(fabs(R.lm), fabs(R.lp)));

@@ -137,7 +137,15 @@ def test_adam_steps_match_oracle(G):
     assert int(live.sum()) > 8000
     assert e_upd <= 1e-4 * lr
     assert np.max(np.abs(upd_ref[live])) > 0.5 * lr          # the steps are not trivially small
-    np.testing.assert_allclose(m[live], opt.m[0][0][live], rtol=1e-5, atol=1e-12)
+    # first moments: 0.09 g1 + 0.1 g2 cancels where the two gradients have
+    # opposite signs, so the fp32 moment (its coefficients 0.9f and 1 - 0.9f
+    # are 3e-8 and 2.4e-7 off 0.9 and 0.1, each product and sum rounded to
+    # 6e-8) is judged against the size of its terms; the second moments are
+    # sums of positive terms and keep the relative bar
+    terms = 0.09 * np.abs(grads[0]) + 0.1 * np.abs(grads[1])
+    e_m = np.abs(m - opt.m[0][0])[live] / (terms[live] + 1e-30)
+    say(f"  max |m - oracle m| / (0.09|g1| + 0.1|g2|) {np.max(e_m):.2e}")
+    assert np.max(e_m) <= 1e-6
     np.testing.assert_allclose(v[live], opt.v[0][0][live], rtol=1e-5, atol=1e-20)
     # the bf16 copy follows the updated fp32 parameters
     tb = net.theta_h.cpu().numpy().astype(np.int16).view(np.uint16).astype(np.uint32) << 16
