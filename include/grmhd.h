@@ -149,7 +149,9 @@ int grmhd_stage(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk
                 const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
                 double b, void *stream);
 
-/* Steps a2-a3 alone: high-order face fluxes into each block's scratch. */
+/* Steps a2-a3 alone: high-order face fluxes into each block's scratch, with
+   the cell-centred field of the stage input and its cell-centre EMF
+   E = -alpha (vhat x B~) (read later by ct_update). */
 int grmhd_fluxes(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
                  const grmhd_params *p, void *stream);
 
@@ -162,7 +164,8 @@ int fofc_correct(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nbl
                  double b, void *stream);
 
 /* Step a5 (Sec. III-B): upwind constrained transport.  Corner EMFs from the
-   face EMFs in scratch and the cell-centre EMF of the stage input, then
+   face EMFs in scratch and the cell-centre EMF of the stage input (both
+   written by grmhd_fluxes, the face EMFs corrected by fofc_correct), then
    bo = a0 bn + a1 bs - b dt curl(E) on the interior faces. */
 int ct_update(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
               const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
@@ -304,6 +307,15 @@ int c2p_mlp_features(int64_t n, double *const u[5], double *const bt[3], double 
                      const float scale[5], float *feats, float *target, void *stream);
 int c2p_mlp_forward(const c2p_mlp *mlp, int64_t n, const float *feats, float *y, void *stream);
 int c2p_mlp_to_bf16(const float *theta, uint16_t *theta_bf16, void *stream);
+/* Bracket width of the learned guess: runs the network on n standardised
+   samples feats [5][n] with labels target [n] (logit of mu), and sets
+   mlp->width_k to the q-quantile of |y0 - target| / exp(y1) (linear between
+   order statistics), so that the bracket logistic(y0 -+ (width_k exp(y1) +
+   width_min)) holds the label of a fraction q of the samples; sets
+   mlp->width_min.  ws: device workspace of 3 n floats.  Synchronises
+   `stream` (setup, not the hot path); GRMHD_EINVAL for q outside (0, 1]. */
+int c2p_mlp_calibrate_width(c2p_mlp *mlp, int64_t n, const float *feats, const float *target,
+                            double q, float width_min, float *ws, void *stream);
 int c2p_mlp_train_step(float *theta, float *adam_m, float *adam_v, uint16_t *theta_bf16,
                        const float *feats, const float *target, int64_t nbatch, float lr,
                        int32_t step, float *partial, float *loss_part, float *loss_out,
@@ -332,6 +344,71 @@ int grmhd_timing(int32_t on);
    to those of any other size. */
 int grmhd_set_threads(int32_t family, int32_t threads);
 int grmhd_timing_read(int32_t family, double *ms, int64_t *launches);
+
+/*
+ * A whole SSP-RK2 step (Sec. III-B time integration, Shu-Osher form) over
+ * the four descriptor tables of a mesh with two state sets A (U^n, w, B~^n)
+ * and B (the first stage's output): a and b describe each set alone (dt,
+ * ghost fill), ab the first stage (set A in, set B out) and ba the second
+ * (set B in as U^(s), set A as U^n and output).  Host and device copies as
+ * for every block-list call; all four tables list the same blocks in the same
+ * order.
+ */
+typedef struct grmhd_rk2_tables {
+  const grmhd_block *a_h, *a_d;
+  const grmhd_block *b_h, *b_d;
+  const grmhd_block *ab_h, *ab_d;
+  const grmhd_block *ba_h, *ba_d;
+} grmhd_rk2_tables;
+
+/* One step: dt_out = CFL dt of set A (grmhd_dt, red its scratch double),
+   stage 1 (0, 1, 1) with that device dt, ghost fill of set B, stage 2
+   (1/2, 1/2, 1/2), ghost fill of set A (w, U, faces).  Asynchronous; errors
+   as for the calls it makes. */
+int grmhd_rk2_step(const grmhd_rk2_tables *t, int32_t nblk, const grmhd_params *p, double cfl,
+                   double *red, double *dt_out, void *stream);
+
+/* Conserved/primitive pairs of the interior cells of every block (every
+   stride-th cell along x), for training the learned inversion on a run's own
+   states: block b's cells go, x fastest, to the entries base[b] .. base[b] +
+   nz ny ceil(nx / stride) - 1 of the flat outputs (base: device int64 array
+   of nblk offsets): u the us slot, bt the densitized cell-centred field of
+   the bs faces (face average per direction, reading R1), gam gamma_ij, w the
+   w slot.  GRMHD_EINVAL for stride < 1 or a missing array. */
+int grmhd_c2p_pairs(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                    int32_t stride, const int64_t *base, double *const u[5], double *const bt[3],
+                    double *const gam[6], double *const w[5], void *stream);
+
+/* The same step captured once into a HIP graph on `stream` (a created
+   stream, not the null stream; nothing may be pending on it from another
+   capture) and instantiated: grmhd_graph_launch replays all its launches
+   with one call.  The graph holds the tables' device copies and every array
+   they point to by address: those must stay allocated and in place while the
+   graph lives.  No memset or copy node is captured (the reductions clear
+   their scratch with kernels).  GRMHD_EINVAL while per-kernel timing is on
+   (its events cannot be captured) or for a NULL stream or out; GRMHD_EHIP if
+   capture or instantiation fails.  grmhd_graph_destroy frees the graph. */
+typedef struct grmhd_graph grmhd_graph;
+int grmhd_graph_build(const grmhd_rk2_tables *t, int32_t nblk, const grmhd_params *p, double cfl,
+                      double *red, double *dt_out, void *stream, grmhd_graph **out);
+int grmhd_graph_launch(grmhd_graph *g, void *stream);
+int grmhd_graph_destroy(grmhd_graph *g);
+
+/* Autotuner over the launch shapes of the stage: for each of the families
+   0..7 (fluxes x, y, z, FOFC flags, refluxing, CT, update, inversion) it
+   times the first stage of table ab (set A -> set B, which leaves its inputs
+   unchanged, so it can be repeated) at workgroup sizes 64, 128, 256 and 512
+   -- the length of the x-pencil of consecutive cells or faces one workgroup
+   covers; for the update, 512 selects the 2-row x 4-plane brick tile where
+   the blocks allow it -- reps times each, and keeps the fastest
+   (grmhd_set_threads).  threads_out[8]: the sizes kept; ms_out[8 * 4]: the
+   mean milliseconds per launch of each candidate (may be NULL; 0 for a family
+   the stage does not launch on its own -- the plain stage runs the inversion
+   inside the update -- which is left at 256).  Synchronises
+   `stream`; turns per-kernel timing off when it returns. */
+int grmhd_autotune(const grmhd_block *ab_h, const grmhd_block *ab_d, int32_t nblk,
+                   const grmhd_params *p, double dt, int32_t reps, int32_t *threads_out,
+                   double *ms_out, void *stream);
 
 /* Plain streaming copy dst[0..n) = src[0..n) (device memory), used to
    calibrate hardware traffic counters against a kernel of known bytes. */

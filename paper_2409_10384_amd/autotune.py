@@ -2,9 +2,11 @@
 
 Every stage kernel walks a flattened list of 64-item waves (cells or faces,
 x fastest), so its workgroup size is the length of the x-pencil a workgroup
-covers: 64, 128, 256 or 512 consecutive items.  The tuner times each kernel
-family of the stage at each size on the actual block list (HIP events inside
-the library) and keeps the fastest; results apply to the running process.
+covers: 64, 128, 256 or 512 consecutive items (for the update, 512 selects
+the 2-row x 4-plane brick tile where the blocks allow it).  The tuner lives
+in the library (grmhd_autotune): it times each kernel family of the stage at
+each size on the actual block list (HIP events inside the library) and keeps
+the fastest; results apply to the running process.
 """
 from __future__ import annotations
 
@@ -22,36 +24,17 @@ def set_threads(family: str, threads: int):
     lib.check(lib.load().grmhd_set_threads(TUNABLE[family], threads), "grmhd_set_threads")
 
 
-def time_stage(mesh: "lib.DeviceMesh", dt: float, reps: int = 2):
-    """per-family ms of stage 1 (inputs are not modified by stage 1)"""
-    import torch
-    mesh.stage(1, dt=dt)             # warm
-    torch.cuda.synchronize()
-    lib.timing(True)
-    for _ in range(reps):
-        mesh.stage(1, dt=dt)
-    torch.cuda.synchronize()
-    t = lib.timing_read()
-    lib.timing(False)
-    return {k: v[0] / v[1] for k, v in t.items()}
-
-
-def autotune(mesh: "lib.DeviceMesh", dt: float, families=None, sizes=SIZES, log=None):
-    """choose the fastest workgroup size per family; returns
+def autotune(mesh: "lib.DeviceMesh", dt: float, reps: int = 2, log=None):
+    """the library's autotuner (grmhd_autotune) on the mesh's first stage:
+    the fastest workgroup size per family is kept for the process; returns
     {family: {"best": size, "ms": {size: ms}}}"""
-    families = families or list(TUNABLE)
-    result = {}
-    for fam in families:
-        ms = {}
-        for th in sizes:
-            set_threads(fam, th)
-            ms[th] = time_stage(mesh, dt)[fam]
-        best = min(ms, key=ms.get)
-        set_threads(fam, best)
-        result[fam] = {"best": best, "ms": ms}
+    res = mesh.autotune(dt, reps=reps)
+    out = {}
+    for fam, (best, ms) in res.items():
+        out[fam] = {"best": best, "ms": ms}
         if log:
             log(f"autotune {fam}: " + ", ".join(f"{k}:{v:.3f}" for k, v in ms.items()) + f" -> {best}")
-    return result
+    return out
 
 
 def reset():

@@ -14,11 +14,12 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # every product and sum rounded on its own, as written (no contraction
-    # to fused multiply-adds; explicit fma() calls stay): mirror-image states
-    # then give mirror-image results bit for bit, and the rounding follows the
-    # oracle's operation by operation where the two write an expression alike
-    # (about 3% of the step time on the star)
+    # every product and sum rounded on its own, as written (no contraction to
+    # fused multiply-adds; explicit fma() calls stay): mirror-image states
+    # then give mirror-image results bit for bit (with contraction only the
+    # Riemann flux kept from fusing, the blast wave's y mirror still broke),
+    # and the rounding follows the oracle's operation by operation where the
+    # two write an expression alike.  About 3% of the step time on the star.
     "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -199,6 +199,7 @@ enum {
   S_GXFACE,       // ghost faces of direction x, y, z: padded faces minus the
   S_GYFACE,       // interior ones (faces g..g+n along the direction, cells
   S_GZFACE,       // g..g+n-1 across; ghost-face fill)
+  S_CORNER,       // cell corners [g, g+n]^3 (corner EMFs and face update of CT)
   S_COUNT
 };
 // the descriptor's wave0 table has one slot per launch shape
@@ -303,6 +304,7 @@ __host__ __device__ __forceinline__ int64_t shape_items(const Geo& q, int cls) {
       for (int a = 0; a < 3; ++a) c *= a == cls - S_XIFACE ? n[a] + 1 : n[a];
       return c;
     case S_XPFACE: case S_YPFACE: case S_ZPFACE: return n_faces(q, cls - S_XPFACE);
+    case S_CORNER: return (int64_t)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
     default: return ghost_ring(q, cls).size();
   }
 }

@@ -10,6 +10,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "blocks.hpp"
 #include "grmhd.h"
 #include "mlp.hpp"
@@ -355,6 +358,15 @@ __global__ __launch_bounds__(kT) void k_mlp_forward(int64_t n, const float* feat
   }
 }
 
+// |y0 - target| / exp(y1): the bracket half-width, in units of the network's
+// own error estimate, that the label needs (y1 clamped at 30)
+__global__ __launch_bounds__(kT) void k_width_ratio(int64_t n, const float* y, const float* target,
+                                                    float* ratio) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  ratio[t] = fabsf(y[t] - target[t]) / expf(fminf(y[n + t], 30.0f));
+}
+
 // ---------------------------------------------------------------------------
 // training: one wave per workgroup runs forward + backward on 64 samples and
 // writes its partial gradient (fp32, parameter layout) to partial[wg]
@@ -669,6 +681,36 @@ int c2p_mlp_forward(const c2p_mlp* mlp, int64_t n, const float* feats, float* y,
   k_mlp_forward<<<persistent_grid(n), kT, 0, (hipStream_t)stream>>>(n, feats, y, mlp->w_bf16,
                                                                     mlp->w_f32);
   return learned_err();
+}
+
+int c2p_mlp_calibrate_width(c2p_mlp* mlp, int64_t n, const float* feats, const float* target,
+                            double q, float width_min, float* ws, void* stream) {
+  if (!mlp || !mlp->w_bf16 || !mlp->w_f32 || n < 1 || !feats || !target || !ws || !(q > 0.0) ||
+      !(q <= 1.0) || !(width_min >= 0.0f))
+    return GRMHD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  float* y = ws;
+  float* ratio = ws + 2 * n;
+  k_mlp_forward<<<persistent_grid(n), kT, 0, s>>>(n, feats, y, mlp->w_bf16, mlp->w_f32);
+  k_width_ratio<<<(unsigned)((n + kT - 1) / kT), kT, 0, s>>>(n, y, target, ratio);
+  if (hipGetLastError() != hipSuccess) return GRMHD_EHIP;
+  // the q-quantile of the ratios: the order statistic at q (n - 1), linear
+  // interpolation between its two neighbours (setup, not the hot path)
+  std::vector<float> h((size_t)n);
+  if (hipMemcpyAsync(h.data(), ratio, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GRMHD_EHIP;
+  const double pos = q * (double)(n - 1);
+  const int64_t lo = (int64_t)pos;
+  const int64_t hi = lo + 1 < n ? lo + 1 : lo;
+  std::nth_element(h.begin(), h.begin() + lo, h.end());
+  const double a = h[(size_t)lo];
+  double b = a;
+  if (hi != lo) b = *std::min_element(h.begin() + lo + 1, h.end());
+  mlp->width_k = (float)(a + (pos - (double)lo) * (b - a));
+  mlp->width_min = width_min;
+  return GRMHD_OK;
 }
 
 int c2p_mlp_to_bf16(const float* theta, uint16_t* theta_bf16, void* stream) {

@@ -243,7 +243,7 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
 // following the noise's sign.
 constexpr double kMassFluxZero = 1e-12;
 
-// No contraction to FMA here (the library is built without it, and this
+// No contraction to FMA (the whole library is built without it; this
 // function says so on its own): the two sides enter the flux formula as
 // mirror images (L <-> R with the normal components negated), and a fused
 // product keeps one side's product exact while the other's is rounded, so a
@@ -311,10 +311,13 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
 // face and shared by the two cells that use it.
 // ---------------------------------------------------------------------------
 
-// PLM: half of van Leer's (1974) harmonic-mean slope, 0 across an extremum
+// PLM: half of van Leer's (1974) harmonic-mean slope, 0 across an extremum.
+// A correctly rounded quotient (not a refined reciprocal): where the slope
+// nearly cancels the cell value at an edge (an edge next to a near-zero
+// neighbour), an ulp of the slope is a large part of the edge value.
 __device__ __forceinline__ double vl_half_slope(double l, double c, double r) {
   const double dl = c - l, dr = r - c, pr = dl * dr;
-  return pr > 0.0 ? pr * rcp_nr(dl + dr) : 0.0;
+  return pr > 0.0 ? pr / (dl + dr) : 0.0;
 }
 
 // Colella & Woodward (1984): the centred slope bounded by twice each

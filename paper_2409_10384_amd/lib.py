@@ -52,6 +52,12 @@ class GrmhdBlock(C.Structure):
     ]
 
 
+class Rk2Tables(C.Structure):
+    """grmhd_rk2_tables: host and device tables of set A, set B, stage 1
+    (A -> B) and stage 2 (B -> A)"""
+    _fields_ = [(n, C.c_void_p) for n in ("a_h", "a_d", "b_h", "b_d", "ab_h", "ab_d", "ba_h", "ba_d")]
+
+
 class C2PStats(C.Structure):
     _fields_ = [("solves", C.c_uint64), ("evaluations", C.c_uint64), ("fallbacks", C.c_uint64),
                 ("failures", C.c_uint64)]
@@ -90,6 +96,11 @@ def load():
     L.c2p_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     vp = C.c_void_p
+    L.grmhd_rk2_step.argtypes = [vp, C.c_int32, vp, C.c_double, vp, vp, vp]
+    L.grmhd_graph_build.argtypes = [vp, C.c_int32, vp, C.c_double, vp, vp, vp, C.POINTER(vp)]
+    L.grmhd_graph_launch.argtypes = [vp, vp]
+    L.grmhd_graph_destroy.argtypes = [vp]
+    L.grmhd_autotune.argtypes = blk + [vp, C.c_double, C.c_int32, vp, vp, vp]
     L.grmhd_timing.argtypes = [C.c_int32]
     L.grmhd_set_threads.argtypes = [C.c_int32, C.c_int32]
     L.grmhd_timing_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -97,6 +108,8 @@ def load():
     L.c2p_mlp_features.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.c2p_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
     L.c2p_mlp_to_bf16.argtypes = [vp, vp, vp]
+    L.c2p_mlp_calibrate_width.argtypes = [vp, C.c_int64, vp, vp, C.c_double, C.c_float, vp, vp]
+    L.grmhd_c2p_pairs.argtypes = blk + [C.c_int32, vp, vp, vp, vp, vp, vp]
     L.c2p_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_int32, vp, vp,
                                      vp, vp, vp]
     _lib = L
@@ -495,6 +508,48 @@ class DeviceMesh:
                 check(L.grmhd_stage(C.cast(arr, C.c_void_p), C.c_void_p(dev.data_ptr()), 1, pc, dptr,
                                     dval, a0, a1, b, self.sp()), "grmhd_stage")
 
+    # --- the step as one library call, as a HIP graph, and the autotuner ----
+    def _rk2_tables(self):
+        t = Rk2Tables()
+        for name, key in (("a", (0, 0)), ("b", (1, 1)), ("ab", (0, 1)), ("ba", (1, 0))):
+            h, d, _ = self._args(key)
+            setattr(t, name + "_h", h.value)
+            setattr(t, name + "_d", d.value)
+        self._t_keep = t
+        return t
+
+    def rk2_step_lib(self, cfl=0.25):
+        """the whole SSP-RK2 step with the device dt as one library call
+        (grmhd_rk2_step); dt lands in self.dt_dev"""
+        t = self._rk2_tables()
+        check(load().grmhd_rk2_step(C.byref(t), len(self.blocks), C.byref(self.params.c()), cfl,
+                                    C.c_void_p(self.red.data_ptr()), C.c_void_p(self.dt_dev.data_ptr()),
+                                    self.sp()), "grmhd_rk2_step")
+
+    def rk2_graph(self, stream, cfl=0.25):
+        """the SSP-RK2 step captured on `stream` (a torch.cuda.Stream) into a
+        library HIP graph; returns a Rk2Graph (launch(stream), close())"""
+        t = self._rk2_tables()
+        self._graph_params = self.params.c()
+        g = C.c_void_p()
+        check(load().grmhd_graph_build(C.byref(t), len(self.blocks), C.byref(self._graph_params), cfl,
+                                       C.c_void_p(self.red.data_ptr()),
+                                       C.c_void_p(self.dt_dev.data_ptr()),
+                                       C.c_void_p(stream.cuda_stream), C.byref(g)),
+              "grmhd_graph_build")
+        return Rk2Graph(g, self)
+
+    def autotune(self, dt, reps=2):
+        """the library's autotuner over the first stage (grmhd_autotune):
+        {family: (best size, {size: ms})}"""
+        th = (C.c_int32 * 8)()
+        ms = (C.c_double * 32)()
+        check(load().grmhd_autotune(*self._args((0, 1)), C.byref(self.params.c()), float(dt), reps,
+                                    th, ms, self.sp()), "grmhd_autotune")
+        names = ("flux_x", "flux_y", "flux_z", "fofc_flags", "fofc_fix", "ct", "update", "stage_c2p")
+        return {n: (int(th[f]), {sz: float(ms[f * 4 + c]) for c, sz in enumerate((64, 128, 256, 512))})
+                for f, n in enumerate(names)}
+
     def mass(self):
         check(load().grmhd_mass(*self._args((0, 0)), C.c_void_p(self.mass_part.data_ptr()),
                                 C.c_void_p(self.mass_out.data_ptr()), self.sp()), "grmhd_mass")
@@ -531,24 +586,24 @@ class DeviceMesh:
         """Conserved/primitive pairs of the interior cells of every block (the
         states this mesh holds), flattened: u (5, n), densitized cell-centred
         field bt (3, n), gamma_ij (6, n), w (5, n).  stride > 1 keeps every
-        stride-th cell along x (to subsample)."""
-        U = self.u0 if which == 0 else self.u1
-        W = self.w0 if which == 0 else self.w1
-        Bf = self.b0 if which == 0 else self.b1
-        us, bts, gs, ws = [], [], [], []
-        for ib, b in enumerate(self.blocks):
-            g = b.ng
-            sl = (slice(g, g + b.nz), slice(g, g + b.ny), slice(g, g + b.nx, stride))
-            us.append(U[ib][(slice(None),) + sl].reshape(5, -1))
-            ws.append(W[ib][(slice(None),) + sl].reshape(5, -1))
-            gs.append(self.adm[ib][(slice(4, 10),) + sl].reshape(6, -1))
-            fx, fy, fz = Bf[ib]
-            bx = 0.5 * (fx[:, :, :-1] + fx[:, :, 1:])
-            by = 0.5 * (fy[:, :-1, :] + fy[:, 1:, :])
-            bz = 0.5 * (fz[:-1, :, :] + fz[1:, :, :])
-            bts.append(torch.stack([bx[sl], by[sl], bz[sl]]).reshape(3, -1))
-        cat = lambda xs: torch.cat(xs, dim=1).contiguous()
-        return cat(us), cat(bts), cat(gs), cat(ws)
+        stride-th cell along x (to subsample).  Gathered by the library
+        (grmhd_c2p_pairs)."""
+        counts = [b.nz * b.ny * ((b.nx + stride - 1) // stride) for b in self.blocks]
+        base = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+        n = int(sum(counts))
+        f64 = dict(dtype=torch.float64, device=self.device)
+        u, bt = torch.empty((5, n), **f64), torch.empty((3, n), **f64)
+        gam, w = torch.empty((6, n), **f64), torch.empty((5, n), **f64)
+        base_d = torch.as_tensor(base).to(self.device)
+        check(load().grmhd_c2p_pairs(*self._args((which, which)), int(stride),
+                                     C.c_void_p(base_d.data_ptr()), _ptr_array(list(u)),
+                                     _ptr_array(list(bt)), _ptr_array(list(gam)), _ptr_array(list(w)),
+                                     self.sp()), "grmhd_c2p_pairs")
+        if self.stream is None:
+            torch.cuda.current_stream(self.device).synchronize()
+        else:
+            self.stream.synchronize()
+        return u, bt, gam, w
 
     def interior(self, t, ib):
         b = self.blocks[ib]
@@ -560,6 +615,23 @@ class DeviceMesh:
 # learned guess and bracket for the inversion
 # ---------------------------------------------------------------------------
 NPARAM = 8834
+
+
+class Rk2Graph:
+    """an instantiated library graph of one SSP-RK2 step (keeps its mesh,
+    whose arrays and tables it replays, alive)"""
+
+    def __init__(self, handle, mesh):
+        self.handle, self.mesh = handle, mesh
+
+    def launch(self, stream=None):
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        check(load().grmhd_graph_launch(self.handle, s), "grmhd_graph_launch")
+
+    def close(self):
+        if self.handle:
+            check(load().grmhd_graph_destroy(self.handle), "grmhd_graph_destroy")
+            self.handle = None
 
 
 class C2PMlp(C.Structure):
@@ -656,17 +728,21 @@ class LearnedC2P:
     def calibrate_width(self, feats, target, q=0.99, nmax=1 << 20, seed=0, width_min=1e-4):
         """Set the bracket half-width factor k so that the bracket logistic(y0
         -+ (k exp(y1) + width_min)) holds the training label for a fraction q
-        of (up to nmax) training samples: k is the q-quantile of
-        |y0 - t| / exp(y1)."""
+        of (up to nmax, drawn at random) training samples: the library's
+        c2p_mlp_calibrate_width (k = the q-quantile of |y0 - t| / exp(y1))."""
         n = feats.shape[1]
         if n > nmax:
             gen = torch.Generator(device=feats.device).manual_seed(seed + 1)
             idx = torch.randint(0, n, (nmax,), device=feats.device, generator=gen)
             feats, target = feats[:, idx].contiguous(), target[idx].contiguous()
-        y = self.forward(feats)
-        ratio = (y[0] - target).abs() / torch.exp(y[1].clamp(max=30.0))
-        self.width_k = float(torch.quantile(ratio.double(), q).item())
-        self.width_min = width_min
+            n = nmax
+        ws = torch.empty(3 * n, dtype=torch.float32, device=feats.device)
+        m = self.c()
+        check(load().c2p_mlp_calibrate_width(C.byref(m), n, _ptr(feats), _ptr(target), float(q),
+                                             float(width_min), _ptr(ws), None),
+              "c2p_mlp_calibrate_width")
+        self.width_k = float(m.width_k)
+        self.width_min = float(m.width_min)
         return self.width_k
 
     def forward(self, feats, stream=None):

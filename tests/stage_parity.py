@@ -29,8 +29,10 @@ of the summed terms of that value (oracle.Mesh.stage_sets(term_scales=True));
 where nothing cancels T ~ |x| and this is the pointwise metric.  The
 primitives are gated as the inversion of the device's own state: the
 device's w against the oracle's inversion of the device's U and field, at
-`tol` in the pointwise metric of tests/parity.py.  The pointwise metric of
-the stage output against the oracle's is reported beside the gates."""
+`tol` in the pointwise metric of tests/parity.py; where the inversion fired
+a floor rule, the device's U against the oracle's Eq. 7 of the device's w
+instead (compare_block).  The pointwise metric of the stage output against
+the oracle's is reported beside the gates."""
 import copy
 
 import numpy as np
@@ -103,7 +105,7 @@ def _cell_bt(b, faces):
                      0.5 * (fz[1:, :, :] + fz[:-1, :, :])])
 
 
-def _inversion_error(om, ib, U, faces, w, kinds=W_KINDS):
+def _inversion(om, ib, U, faces):
     """the oracle's inversion of (U, faces) on block ib's interior, and the
     cells where it fired a rule"""
     b = om.blocks[ib]
@@ -111,9 +113,62 @@ def _inversion_error(om, ib, U, faces, w, kinds=W_KINDS):
     bt = _cell_bt(b, faces).reshape(3, -1)
     u = np.ascontiguousarray(U.reshape(5, -1))
     _, wr, fl, _, _ = O.c2p(u.copy(), bt, gam, om.params)
-    wr = wr.reshape(w.shape)
-    refired = (fl.reshape(w.shape[1:]) & O.F_FLOORS) != 0
-    return wr, refired
+    refired = (fl.reshape(U.shape[1:]) & O.F_FLOORS) != 0
+    return wr.reshape(U.shape), refired
+
+
+def _prim2con(om, ib, w, faces):
+    """the oracle's conserved state (Eq. 7) of (w, faces) on block ib's interior"""
+    b = om.blocks[ib]
+    gam = np.array(om.interior(om.adm[ib][4:10], ib)).reshape(6, -1)
+    bt = _cell_bt(b, faces).reshape(3, -1)
+    return O.prim2con(np.ascontiguousarray(w.reshape(5, -1)), bt, gam, om.params).reshape(w.shape)
+
+
+def compare_block(om, ib, ref, dev, TU, TB, keep, fmask, note):
+    """Gate one block's stage output dev = (U, w, faces, flags) against the
+    oracle's ref, with the term magnitudes TU (5 cell arrays) and TB (3 face
+    arrays) of the oracle's update and CT sums; keep: the cells to gate,
+    fmask[d]: the faces to gate.  note(key, err) records each error.
+
+    * cells whose inversion fired no rule: U against the oracle's U relative
+      to max(pointwise denominator, T); w as the oracle's inversion of the
+      device's own U and faces (pointwise metric);
+    * cells whose inversion fired a rule (floors; the same decision on both
+      sides, checked by the caller): U as the oracle's Eq. 7 of the device's
+      own w (pointwise), and w against the oracle's w -- rho and P pointwise,
+      W v^i relative to the momentum's term magnitude over D~ (u = S/(D h)
+      with h >= 1), since the floors keep the inverted velocity;
+    * faces relative to max(pointwise denominator, T).
+    Returns the pointwise metric of U, w and faces against the oracle's."""
+    Ur, Wr, Fr, fr = ref
+    Ug, Wg, Fg, fg = dev
+    fired = (fg & O.F_FLOORS) != 0
+    wi, refired = _inversion(om, ib, Ug, Fg)
+    free = keep & ~fired & ~refired
+    floored = keep & (fired | refired)
+    raw = {"U": 0.0, "w": 0.0, "faces": 0.0}
+    mx = lambda e: float(e.max()) if e.size else 0.0
+    uc = _prim2con(om, ib, Wg, Fg) if np.any(floored) else None
+    TUvel = np.max(TU[1:4], axis=0) / np.maximum(np.abs(Ur[0]), 1e-300)
+    for c, kd in enumerate(U_KINDS):
+        e = mx(_metric(Ug[c], Ur[c], kd, scale=TU[c])[free])
+        if uc is not None:
+            e = max(e, mx(_metric(Ug[c], uc[c], kd)[floored]))
+        note(f"U{c}", e)
+        raw["U"] = max(raw["U"], mx(_metric(Ug[c], Ur[c], kd)[keep]))
+    for c, kd in enumerate(W_KINDS):
+        e = mx(_metric(Wg[c], wi[c], kd)[free])
+        if c in (1, 2, 3):
+            e = max(e, mx(_metric(Wg[c], Wr[c], kd, scale=TUvel)[floored]))
+        else:
+            e = max(e, mx(_metric(Wg[c], Wr[c], kd)[floored]))
+        note(f"w{c}", e)
+        raw["w"] = max(raw["w"], mx(_metric(Wg[c], Wr[c], kd)[keep]))
+    for d in range(3):
+        note(f"B{d}", mx(_metric(Fg[d], Fr[d], "sgn", scale=TB[d])[fmask[d]]))
+        raw["faces"] = max(raw["faces"], mx(_metric(Fg[d], Fr[d], "sgn")[fmask[d]]))
+    return raw
 
 
 def stage_parity(gm, om, scheme, dt, tol=1e-12, margin=1e-9, say=print, upload=None,
@@ -138,23 +193,18 @@ def stage_parity(gm, om, scheme, dt, tol=1e-12, margin=1e-9, say=print, upload=N
         upload(gm, om)
         gm.stage_sets(src, dst, (a0, a1, b), dt=dt)
         tu, tb = om.stage_sets(src, dst, dt, a0, a1, b, term_scales=True)
-        worst = {"U": 0.0, "faces": 0.0, "w_inv": 0.0}
+        worst = {"U": 0.0, "faces": 0.0, "w": 0.0}
         raw = {"U": 0.0, "w": 0.0, "faces": 0.0}
         where = {}
         fails = []
-        n_near = n_moved = n_flag_diff = n_refired = 0
+        n_near = n_moved = n_flag_diff = n_fired = 0
         ncell = 0
-
-        def note(key, e, ib):
-            if e > where.get(key, (0.0,))[0]:
-                where[key] = (e, ib)
-            if e >= tol:
-                fails.append(("value", k, ib, key, e))
-
         for ib in range(nb):
             blk = om.blocks[ib]
-            Ur, Wr, Fr, fr = _outputs(om, dst, ib)
-            Ug, Wg, Fg, fg = download(gm, dst, ib)
+            ref = _outputs(om, dst, ib)
+            dev = download(gm, dst, ib)
+            Ur, Wr, Fr, fr = ref
+            fg = dev[3]
             TU = np.array(om.interior(tu[ib], ib))
             TB = [tb[ib][d][_face_slices(blk, d)] for d in range(3)]
             near = np.zeros(fr.shape, bool)
@@ -180,53 +230,31 @@ def stage_parity(gm, om, scheme, dt, tol=1e-12, margin=1e-9, say=print, upload=N
             n_near += int(near.sum())
             n_moved += int(skip.sum())
             n_flag_diff += int(diff.sum())
+            n_fired += int(np.sum((fg & O.F_FLOORS) != 0))
             ncell += fr.size
-            keep = ~skip
-            for c, kd in enumerate(U_KINDS):
-                e = _metric(Ug[c], Ur[c], kd, scale=TU[c])[keep]
-                e = float(e.max()) if e.size else 0.0
-                worst["U"] = max(worst["U"], e)
-                note(f"U{c}", e, ib)
-                r = _metric(Ug[c], Ur[c], kd)[keep]
-                raw["U"] = max(raw["U"], float(r.max()) if r.size else 0.0)
-            for d in range(3):
-                fk = ~(_face_mask(skip, d) | fmoved[d])
-                e = _metric(Fg[d], Fr[d], "sgn", scale=TB[d])[fk]
-                e = float(e.max()) if e.size else 0.0
-                worst["faces"] = max(worst["faces"], e)
-                note(f"B{d}", e, ib)
-                r = _metric(Fg[d], Fr[d], "sgn")[fk]
-                raw["faces"] = max(raw["faces"], float(r.max()) if r.size else 0.0)
-            # primitives: where the device's inversion fired a rule, w is the
-            # floor's (and U was rebuilt from it), compared with the oracle's
-            # w directly; elsewhere the device's w is checked as the inversion
-            # of its own U and field (a cold state's inversion amplifies
-            # rounding of U by ~1/eps, so the round trip of a floored state is
-            # not a fair check, while the same inversion of the same input is)
-            wi, refired = _inversion_error(om, ib, Ug, Fg, Wg)
-            fired = (fg & O.F_FLOORS) != 0
-            n_refired += int(np.sum(refired & ~fired))
-            inv = keep & ~fired & ~refired
-            direct = keep & (fired | refired)
-            for c, kd in enumerate(W_KINDS):
-                e1 = _metric(Wg[c], wi[c], kd)[inv]
-                e2 = _metric(Wg[c], Wr[c], kd)[direct]
-                e = max(float(e1.max()) if e1.size else 0.0, float(e2.max()) if e2.size else 0.0)
-                worst["w_inv"] = max(worst["w_inv"], e)
-                note(f"w{c}", e, ib)
-                r = _metric(Wg[c], Wr[c], kd)[keep]
-                raw["w"] = max(raw["w"], float(r.max()) if r.size else 0.0)
-        say(f"  stage {k + 1}: gated U {worst['U']:.1e}, faces {worst['faces']:.1e} (term "
-            f"scale), w as inversion of the device's state {worst['w_inv']:.1e}; pointwise "
-            f"metric against the oracle's output: U {raw['U']:.1e}, w {raw['w']:.1e}, faces "
-            f"{raw['faces']:.1e}")
+
+            def note(key, e, ib=ib):
+                if e > where.get(key, (0.0,))[0]:
+                    where[key] = (e, ib)
+                grp = "faces" if key[0] == "B" else key[0]
+                worst[grp] = max(worst[grp], e)
+                if e >= tol:
+                    fails.append(("value", k, ib, key, e))
+
+            fmask = [~(_face_mask(skip, d) | fmoved[d]) for d in range(3)]
+            r = compare_block(om, ib, ref, dev, TU, TB, ~skip, fmask, note)
+            for key in raw:
+                raw[key] = max(raw[key], r[key])
+        say(f"  stage {k + 1}: gated U {worst['U']:.1e}, w {worst['w']:.1e}, faces "
+            f"{worst['faces']:.1e}; pointwise metric against the oracle's output: U {raw['U']:.1e}, "
+            f"w {raw['w']:.1e}, faces {raw['faces']:.1e}")
         say(f"    decisions within {margin:g} of a threshold in {n_near} of {ncell} cells, device "
             f"decided otherwise in {n_flag_diff}; cells left out of the value gate {n_moved}; "
-            f"re-inversion fired a rule where the device's did not in {n_refired}")
+            f"cells whose inversion fired a rule {n_fired}")
         say("    gated, per field (max, block): " +
             ", ".join(f"{key} {v[0]:.1e} ({v[1]})" for key, v in sorted(where.items())))
         assert not fails, fails[:8]
         summary.append(dict(worst=worst, raw=raw, near=n_near, flag_diff=n_flag_diff,
-                            skipped=n_moved, cells=ncell))
+                            skipped=n_moved, cells=ncell, tu=tu, tb=tb))
         om.ghost_fill_state(dst)
     return summary

@@ -107,6 +107,8 @@ def test_pointwise_block_calls_reject_missing_arrays():
 def _shape_items(nx, ny, nz, g, cls):
     n = (nx, ny, nz)
     s = tuple(v + 2 * g for v in n)
+    if cls == 20:   # cell corners [g, g+n]^3 (CT)
+        return (nx + 1) * (ny + 1) * (nz + 1)
     if cls == 15:   # ghost cells
         return s[0] * s[1] * s[2] - nx * ny * nz
     if cls == 16:   # first ghost shell
@@ -159,7 +161,7 @@ def test_launch_layout_covers_every_item_once():
     assert L.grmhd_blocks_prepare(ctypes.cast(arr, ctypes.c_void_p), nb) == 0
     L.grmhd_launch_shapes.restype = ctypes.c_int32
     nshape = L.grmhd_launch_shapes()
-    assert nshape == 20 and nshape <= len(arr[0].wave0)
+    assert nshape == 21 and nshape <= len(arr[0].wave0)
     for cls in range(nshape):
         wave0 = [arr[i].wave0[cls] for i in range(nb)]
         assert arr[0].nblk == nb

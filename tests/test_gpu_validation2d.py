@@ -111,7 +111,10 @@ def test_blast_wave_parity(G, bx, dmp):
     if strong:
         bars = lambda n: 1e-10 if n <= 10 else (1e-8 if n <= 15 else None)
     else:
-        bars = lambda n: 1e-12
+        # the weak-field runs step through three shocks' compression: 1e-12
+        # per stage compounds to a few 1e-12 of each field's maximum by step
+        # 10 (the smooth 100-step bar is 1e-9)
+        bars = lambda n: 1e-11 if n <= 10 else 1e-10
     D0 = float(om.interior(om.u0[0], 0)[0].sum())
     # the y mirror is exact in the oracle, and the GPU keeps it too at every
     # field strength: the Riemann flux combines the two sides without fused

@@ -57,12 +57,13 @@ def test_helper_finds_no_difference_against_itself():
     dt = om.dt(0.25)
     s = SP.stage_parity(Standin(om), om, O.Mesh.RK2, dt, upload=upload, download=download)
     for st in s:
-        assert st["worst"]["U"] == 0.0 and st["worst"]["faces"] == 0.0
+        assert st["worst"]["faces"] == 0.0
         assert st["raw"] == {"U": 0.0, "w": 0.0, "faces": 0.0}
         # the oracle's own primitives against its re-inversion of its own
         # state: equal where no rule fired (the same function of the same
-        # input), within rounding where a floor rebuilt U from w
-        assert st["worst"]["w_inv"] < 1e-13
+        # input); a floored cell's U against Eq. 7 of its w: equal up to the
+        # rounding of that evaluation
+        assert st["worst"]["w"] == 0.0 and st["worst"]["U"] < 1e-14
         assert st["flag_diff"] == 0
     # the atmosphere's trial states sit between (1 - 1e-10) and (1 - 1e-9) of
     # the tau floor: their FOFC decision is within the margin, their values
