@@ -113,6 +113,19 @@ def pmc_fp64():
     return {k: v["flops_per_launch"] for k, v in d.get("kernels", {}).items()}
 
 
+def pmc_step(name, key):
+    """a per-step total (FP64 operations or counted HBM bytes of every kernel
+    of the RK step) from a committed counter summary; None when the kernel
+    sources changed since the counters were taken"""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get(key)
+
+
 def pmc_traffic(family, launches_per_step):
     """HBM bytes per launch of the kernel from the committed counter summary,
     null when the kernel sources changed since the counters were taken"""
@@ -129,28 +142,59 @@ def pmc_traffic(family, launches_per_step):
 
 
 # ---------------------------------------------------------------------------
-def cpu_baseline(st, n_per_side, nb, params_kw, target_s=12.0):
+def cpu_model():
+    """the host CPU's model name (from /proc/cpuinfo, as lscpu shows it)"""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(st, n_per_side, nb, params_kw, target_s=12.0, single_s=6.0):
     """The FP64 oracle as it stands, on one block of the same workload (the
-    block at the star's centre, ghosts frozen at the analytic data), RK2
-    steps until ~target_s seconds of CPU work."""
+    block at the star's centre, ghosts frozen at the analytic data): RK2
+    steps until ~target_s seconds of CPU work with OpenMP over k-slabs on the
+    host's threads, then on one thread for ~single_s seconds."""
     from paper_2409_10384_amd import inputs
     import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     c = n_per_side // 2
     blk = inputs.star_block_numpy(st, c, c, c, n_per_side, nb)
-    m = O.Mesh([blk], O.Params(**params_kw))
-    dt = m.dt(0.25)
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        m.rk2_step(dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > target_s or steps >= 50:
-            break
-    zu = blk.nx * blk.ny * blk.nz * steps / el
-    return {"value": zu, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+
+    def run(budget, max_steps):
+        m = O.Mesh([copy_block(blk)], O.Params(**params_kw))
+        dt = m.dt(0.25)
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            m.rk2_step(dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget or steps >= max_steps:
+                return steps, el
+
+    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    steps, el = run(target_s, 50)
+    O.set_threads(1)
+    s1, e1 = run(single_s, 20)
+    O.set_threads(threads)
+    n = blk.nx * blk.ny * blk.nz
+    return {"value": n * steps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": n * s1 / e1, "steps": s1, "s": e1},
             "sample": f"one {blk.nx}^3 block of the star (frozen ghosts), {steps} RK2 steps, "
-                      f"{el:.1f} s, OpenMP over k-slabs"}
+                      f"{el:.1f} s, OpenMP over k-slabs on {threads} threads; single thread "
+                      f"{s1} steps in {e1:.1f} s"}
+
+
+def copy_block(b):
+    import copy
+    c = copy.copy(b)
+    c.w = np.array(b.w)
+    c.bf = [np.array(x) for x in b.bf]
+    c.adm = np.array(b.adm)
+    return c
 
 
 def copy_bandwidth(torch, lib, n=1 << 27, reps=10):
@@ -197,6 +241,7 @@ def star_section(args, torch, inputs, lib):
         from paper_2409_10384_amd import autotune
         dt0 = float(mesh.compute_dt(0.25).item())
         tuned = {k: v["best"] for k, v in autotune.autotune(mesh, dt0, log=log).items()}
+        tuned.pop("stage_c2p", None)     # fused into the update in the plain stage
     for _ in range(args.warmup):
         mesh.rk2_step(cfl=0.25)
     torch.cuda.synchronize()
@@ -247,10 +292,28 @@ def star_section(args, torch, inputs, lib):
                 tot += ops[k] * v[1]
         fp64 = {"peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "kernels": per,
                 "counted_kernels_tflops": tot / (sum(v[0] for k, v in fam.items() if k in ops) * 1e-3) / 1e12}
+    # the whole step (every kernel of both stages, the ghost fills and dt):
+    # its algorithmic HBM bytes and its FP64 operations (counters of this
+    # build) over the timed ms per step; the binding roofline is the one the
+    # step's minimum time is set by
     sb = step_bytes(blocks)
-    path = {"bound": "hbm", "algorithmic_bytes_per_step": sb,
-            "achieved": sb / (ms / args.steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    path["frac"] = path["achieved"] / HBM_PEAK_GBS
+    step_s = ms / args.steps * 1e-3
+    traffic_step = pmc_step("pmc_traffic.json", "bytes_per_step")
+    hbm = {"bound": "hbm", "algorithmic_bytes_per_step": sb, "achieved": sb / step_s / 1e9,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sb / step_s / 1e9 / HBM_PEAK_GBS,
+           "traffic": traffic_step}
+    flops = pmc_step("pmc_fp64.json", "flops_per_step")
+    scope = "whole SSP-RK2 step: both stages, ghost fills and the dt reduction"
+    if flops:
+        t_fp, t_hbm = flops / (FP64_PEAK_TFS * 1e12), sb / (HBM_PEAK_GBS * 1e9)
+        path = {"bound": "alu", "scope": scope, "achieved": flops / step_s / 1e12,
+                "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": flops / step_s / 1e12 / FP64_PEAK_TFS,
+                "traffic": traffic_step, "flops_per_step": flops, "flops_per_zone_update": flops / ncell,
+                "binding": "fp64" if t_fp >= t_hbm else "hbm",
+                "min_ms_per_step": max(t_fp, t_hbm) * 1e3, "hbm": hbm}
+    else:
+        # FP64 counters not taken on this build: the HBM roofline alone
+        path = dict(hbm, scope=scope, note="FP64 counters of this build not committed")
     mass = float(mesh.mass().item())
     variants = None if args.no_variants else variant_section(args, torch, lib, mesh, params, ncell)
     if tuned:
@@ -339,25 +402,41 @@ def refined_section(args, torch, inputs, lib):
     ms = timed(lambda: mesh.rk2_step(dt=dt))
     res["batched"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
     log(f"refined batched: {ms:.2f} ms/step")
-    tune = autotune.autotune(mesh, dt, log=log)
+    # the library's autotuner (grmhd_autotune) over the pencil length of
+    # every stage kernel family
+    tune = mesh.autotune(dt, reps=2)
+    for fam, (best, ms_c) in tune.items():
+        log(f"autotune {fam}: " + ", ".join(f"{k}:{v:.3f}" for k, v in ms_c.items()) + f" -> {best}")
     ms = timed(lambda: mesh.rk2_step(dt=dt))
     res["batched_autotuned"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3),
-                                "workgroup_sizes": {k: v["best"] for k, v in tune.items()}}
+                                "workgroup_sizes": {k: v[0] for k, v in tune.items()}}
     log(f"refined batched + autotuned: {ms:.2f} ms/step")
-    # whole step (device dt, both stages, ghost fills) captured once, replayed
+    # the whole step with device dt as one library call, and captured once
+    # into the library's HIP graph and replayed
+    ms = timed(lambda: mesh.rk2_step_lib(cfl=0.25))
+    res["library_step_autotuned"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
+    log(f"refined library step (device dt): {ms:.2f} ms/step")
     side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        mesh.rk2_step(cfl=0.25)
-    torch.cuda.current_stream().wait_stream(side)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        mesh.rk2_step(cfl=0.25)
-    ms = timed(g.replay)
+    torch.cuda.synchronize()
+    g = mesh.rk2_graph(side, cfl=0.25)
+    try:
+        def replay():
+            g.launch(side)
+        replay()
+        side.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(side)
+        for _ in range(K):
+            g.launch(side)
+        e1.record(side)
+        side.synchronize()
+        ms = e0.elapsed_time(e1) / K
+    finally:
+        g.close()
     res["graph_autotuned"] = {"ms_per_step": ms, "zone_updates_per_s": ncell / (ms * 1e-3)}
-    log(f"refined graph replay: {ms:.2f} ms/step")
+    log(f"refined library graph replay: {ms:.2f} ms/step")
     autotune.reset()
-    del g
     return res
 
 
@@ -711,8 +790,8 @@ def main():
                                f"{args.blocks_per_side ** 3} MeshBlocks of {args.block}^3 (+3 ghosts), "
                                f"Gamma=2, WENOZ+HLLE, FOFC+DMP M=1.1, SSP-RK2 CFL 0.25",
                    "cells": star["ncell"], "workgroup_sizes": star["workgroup_sizes"]},
-        "roofline": star["roofline"],
-        "path_roofline": star["path"],
+        "roofline": star["path"],
+        "kernel_roofline": star["roofline"],
         "fp64_rate": star["fp64"],
         "kernel_breakdown": star["breakdown"],
         "variants": star["variants"],

@@ -72,6 +72,12 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops (n <= 0 leaves them); returns
+    the number now in use"""
+    return int(lib().or_set_threads(C.c_int(n)))
+
+
 def set_decision_margin(m: float):
     """Move every threshold test of the method by the relative amount m
     (test instrument; 0 restores the method exactly).  Oracle runs at +m and

@@ -94,6 +94,20 @@ enum {
    could send the other way. */
 static double g_margin = 0.0;
 void or_set_decision_margin(double m) { g_margin = m; }
+
+/* OpenMP threads of the oracle's loops (timing of the CPU baseline) */
+#ifdef _OPENMP
+#include <omp.h>
+int or_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
+#else
+int or_set_threads(int n) {
+  (void)n;
+  return 1;
+}
+#endif
 #define THR(x) ((x) * (1.0 + g_margin))
 
 /* Term magnitudes (test instrument, off unless set).  When set, the update

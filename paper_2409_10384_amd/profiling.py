@@ -2,10 +2,12 @@
 
   python -m paper_2409_10384_amd.profiling stats <kernel_stats.csv>
       per-kernel calls, total and average duration (markdown table)
-  python -m paper_2409_10384_amd.profiling fp64 <counter_collection.csv> <out.json>
-      FP64 lane operations per launch from the four FP64 VALU counters
+  python -m paper_2409_10384_amd.profiling fp64 <counter_collection.csv> <out.json> <steps> <tail>
+      FP64 lane operations per launch from the four FP64 VALU counters, and per
+      RK step over the step's kernels (the run profiled executed <steps> steps; means
+      over the last <tail> of them)
   python -m paper_2409_10384_amd.profiling traffic <fetch counter_collection.csv>
-      <write counter_collection.csv> <out.json>
+      <write counter_collection.csv> <out.json> <steps> <tail>
       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel, scaled by what the
       same counters read for the plain copy kernel k_copy of known size
       (1 GiB read + 1 GiB written), written as bytes per launch
@@ -74,31 +76,60 @@ def stats(path):
     return "\n".join(out)
 
 
-def counter_per_kernel(path, counter):
+def counter_per_kernel(path, counter, with_count=False, tail=1.0):
+    """mean value per dispatch of `counter` for each kernel (and, with
+    with_count, the number of dispatches); tail < 1 averages over the last
+    fraction `tail` of each kernel's dispatches only (the steady steps after
+    the first ones, whose FOFC work is larger)"""
     acc = defaultdict(list)
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name", r.get("Counter-Name", "")) != counter:
             continue
         name = short(r.get("Kernel_Name", r.get("Kernel-Name", "")))
-        acc[name].append(float(r.get("Counter_Value", r.get("Counter-Value", 0.0))))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+        did = int(r.get("Dispatch_Id", r.get("Dispatch-Id", len(acc[name]))))
+        acc[name].append((did, float(r.get("Counter_Value", r.get("Counter-Value", 0.0)))))
+    out = {}
+    for k, v in acc.items():
+        v.sort()
+        m = max(1, int(round(len(v) * tail)))
+        vals = [x for _, x in v[-m:]]
+        out[k] = (sum(vals) / len(vals), len(v)) if with_count else sum(vals) / len(vals)
+    return out
 
 
-def traffic(fetch_csv, write_csv, out_json):
-    fetch = counter_per_kernel(fetch_csv, "FETCH_SIZE")
-    write = counter_per_kernel(write_csv, "WRITE_SIZE")
-    f_scale = COPY_BYTES / (fetch["k_copy"] * 1024.0)
-    w_scale = COPY_BYTES / (write["k_copy"] * 1024.0)
-    kernels = {}
-    for k in fetch:
+# kernels that run outside the RK step in a profiled bench run (set-up,
+# diagnostics, counter calibration)
+NOT_IN_STEP = ("k_copy", "k_p2c_block", "k_mass_block", "k_mass_final")
+
+
+def in_step(kname):
+    base = kname.partition("<")[0]
+    return base.startswith("k_") and base not in NOT_IN_STEP
+
+
+def traffic(fetch_csv, write_csv, out_json, steps, tail_steps):
+    """scaled HBM bytes per dispatch of every kernel, per family, and summed
+    over the kernels of the RK step per step (the profiled run executed
+    `steps` steps; per-dispatch means over the last `tail_steps` of them)"""
+    tail = tail_steps / steps
+    fetch = counter_per_kernel(fetch_csv, "FETCH_SIZE", with_count=True, tail=tail)
+    write = counter_per_kernel(write_csv, "WRITE_SIZE", with_count=True, tail=tail)
+    f_scale = COPY_BYTES / (fetch["k_copy"][0] * 1024.0)
+    w_scale = COPY_BYTES / (write["k_copy"][0] * 1024.0)
+    kernels, per_kernel, step_bytes = {}, {}, 0.0
+    for k, (fv, n) in fetch.items():
+        wv = write.get(k, (0.0, n))[0]
+        b = fv * 1024.0 * f_scale + wv * 1024.0 * w_scale
+        per_kernel[k] = {"fetch_kib": fv, "write_kib": wv, "bytes_per_dispatch": b, "dispatches": n}
+        if in_step(k):
+            step_bytes += b * n / steps
         fam = family(k)
         if fam is None or fam == "copy":
             continue
-        b = fetch[k] * 1024.0 * f_scale + write.get(k, 0.0) * 1024.0 * w_scale
-        kernels[fam] = {"kernel": k, "fetch_kib": fetch[k], "write_kib": write.get(k, 0.0),
-                        "bytes_per_launch": b}
+        kernels[fam] = {"kernel": k, "fetch_kib": fv, "write_kib": wv, "bytes_per_launch": b}
     d = {"source_hash": source_hash(), "copy_fetch_scale": f_scale, "copy_write_scale": w_scale,
-         "kernels": kernels}
+         "steps": steps, "tail_steps": tail_steps, "bytes_per_step": step_bytes, "kernels": kernels,
+         "per_kernel": per_kernel}
     json.dump(d, open(out_json, "w"), indent=1)
     return d
 
@@ -107,20 +138,28 @@ FP64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VAL
                  "SQ_INSTS_VALU_TRANS_F64")
 
 
-def fp64(csv_path, out_json):
+def fp64(csv_path, out_json, steps, tail_steps):
     """FP64 lane operations per launch of every stage kernel family from one
     pass of the four FP64 VALU instruction counters (wave instructions x 64
-    lanes; an FMA counts two operations, a transcendental one)"""
-    per = {c: counter_per_kernel(csv_path, c) for c in FP64_COUNTERS}
-    kernels = {}
-    for k in per["SQ_INSTS_VALU_FMA_F64"]:
+    lanes; an FMA counts two operations, a transcendental one), and their sum
+    over the kernels of the RK step per step (the profiled run executed
+    `steps` steps; per-dispatch means over the last `tail_steps` of them)"""
+    tail = tail_steps / steps
+    per = {c: counter_per_kernel(csv_path, c, with_count=True, tail=tail) for c in FP64_COUNTERS}
+    kernels, per_kernel, step_flops = {}, {}, 0.0
+    for k, (_, n) in per["SQ_INSTS_VALU_FMA_F64"].items():
+        add, mul, fma, trans = (per[c].get(k, (0.0, n))[0] for c in FP64_COUNTERS)
+        fl = 64.0 * (add + mul + 2.0 * fma + trans)
+        per_kernel[k] = {"flops_per_dispatch": fl, "dispatches": n}
+        if in_step(k):
+            step_flops += fl * n / steps
         fam = family(k)
         if fam is None or fam == "copy":
             continue
-        add, mul, fma, trans = (per[c].get(k, 0.0) for c in FP64_COUNTERS)
         kernels[fam] = {"kernel": k, "add": add, "mul": mul, "fma": fma, "trans": trans,
-                        "flops_per_launch": 64.0 * (add + mul + 2.0 * fma + trans)}
-    d = {"source_hash": source_hash(), "kernels": kernels}
+                        "flops_per_launch": fl}
+    d = {"source_hash": source_hash(), "steps": steps, "tail_steps": tail_steps,
+         "flops_per_step": step_flops, "kernels": kernels, "per_kernel": per_kernel}
     json.dump(d, open(out_json, "w"), indent=1)
     return d
 
@@ -129,6 +168,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]),
+                                 int(sys.argv[6])), indent=1))
     elif sys.argv[1] == "fp64":
-        print(json.dumps(fp64(sys.argv[2], sys.argv[3]), indent=1))
+        print(json.dumps(fp64(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])), indent=1))
