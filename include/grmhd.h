@@ -44,6 +44,7 @@ extern "C" {
 #define GRMHD_EINVAL (-1)       /* bad argument (size, pointer, option) */
 #define GRMHD_EHIP (-2)         /* a HIP launch or runtime call failed */
 #define GRMHD_EUNSUPPORTED (-3) /* option not implemented */
+#define GRMHD_ETOOBIG (-4)      /* input larger than a fixed-size library workspace */
 
 /* per-cell flag bits (uint16) */
 #define GRMHD_F_C2P_FAIL        (1u << 0)  /* inversion failed -> atmosphere */
@@ -201,6 +202,19 @@ int grmhd_dt(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
    us[0]. */
 int grmhd_mass(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
                double *partial, double *out, void *stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): grmhd_mass without the
+   partial workspace.  The nblk per-block partial sums live in a fixed device
+   array of the library (grmhd_mass_noalloc_max_blocks() = 65536 doubles,
+   512 KiB per GPU, held until the process ends); the call allocates nothing.
+   Same result as grmhd_mass, bit for bit.  Call with the device of `stream`
+   current.  All calls on one GPU share that array: calls that overlap in time
+   on one GPU (different streams, no ordering) race.  GRMHD_ETOOBIG for
+   nblk > grmhd_mass_noalloc_max_blocks(); GRMHD_EINVAL as for grmhd_mass. */
+int grmhd_mass_noalloc(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                       double *out, void *stream);
+int32_t grmhd_mass_noalloc_max_blocks(void);
 
 /* Eq. 7 over every padded cell of each block: us <- prim2con(w, B~_cc(bs)),
    B~_cc the face average of the bs slot.  Initialises the conserved state. */

@@ -9,6 +9,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 
 #include "grmhd.h"
 #include "physics.hpp"
@@ -1445,6 +1446,38 @@ __global__ __launch_bounds__(kThreads) void k_copy(const double* __restrict__ a,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free baryon-mass sum (grmhd_mass_noalloc): the per-block partial
+// sums live in this file-scope device array instead of a caller workspace.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not the device array:
+// its device address is taken once per device with hipGetSymbolAddress and
+// only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+constexpr int kMassNoAllocBlocks = 65536;   // 512 KiB of partial sums
+static __device__ __align__(256) double scratch[kMassNoAllocBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current)
+int scratch_address(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GRMHD_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GRMHD_EHIP;
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return GRMHD_OK;
+}
+}  // namespace
+
 namespace gk {
 Timing g_tm;
 // plain or bracketed inversion of n states (pointer arrays already checked)
@@ -1695,6 +1728,24 @@ int grmhd_mass(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
   k_mass_final<<<1, 64, 0, s>>>(partial, nblk, out);
   return last_err();
 }
+
+int grmhd_mass_noalloc(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                       double* out, void* stream) {
+  if (!out) return GRMHD_EINVAL;
+  if (nblk > kMassNoAllocBlocks) return GRMHD_ETOOBIG;
+  int r = check_reads(blk_h, blk_d, nblk, NEED_D);
+  if (r) return r;
+  double* part = nullptr;
+  if ((r = scratch_address(&part))) return r;
+  hipStream_t s = (hipStream_t)stream;
+  // every partial[0..nblk) is written by k_mass_block before k_mass_final
+  // reads it (stream order): nothing to clear
+  k_mass_block<<<nblk, kThreads, 0, s>>>(blk_d, part);
+  k_mass_final<<<1, 64, 0, s>>>(part, nblk, out);
+  return last_err();
+}
+
+int32_t grmhd_mass_noalloc_max_blocks(void) { return kMassNoAllocBlocks; }
 
 int prim2con(int64_t n, double* const w[5], double* const bt[3], double* const gam[6], double* u[5],
              const grmhd_params* p, void* stream) {

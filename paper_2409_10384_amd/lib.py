@@ -91,6 +91,8 @@ def load():
     L.grmhd_ghost_fill.argtypes = blk + [C.c_int32, C.c_void_p]
     L.grmhd_dt.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     L.grmhd_mass.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.grmhd_mass_noalloc.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_mass_noalloc_max_blocks.restype = C.c_int32
     L.prim2con.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_void_p]
     L.c2p_batch.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -554,6 +556,13 @@ class DeviceMesh:
         check(load().grmhd_mass(*self._args((0, 0)), C.c_void_p(self.mass_part.data_ptr()),
                                 C.c_void_p(self.mass_out.data_ptr()), self.sp()), "grmhd_mass")
         return self.mass_out
+
+    def mass_noalloc(self, out):
+        """grmhd_mass_noalloc into the device double `out` (the partial sums
+        in the library's fixed device array)"""
+        check(load().grmhd_mass_noalloc(*self._args((0, 0)), C.c_void_p(out.data_ptr()), self.sp()),
+              "grmhd_mass_noalloc")
+        return out
 
     # --- granular steps (for tests) ------------------------------------------
     def run_steps(self, stage, dt, mode):
