@@ -59,6 +59,13 @@ class OrBlock(C.Structure):
     ]
 
 
+class OrAmr(C.Structure):
+    _fields_ = [
+        ("n0", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+        ("level", C.POINTER(C.c_int32)), ("org", C.POINTER(C.c_int32)),
+    ]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -409,12 +416,15 @@ class Mesh:
             lib().or_set_term_scales(pu, pb)
             out = (tu, tb)
         try:
-            lib().or_stage(arr, nb, C.byref(self.params.c()), C.c_double(dt), C.c_double(a0),
-                           C.c_double(a1), C.c_double(b))
+            self._run_stage(arr, nb, dt, a0, a1, b)
         finally:
             if term_scales:
                 lib().or_set_term_scales(None, None)
         return out
+
+    def _run_stage(self, arr, nb, dt, a0, a1, b):
+        lib().or_stage(arr, nb, C.byref(self.params.c()), C.c_double(dt), C.c_double(a0),
+                       C.c_double(a1), C.c_double(b))
 
     def stage(self, stage, dt):
         src, dst, (a0, a1, b) = self.RK2[stage - 1]
@@ -463,6 +473,56 @@ class Mesh:
         b = self.blocks[ib]
         g = b.ng
         return a[..., g:g + b.nz, g:g + b.ny, g:g + b.nx]
+
+
+class RefinedMesh(Mesh):
+    """A Mesh whose blocks are the leaves of a refined mesh (LeafMesh from
+    paper_2409_10384_amd.inputs, blocks in its leaf order): ghost fills across
+    levels (or_ghost_fill_amr) and stages with the flux and EMF corrections
+    at level boundaries (or_stage_amr)."""
+
+    def __init__(self, blocks, params: Params, leafmesh):
+        super().__init__(blocks, params)
+        nb = len(blocks)
+        self.leafmesh = leafmesh
+        self._level = (C.c_int32 * nb)(*leafmesh.levels)
+        self._org = (C.c_int32 * (3 * nb))(*[o for i in range(nb) for o in leafmesh.org(i)])
+        self.amr = OrAmr()
+        self.amr.n0 = (C.c_int32 * 3)(*leafmesh.n0)
+        self.amr.periodic = (C.c_int32 * 3)(*leafmesh.periodic)
+        self.amr.level = C.cast(self._level, C.POINTER(C.c_int32))
+        self.amr.org = C.cast(self._org, C.POINTER(C.c_int32))
+
+    def ghost_fill_state(self, which):
+        U, W, Bf = self._set(which)
+        arr = (OrBlock * len(self.blocks))()
+        for ib in range(len(self.blocks)):
+            arr[ib] = self._desc(ib, W[ib], U[ib], U[ib], Bf[ib], Bf[ib], U[ib], Bf[ib], W[ib])
+        lib().or_ghost_fill_amr(arr, len(self.blocks), GF_W | GF_US | GF_BS, C.byref(self.amr))
+
+    def ghost_fill_mask(self, which, mask):
+        """ghost fill of the selected fields (GF_* bits) of state set `which`"""
+        U, W, Bf = self._set(which)
+        arr = (OrBlock * len(self.blocks))()
+        for ib in range(len(self.blocks)):
+            arr[ib] = self._desc(ib, W[ib], U[ib], U[ib], Bf[ib], Bf[ib], U[ib], Bf[ib], W[ib])
+        lib().or_ghost_fill_amr(arr, len(self.blocks), mask, C.byref(self.amr))
+
+    def _run_stage(self, arr, nb, dt, a0, a1, b):
+        lib().or_stage_amr(arr, nb, C.byref(self.params.c()), C.c_double(dt), C.c_double(a0),
+                           C.c_double(a1), C.c_double(b), C.byref(self.amr))
+
+    def mass_total(self, which=0):
+        """sum of D~ dV over every leaf's interior (each leaf with its own dV)"""
+        U = self._set(which)[0]
+        return sum(float(np.sum(self.interior(U[ib][0], ib))) * np.prod(b.dx)
+                   for ib, b in enumerate(self.blocks))
+
+    def totals(self, which=0):
+        """sums of the five conserved fields over every leaf's interior (x dV)"""
+        U = self._set(which)[0]
+        return np.array([sum(float(np.sum(self.interior(U[ib][v], ib))) * np.prod(b.dx)
+                             for ib, b in enumerate(self.blocks)) for v in range(5)])
 
 
 def stage_steps(mesh: Mesh, stage, dt, fluxes, mode, flux_scales=None):

@@ -1155,6 +1155,373 @@ int or_ghost_fill(or_block *blks, int nblk, int mask) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Inter-level transfer on a refined mesh (the block-based mesh refinement   */
+/* of Sec. I; the prolongation and restriction that Sec. V-A counts among    */
+/* the costs).  Refinement by a factor 2; every block is a leaf; leaves that */
+/* touch (across a face, an edge or a corner) differ by at most one level.   */
+/* A ghost cell or face takes its value from the leaf covering its position: */
+/*  - a leaf of the same level: a copy;                                       */
+/*  - a finer leaf: restriction -- the mean of the 8 child cells (flags: OR), */
+/*    of the 4 child faces in the face's plane;                               */
+/*  - a coarser leaf: prolongation -- a cell: the parent's value plus, per    */
+/*    axis, a quarter of the parent's minmod-limited slope, signed towards   */
+/*    the child (the 8 children average to the parent); flags: the parent's; */
+/*    a face on a parent face: that face's value; a face inside a parent     */
+/*    cell: the mean of the parent's two faces along its normal (each child  */
+/*    cell then has its parent's divergence).                                 */
+/* Copies and restrictions read interiors only and go first; prolongations   */
+/* go level by level upwards, since the parent's slope may read the parent   */
+/* leaf's ghosts.  In a stage, every face flux a block holds on its boundary */
+/* next to a finer leaf becomes the mean of the 4 fine fluxes there          */
+/* (conservation across the level boundary), and every boundary edge EMF     */
+/* next to a finer leaf the mean of the 2 fine EMFs along it (the coarse     */
+/* face then changes by the mean of the fine faces' changes: div B~ stays at */
+/* round-off).  One dt for every level.  Outflow boundaries take the         */
+/* nearest cell of the domain, periodic ones wrap.                           */
+/* ------------------------------------------------------------------------- */
+/* test instrument: switch the flux / EMF correction off (1, 1 = the method) */
+static int g_amr_flux_fix = 1, g_amr_emf_fix = 1;
+void or_set_amr_corrections(int flux, int emf) {
+  g_amr_flux_fix = flux;
+  g_amr_emf_fix = emf;
+}
+
+typedef struct {
+  int32_t n0[3];        /* the domain in level-0 cells                          */
+  int32_t periodic[3];  /* per axis: 1 periodic, 0 outflow                      */
+  const int32_t *level; /* per block: its refinement level (dx = dx0 / 2^level) */
+  const int32_t *org;   /* per block, 3 each: global index at its level of its first interior cell */
+} or_amr;
+
+static int amr_cell_axis(const or_amr *amr, int lvl, int a, int I) {
+  const int N = amr->n0[a] << lvl;
+  if (I >= 0 && I < N) return I;
+  if (amr->periodic[a]) return ((I % N) + N) % N;
+  return I < 0 ? 0 : N - 1;
+}
+
+/* the leaf that covers global cell I (inside the domain) of level lvl */
+static int find_leaf(const or_block *blks, int nblk, const or_amr *amr, int lvl, const int I[3]) {
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int L = amr->level[ib];
+    const int n[3] = {blks[ib].nx, blks[ib].ny, blks[ib].nz};
+    int in = 1;
+    for (int a = 0; a < 3 && in; ++a) {
+      const int64_t lo = (int64_t)amr->org[3 * ib + a], hi = lo + n[a];
+      /* the cell's extent in leaf-level indices: [c0, c1) */
+      int64_t c0, c1;
+      if (L >= lvl) {
+        c0 = (int64_t)I[a] << (L - lvl);
+        c1 = c0 + ((int64_t)1 << (L - lvl));
+      } else {
+        c0 = (int64_t)I[a] >> (lvl - L);
+        c1 = c0 + 1;
+      }
+      in = c0 >= lo && c1 <= hi;
+    }
+    if (in) return ib;
+  }
+  return -1;
+}
+
+static double minmod2(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+/* padded index in leaf L (at level lvl(L)) of global cell J of that level */
+static int64_t leaf_cell(const or_block *L, const int32_t *org, const int J[3]) {
+  return cidx(L, J[0] - org[0] + L->ng, J[1] - org[1] + L->ng, J[2] - org[2] + L->ng);
+}
+
+/* prolongation of padded cell array f of leaf L to the child Ic (a global
+   index one level finer than L) */
+static double prolong_cell(const or_block *L, const int32_t *org, const double *f, const int Ic[3]) {
+  const int P[3] = {Ic[0] >> 1, Ic[1] >> 1, Ic[2] >> 1};
+  const int64_t c = leaf_cell(L, org, P);
+  const double v = f[c];
+  double out = v;
+  for (int a = 0; a < 3; ++a) {
+    int lo[3] = {P[0], P[1], P[2]}, hi[3] = {P[0], P[1], P[2]};
+    lo[a] -= 1;
+    hi[a] += 1;
+    const double s = minmod2(f[leaf_cell(L, org, hi)] - v, v - f[leaf_cell(L, org, lo)]);
+    out += (Ic[a] & 1) ? 0.25 * s : -0.25 * s;
+  }
+  return out;
+}
+
+/* ghost cells of block ib: pass 0 copies and restrictions, pass > 0 the
+   prolongations of a block at level == pass */
+static void amr_fill_cells(or_block *blks, int nblk, const or_amr *amr, int ib, int mask, int pass) {
+  or_block *b = &blks[ib];
+  const int lv = amr->level[ib], g = b->ng;
+  const int n[3] = {b->nx, b->ny, b->nz};
+  const int s[3] = {n[0] + 2 * g, n[1] + 2 * g, n[2] + 2 * g};
+  for (int k = 0; k < s[2]; ++k)
+    for (int j = 0; j < s[1]; ++j)
+      for (int i = 0; i < s[0]; ++i) {
+        const int x[3] = {i, j, k};
+        int inner = 1;
+        for (int a = 0; a < 3; ++a) inner = inner && x[a] >= g && x[a] < g + n[a];
+        if (inner) continue;
+        int I[3];
+        for (int a = 0; a < 3; ++a) I[a] = amr_cell_axis(amr, lv, a, amr->org[3 * ib + a] + x[a] - g);
+        const int il = find_leaf(blks, nblk, amr, lv, I);
+        if (il < 0) continue;
+        const or_block *L = &blks[il];
+        const int32_t *lorg = amr->org + 3 * il;
+        const int ll = amr->level[il];
+        const int64_t dst = cidx(b, i, j, k);
+        if (pass == 0 && ll == lv) {
+          const int64_t src = leaf_cell(L, lorg, I);
+          if (mask & GF_W)
+            for (int v = 0; v < 5; ++v) b->w[v][dst] = L->w[v][src];
+          if (mask & GF_US)
+            for (int v = 0; v < 5; ++v) b->us[v][dst] = L->us[v][src];
+          if (mask & GF_FLAGS) b->flags[dst] = L->flags[src];
+        } else if (pass == 0 && ll == lv + 1) {
+          double sw[5] = {0, 0, 0, 0, 0}, su[5] = {0, 0, 0, 0, 0};
+          uint16_t fl = 0;
+          for (int c = 0; c < 8; ++c) {
+            const int C[3] = {2 * I[0] + (c & 1), 2 * I[1] + ((c >> 1) & 1), 2 * I[2] + (c >> 2)};
+            const int64_t src = leaf_cell(L, lorg, C);
+            for (int v = 0; v < 5; ++v) {
+              if (mask & GF_W) sw[v] += L->w[v][src];
+              if (mask & GF_US) su[v] += L->us[v][src];
+            }
+            fl |= L->flags[src];
+          }
+          if (mask & GF_W)
+            for (int v = 0; v < 5; ++v) b->w[v][dst] = 0.125 * sw[v];
+          if (mask & GF_US)
+            for (int v = 0; v < 5; ++v) b->us[v][dst] = 0.125 * su[v];
+          if (mask & GF_FLAGS) b->flags[dst] = fl;
+        } else if (pass == lv && ll == lv - 1) {
+          if (mask & GF_W)
+            for (int v = 0; v < 5; ++v) b->w[v][dst] = prolong_cell(L, lorg, L->w[v], I);
+          if (mask & GF_US)
+            for (int v = 0; v < 5; ++v) b->us[v][dst] = prolong_cell(L, lorg, L->us[v], I);
+          if (mask & GF_FLAGS) {
+            const int P[3] = {I[0] >> 1, I[1] >> 1, I[2] >> 1};
+            b->flags[dst] = L->flags[leaf_cell(L, lorg, P)];
+          }
+        }
+      }
+}
+
+/* value of the face of direction d whose lower corner, in global indices of
+   leaf L's level, is J (J[d] the face index), read from L's face array */
+static double leaf_face(const or_block *L, const int32_t *org, int d, const int J[3]) {
+  return L->bs[d][fidx(L, d, J[0] - org[0] + L->ng, J[1] - org[1] + L->ng, J[2] - org[2] + L->ng)];
+}
+
+/* ghost faces of direction d of block ib (passes as for the cells) */
+static void amr_fill_faces(or_block *blks, int nblk, const or_amr *amr, int ib, int d, int pass) {
+  or_block *b = &blks[ib];
+  const int lv = amr->level[ib], g = b->ng;
+  const int n[3] = {b->nx, b->ny, b->nz};
+  const int e[3] = {n[0] + 2 * g + (d == 0), n[1] + 2 * g + (d == 1), n[2] + 2 * g + (d == 2)};
+  const int N = amr->n0[d] << lv;
+  for (int k = 0; k < e[2]; ++k)
+    for (int j = 0; j < e[1]; ++j)
+      for (int i = 0; i < e[0]; ++i) {
+        const int x[3] = {i, j, k};
+        int inner = 1;
+        for (int a = 0; a < 3; ++a) inner = inner && x[a] >= g && x[a] <= g + n[a] - (a != d);
+        if (inner) continue;
+        /* the face in global indices of level lv: along d a face index
+           (periodic: mod N; outflow: clamped to the boundary faces 0 and N),
+           across d the cell indices */
+        int F[3];
+        for (int a = 0; a < 3; ++a) {
+          const int G = amr->org[3 * ib + a] + x[a] - g;
+          if (a != d) {
+            F[a] = amr_cell_axis(amr, lv, a, G);
+          } else if (amr->periodic[a]) {
+            F[a] = ((G % N) + N) % N;
+          } else {
+            F[a] = G < 0 ? 0 : (G > N ? N : G);
+          }
+        }
+        /* the cells above (F) and below (F - e_d) the face, where inside the domain */
+        int Ip[3] = {F[0], F[1], F[2]}, Im[3] = {F[0], F[1], F[2]};
+        Im[d] = F[d] - 1;
+        if (amr->periodic[d] && Im[d] < 0) Im[d] += N;
+        const int lp = Ip[d] < N ? find_leaf(blks, nblk, amr, lv, Ip) : -1;
+        const int lm = Im[d] >= 0 ? find_leaf(blks, nblk, amr, lv, Im) : -1;
+        /* the two sides: leaf, its level, and the face's index along d in that
+           side's numbering (the upper face of M's cell is Im + 1, N across a
+           periodic boundary); the side within the block's own range along d
+           first (the upper side except on the block's upper boundary plane) */
+        const int first_m = x[d] == g + n[d];
+        const int sl[2] = {first_m ? lm : lp, first_m ? lp : lm};
+        const int sf[2] = {first_m ? Im[d] + 1 : F[d], first_m ? F[d] : Im[d] + 1};
+        int sv[2];
+        for (int q = 0; q < 2; ++q) sv[q] = sl[q] >= 0 ? amr->level[sl[q]] : -100;
+        int pick = -1, kind = -1;   /* kind 0 copy, 1 restriction, 2 prolongation */
+        for (int want = 0; want < 3 && pick < 0; ++want) {
+          const int lw = want == 0 ? lv : want == 1 ? lv + 1 : lv - 1;
+          for (int q = 0; q < 2 && pick < 0; ++q)
+            if (sv[q] == lw) {
+              pick = q;
+              kind = want;
+            }
+        }
+        if (pick < 0) continue;
+        if ((kind < 2 && pass != 0) || (kind == 2 && pass != lv)) continue;
+        const int il = sl[pick];
+        const int32_t *lorg = amr->org + 3 * il;
+        const int Fd = sf[pick];
+        const int64_t dst = fidx(b, d, i, j, k);
+        if (kind == 0) {
+          int J[3] = {F[0], F[1], F[2]};
+          J[d] = Fd;
+          b->bs[d][dst] = leaf_face(&blks[il], lorg, d, J);
+        } else if (kind == 1) {
+          double sum = 0.0;
+          for (int c = 0; c < 4; ++c) {
+            int J[3];
+            int t = 0;
+            for (int a = 0; a < 3; ++a) {
+              if (a == d) {
+                J[a] = 2 * Fd;
+              } else {
+                J[a] = 2 * F[a] + ((c >> t) & 1);
+                ++t;
+              }
+            }
+            sum += leaf_face(&blks[il], lorg, d, J);
+          }
+          b->bs[d][dst] = 0.25 * sum;
+        } else {
+          /* on a parent face (even index) its value; inside a parent cell
+             (odd index) the mean of that cell's two faces along d */
+          int J[3] = {F[0] >> 1, F[1] >> 1, F[2] >> 1};
+          J[d] = Fd >> 1;
+          if ((Fd & 1) == 0) {
+            b->bs[d][dst] = leaf_face(&blks[il], lorg, d, J);
+          } else {
+            int J1[3] = {J[0], J[1], J[2]};
+            J1[d] += 1;
+            b->bs[d][dst] = 0.5 * (leaf_face(&blks[il], lorg, d, J) + leaf_face(&blks[il], lorg, d, J1));
+          }
+        }
+      }
+}
+
+int or_ghost_fill_amr(or_block *blks, int nblk, int mask, const or_amr *amr) {
+  int maxlvl = 0;
+  for (int ib = 0; ib < nblk; ++ib)
+    if (amr->level[ib] > maxlvl) maxlvl = amr->level[ib];
+  for (int pass = 0; pass <= maxlvl; ++pass)
+    for (int ib = 0; ib < nblk; ++ib) {
+      if (blks[ib].bc == 0) continue;
+      if (pass > 0 && amr->level[ib] != pass) continue;
+      if (mask & (GF_W | GF_US | GF_FLAGS)) amr_fill_cells(blks, nblk, amr, ib, mask, pass);
+      if (mask & GF_BS)
+        for (int d = 0; d < 3; ++d) amr_fill_faces(blks, nblk, amr, ib, d, pass);
+    }
+  return 0;
+}
+
+/* flux correction: each boundary face of a block next to a finer leaf takes
+   the mean of that leaf's 4 fluxes there (all 7 components) */
+static void amr_flux_correct(or_block *blks, int nblk, const or_amr *amr, double **Fall) {
+  for (int ib = 0; ib < nblk; ++ib) {
+    or_block *b = &blks[ib];
+    const int lv = amr->level[ib], g = b->ng;
+    const int n[3] = {b->nx, b->ny, b->nz};
+    double **Fb = Fall + (int64_t)ib * 21;
+    for (int d = 0; d < 3; ++d)
+      for (int side = 0; side < 2; ++side) {
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        const int N = amr->n0[d] << lv;
+        /* the cell across the face, at level lv */
+        const int Gd = amr->org[3 * ib + d] + (side ? n[d] : -1);
+        if (!amr->periodic[d] && (Gd < 0 || Gd >= N)) continue;   /* domain boundary */
+        for (int q2 = 0; q2 < n[t2]; ++q2)
+          for (int q1 = 0; q1 < n[t1]; ++q1) {
+            int I[3];
+            I[d] = ((Gd % N) + N) % N;
+            I[t1] = amr->org[3 * ib + t1] + q1;
+            I[t2] = amr->org[3 * ib + t2] + q2;
+            const int il = find_leaf(blks, nblk, amr, lv, I);
+            if (il < 0 || amr->level[il] != lv + 1) continue;
+            const or_block *L = &blks[il];
+            double **FL = Fall + (int64_t)il * 21;
+            double sum[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (int c = 0; c < 4; ++c) {
+              int J[3];
+              /* across the lower face: the upper faces of children 2I+1; across
+                 the upper face: the lower faces of children 2I */
+              J[d] = side ? 2 * I[d] : 2 * I[d] + 2;
+              J[t1] = 2 * I[t1] + (c & 1);
+              J[t2] = 2 * I[t2] + (c >> 1);
+              const int64_t f = fidx(L, d, J[0] - amr->org[3 * il] + L->ng, J[1] - amr->org[3 * il + 1] + L->ng,
+                                     J[2] - amr->org[3 * il + 2] + L->ng);
+              for (int v = 0; v < 7; ++v) sum[v] += FL[d * 7 + v][f];
+            }
+            int x[3];
+            x[d] = side ? g + n[d] : g;
+            x[t1] = g + q1;
+            x[t2] = g + q2;
+            const int64_t f0 = fidx(b, d, x[0], x[1], x[2]);
+            for (int v = 0; v < 7; ++v) Fb[d * 7 + v][f0] = 0.25 * sum[v];
+          }
+      }
+  }
+}
+
+/* EMF correction: each boundary edge EMF of a block where one of the 4 cells
+   around the edge lies in a finer leaf takes the mean of that leaf's 2 EMFs
+   along the edge.  Eall[3 * ib + c]: block ib's edge array of component c. */
+static void amr_emf_correct(or_block *blks, int nblk, const or_amr *amr, double **Eall) {
+  for (int ib = 0; ib < nblk; ++ib) {
+    or_block *b = &blks[ib];
+    const int lv = amr->level[ib], g = b->ng;
+    const int n[3] = {b->nx, b->ny, b->nz};
+    for (int comp = 0; comp < 3; ++comp) {
+      const int A = (comp + 1) % 3, Bx = (comp + 2) % 3;
+      for (int k = g; k <= g + n[2] - (comp == 2); ++k)
+        for (int j = g; j <= g + n[1] - (comp == 1); ++j)
+          for (int i = g; i <= g + n[0] - (comp == 0); ++i) {
+            const int x[3] = {i, j, k};
+            if (x[A] != g && x[A] != g + n[A] && x[Bx] != g && x[Bx] != g + n[Bx]) continue;
+            for (int cell = 0; cell < 4; ++cell) {
+              const int oa = cell & 1, ob = cell >> 1;   /* the cell (a - oa, b - ob) */
+              int I[3], outside = 0;
+              for (int a = 0; a < 3; ++a) {
+                int G = amr->org[3 * ib + a] + x[a] - g;
+                if (a == A) G -= oa;
+                if (a == Bx) G -= ob;
+                const int N = amr->n0[a] << lv;
+                if (!amr->periodic[a] && (G < 0 || G >= N)) outside = 1;
+                I[a] = ((G % N) + N) % N;
+              }
+              if (outside) continue;
+              const int il = find_leaf(blks, nblk, amr, lv, I);
+              if (il < 0 || amr->level[il] != lv + 1) continue;
+              const or_block *L = &blks[il];
+              const double *EL = Eall[3 * il + comp];
+              double sum = 0.0;
+              for (int h = 0; h < 2; ++h) {
+                int J[3];
+                J[comp] = 2 * I[comp] + h;
+                J[A] = 2 * (I[A] + oa);
+                J[Bx] = 2 * (I[Bx] + ob);
+                sum += EL[eidx(L, J[0] - amr->org[3 * il] + L->ng, J[1] - amr->org[3 * il + 1] + L->ng,
+                               J[2] - amr->org[3 * il + 2] + L->ng)];
+              }
+              Eall[3 * ib + comp][eidx(b, i, j, k)] = 0.5 * sum;
+              break;
+            }
+          }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
 /* a4: FOFC (+DMP).  Trial state without sources or CT, trial C2P with the   */
 /* stage-input cell-centred field; flag cells whose trial needs a floor or    */
 /* fails, or (DMP) whose D~ or tau~ leaves [lo(min), hi(max)] of Eq. 12 over   */
@@ -1312,136 +1679,160 @@ static double corner_emf_scale(double EA_b, double EA_bm, double EB_a, double EB
          0.25 * (db_lo + db_hi + da_lo + da_hi);
 }
 
-int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1, double bb,
-          double **Fall) {
-  eos_t e;
-  eos_setup(p, &e);
-  (void)e;
-  for (int ib = 0; ib < nblk; ++ib) {
-    or_block *b = &blks[ib];
-    double **Fb = Fall + (int64_t)ib * 21;
-    int g = b->ng;
-    int n[3] = {b->nx, b->ny, b->nz};
-    int64_t nc = ncell(b), ne = nedge(b);
-    double *Ecc[3], *Ec[3], *Eccs[3] = {NULL, NULL, NULL}, *Ecs[3] = {NULL, NULL, NULL};
-    for (int a = 0; a < 3; ++a) {
-      Ecc[a] = (double *)calloc((size_t)nc, sizeof(double));
-      Ec[a] = (double *)calloc((size_t)ne, sizeof(double));
-      if (g_tscale_b) {
-        Eccs[a] = (double *)calloc((size_t)nc, sizeof(double));
-        Ecs[a] = (double *)calloc((size_t)ne, sizeof(double));
+/* corner EMFs of block ib into Ec[3] (edge arrays; with the term-scale
+   instrument also their term magnitudes into Ecs[3]) */
+static void ct_emfs(or_block *blks, int ib, double **Fall, double *Ec[3], double *Ecs[3]) {
+  or_block *b = &blks[ib];
+  double **Fb = Fall + (int64_t)ib * 21;
+  int g = b->ng;
+  int n[3] = {b->nx, b->ny, b->nz};
+  int64_t nc = ncell(b);
+  double *Ecc[3], *Eccs[3] = {NULL, NULL, NULL};
+  for (int a = 0; a < 3; ++a) {
+    Ecc[a] = (double *)calloc((size_t)nc, sizeof(double));
+    if (g_tscale_b) Eccs[a] = (double *)calloc((size_t)nc, sizeof(double));
+  }
+  /* cell-centre EMF on cells [g-1, g+n] */
+  for (int k = g - 1; k <= g + n[2]; ++k)
+    for (int j = g - 1; j <= g + n[1]; ++j)
+      for (int i = g - 1; i <= g + n[0]; ++i) {
+        int64_t c = cidx(b, i, j, k);
+        met3 m;
+        cell_metric(b, c, &m);
+        double al = b->adm[0][c];
+        double u[3] = {b->w[1][c], b->w[2][c], b->w[3][c]};
+        double ul[3];
+        lower3(&m, u, ul);
+        double W = sqrt(1.0 + dot3(u, ul));
+        double vh[3];
+        for (int a = 0; a < 3; ++a) vh[a] = u[a] / W - b->adm[1 + a][c] / al;
+        double Bt[3];
+        cell_bt(b, b->bs, i, j, k, Bt);
+        Ecc[0][c] = -al * (vh[1] * Bt[2] - vh[2] * Bt[1]);
+        Ecc[1][c] = -al * (vh[2] * Bt[0] - vh[0] * Bt[2]);
+        Ecc[2][c] = -al * (vh[0] * Bt[1] - vh[1] * Bt[0]);
+        if (g_tscale_b) {
+          Eccs[0][c] = fabs(al) * (fabs(vh[1] * Bt[2]) + fabs(vh[2] * Bt[1]));
+          Eccs[1][c] = fabs(al) * (fabs(vh[2] * Bt[0]) + fabs(vh[0] * Bt[2]));
+          Eccs[2][c] = fabs(al) * (fabs(vh[0] * Bt[1]) + fabs(vh[1] * Bt[0]));
+        }
       }
+  /* corner EMFs.  For component c with plane axes (a, bx) cyclic, the edge
+     (ia-1/2, ib-1/2) is stored at edge index with face indices on a and bx */
+  for (int comp = 0; comp < 3; ++comp) {
+    int A = (comp + 1) % 3, Bx = (comp + 2) % 3;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a == comp) { lo[a] = g; hi[a] = g + n[a] - 1; }
+      else { lo[a] = g; hi[a] = g + n[a]; }
     }
-    /* cell-centre EMF on cells [g-1, g+n] */
-    for (int k = g - 1; k <= g + n[2]; ++k)
-      for (int j = g - 1; j <= g + n[1]; ++j)
-        for (int i = g - 1; i <= g + n[0]; ++i) {
-          int64_t c = cidx(b, i, j, k);
-          met3 m;
-          cell_metric(b, c, &m);
-          double al = b->adm[0][c];
-          double u[3] = {b->w[1][c], b->w[2][c], b->w[3][c]};
-          double ul[3];
-          lower3(&m, u, ul);
-          double W = sqrt(1.0 + dot3(u, ul));
-          double vh[3];
-          for (int a = 0; a < 3; ++a) vh[a] = u[a] / W - b->adm[1 + a][c] / al;
-          double Bt[3];
-          cell_bt(b, b->bs, i, j, k, Bt);
-          Ecc[0][c] = -al * (vh[1] * Bt[2] - vh[2] * Bt[1]);
-          Ecc[1][c] = -al * (vh[2] * Bt[0] - vh[0] * Bt[2]);
-          Ecc[2][c] = -al * (vh[0] * Bt[1] - vh[1] * Bt[0]);
-          if (g_tscale_b) {
-            Eccs[0][c] = fabs(al) * (fabs(vh[1] * Bt[2]) + fabs(vh[2] * Bt[1]));
-            Eccs[1][c] = fabs(al) * (fabs(vh[2] * Bt[0]) + fabs(vh[0] * Bt[2]));
-            Eccs[2][c] = fabs(al) * (fabs(vh[0] * Bt[1]) + fabs(vh[1] * Bt[0]));
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          int x[3] = {i, j, k};
+          /* helpers: position shifted by -1 along A and/or Bx */
+#define AT(da, db, out) do { int y_[3] = {x[0], x[1], x[2]}; y_[A] += (da); y_[Bx] += (db); \
+                           out[0] = y_[0]; out[1] = y_[1]; out[2] = y_[2]; } while (0)
+          int p00[3], p10[3], p01[3], p11[3];
+          AT(0, 0, p00);    /* cell (a, b)       */
+          AT(-1, 0, p10);   /* cell (a-1, b)     */
+          AT(0, -1, p01);   /* cell (a, b-1)     */
+          AT(-1, -1, p11);  /* cell (a-1, b-1)   */
+#undef AT
+          /* a-faces at (a-1/2, b) and (a-1/2, b-1): face index = p00 / p01 along A */
+          double EA_b = face_emf(b, Fb, A, comp, p00[0], p00[1], p00[2]);
+          double EA_bm = face_emf(b, Fb, A, comp, p01[0], p01[1], p01[2]);
+          /* b-faces at (a, b-1/2) and (a-1, b-1/2): face index = p00 / p10 along Bx */
+          double EB_a = face_emf(b, Fb, Bx, comp, p00[0], p00[1], p00[2]);
+          double EB_am = face_emf(b, Fb, Bx, comp, p10[0], p10[1], p10[2]);
+          double mA_b = Fb[A * 7 + 0][fidx(b, A, p00[0], p00[1], p00[2])];
+          double mA_bm = Fb[A * 7 + 0][fidx(b, A, p01[0], p01[1], p01[2])];
+          double mB_a = Fb[Bx * 7 + 0][fidx(b, Bx, p00[0], p00[1], p00[2])];
+          double mB_am = Fb[Bx * 7 + 0][fidx(b, Bx, p10[0], p10[1], p10[2])];
+          double *E = Ecc[comp];
+          double Ec00 = E[cidx(b, p00[0], p00[1], p00[2])];
+          double Ec10 = E[cidx(b, p10[0], p10[1], p10[2])];
+          double Ec01 = E[cidx(b, p01[0], p01[1], p01[2])];
+          double Ec11 = E[cidx(b, p11[0], p11[1], p11[2])];
+          Ec[comp][eidx(b, i, j, k)] = corner_emf(EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a,
+                                                  mB_am, Ec00, Ec10, Ec01, Ec11);
+          if (g_tscale_b && g_tscale_f) {
+            double *Es = Eccs[comp];
+            double **Sb = g_tscale_f + (int64_t)ib * 21;
+            Ecs[comp][eidx(b, i, j, k)] = corner_emf_scale(
+                face_emf(b, Sb, A, comp, p00[0], p00[1], p00[2]),
+                face_emf(b, Sb, A, comp, p01[0], p01[1], p01[2]),
+                face_emf(b, Sb, Bx, comp, p00[0], p00[1], p00[2]),
+                face_emf(b, Sb, Bx, comp, p10[0], p10[1], p10[2]), mA_b, mA_bm, mB_a, mB_am,
+                Es[cidx(b, p00[0], p00[1], p00[2])], Es[cidx(b, p10[0], p10[1], p10[2])],
+                Es[cidx(b, p01[0], p01[1], p01[2])], Es[cidx(b, p11[0], p11[1], p11[2])]);
           }
         }
-    /* corner EMFs.  For component c with plane axes (a, bx) cyclic, the edge
-       (ia-1/2, ib-1/2) is stored at edge index with face indices on a and bx */
-    for (int comp = 0; comp < 3; ++comp) {
-      int A = (comp + 1) % 3, Bx = (comp + 2) % 3;
-      int lo[3], hi[3];
-      for (int a = 0; a < 3; ++a) {
-        if (a == comp) { lo[a] = g; hi[a] = g + n[a] - 1; }
-        else { lo[a] = g; hi[a] = g + n[a]; }
-      }
-      for (int k = lo[2]; k <= hi[2]; ++k)
-        for (int j = lo[1]; j <= hi[1]; ++j)
-          for (int i = lo[0]; i <= hi[0]; ++i) {
-            int x[3] = {i, j, k};
-            /* helpers: position shifted by -1 along A and/or Bx */
-#define AT(da, db, out) do { int y_[3] = {x[0], x[1], x[2]}; y_[A] += (da); y_[Bx] += (db); \
-                             out[0] = y_[0]; out[1] = y_[1]; out[2] = y_[2]; } while (0)
-            int p00[3], p10[3], p01[3], p11[3];
-            AT(0, 0, p00);    /* cell (a, b)       */
-            AT(-1, 0, p10);   /* cell (a-1, b)     */
-            AT(0, -1, p01);   /* cell (a, b-1)     */
-            AT(-1, -1, p11);  /* cell (a-1, b-1)   */
-#undef AT
-            /* a-faces at (a-1/2, b) and (a-1/2, b-1): face index = p00 / p01 along A */
-            double EA_b = face_emf(b, Fb, A, comp, p00[0], p00[1], p00[2]);
-            double EA_bm = face_emf(b, Fb, A, comp, p01[0], p01[1], p01[2]);
-            /* b-faces at (a, b-1/2) and (a-1, b-1/2): face index = p00 / p10 along Bx */
-            double EB_a = face_emf(b, Fb, Bx, comp, p00[0], p00[1], p00[2]);
-            double EB_am = face_emf(b, Fb, Bx, comp, p10[0], p10[1], p10[2]);
-            double mA_b = Fb[A * 7 + 0][fidx(b, A, p00[0], p00[1], p00[2])];
-            double mA_bm = Fb[A * 7 + 0][fidx(b, A, p01[0], p01[1], p01[2])];
-            double mB_a = Fb[Bx * 7 + 0][fidx(b, Bx, p00[0], p00[1], p00[2])];
-            double mB_am = Fb[Bx * 7 + 0][fidx(b, Bx, p10[0], p10[1], p10[2])];
-            double *E = Ecc[comp];
-            double Ec00 = E[cidx(b, p00[0], p00[1], p00[2])];
-            double Ec10 = E[cidx(b, p10[0], p10[1], p10[2])];
-            double Ec01 = E[cidx(b, p01[0], p01[1], p01[2])];
-            double Ec11 = E[cidx(b, p11[0], p11[1], p11[2])];
-            Ec[comp][eidx(b, i, j, k)] = corner_emf(EA_b, EA_bm, EB_a, EB_am, mA_b, mA_bm, mB_a,
-                                                    mB_am, Ec00, Ec10, Ec01, Ec11);
-            if (g_tscale_b && g_tscale_f) {
-              double *Es = Eccs[comp];
-              double **Sb = g_tscale_f + (int64_t)ib * 21;
-              Ecs[comp][eidx(b, i, j, k)] = corner_emf_scale(
-                  face_emf(b, Sb, A, comp, p00[0], p00[1], p00[2]),
-                  face_emf(b, Sb, A, comp, p01[0], p01[1], p01[2]),
-                  face_emf(b, Sb, Bx, comp, p00[0], p00[1], p00[2]),
-                  face_emf(b, Sb, Bx, comp, p10[0], p10[1], p10[2]), mA_b, mA_bm, mB_a, mB_am,
-                  Es[cidx(b, p00[0], p00[1], p00[2])], Es[cidx(b, p10[0], p10[1], p10[2])],
-                  Es[cidx(b, p01[0], p01[1], p01[2])], Es[cidx(b, p11[0], p11[1], p11[2])]);
-            }
-          }
-    }
-    /* face update on interior faces */
-    for (int d = 0; d < 3; ++d) {
-      int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
-      int lo[3], hi[3];
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = g;
-        hi[a] = a == d ? g + n[a] : g + n[a] - 1;
-      }
-      for (int k = lo[2]; k <= hi[2]; ++k)
-        for (int j = lo[1]; j <= hi[1]; ++j)
-          for (int i = lo[0]; i <= hi[0]; ++i) {
-            int x1[3] = {i, j, k}, x2[3] = {i, j, k};
-            x1[d1] += 1;
-            x2[d2] += 1;
-            /* (curl E)^d = d_{d1} E_{d2} - d_{d2} E_{d1} */
-            double c1 = (Ec[d2][eidx(b, x1[0], x1[1], x1[2])] - Ec[d2][eidx(b, i, j, k)]) / b->dx[d1];
-            double c2 = (Ec[d1][eidx(b, x2[0], x2[1], x2[2])] - Ec[d1][eidx(b, i, j, k)]) / b->dx[d2];
-            int64_t f = fidx(b, d, i, j, k);
-            b->bo[d][f] = a0 * b->bn[d][f] + a1 * b->bs[d][f] - bb * dt * (c1 - c2);
-            if (g_tscale_b && g_tscale_f) {
-              double s1 = (Ecs[d2][eidx(b, x1[0], x1[1], x1[2])] + Ecs[d2][eidx(b, i, j, k)]) / b->dx[d1];
-              double s2 = (Ecs[d1][eidx(b, x2[0], x2[1], x2[2])] + Ecs[d1][eidx(b, i, j, k)]) / b->dx[d2];
-              g_tscale_b[ib * 3 + d][f] = fabs(a0 * b->bn[d][f]) + fabs(a1 * b->bs[d][f]) +
-                                          fabs(bb) * dt * (s1 + s2);
-            }
-          }
-    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    free(Ecc[a]);
+    free(Eccs[a]);
+  }
+}
+
+/* face update of block ib's interior faces from its corner EMFs */
+static void ct_faces(or_block *blks, int ib, double dt, double a0, double a1, double bb,
+                     double *Ec[3], double *Ecs[3]) {
+  or_block *b = &blks[ib];
+  int g = b->ng;
+  int n[3] = {b->nx, b->ny, b->nz};
+  /* face update on interior faces */
+  for (int d = 0; d < 3; ++d) {
+    int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-      free(Ecc[a]);
-      free(Ec[a]);
-      free(Eccs[a]);
-      free(Ecs[a]);
+      lo[a] = g;
+      hi[a] = a == d ? g + n[a] : g + n[a] - 1;
     }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          int x1[3] = {i, j, k}, x2[3] = {i, j, k};
+          x1[d1] += 1;
+          x2[d2] += 1;
+          /* (curl E)^d = d_{d1} E_{d2} - d_{d2} E_{d1} */
+          double c1 = (Ec[d2][eidx(b, x1[0], x1[1], x1[2])] - Ec[d2][eidx(b, i, j, k)]) / b->dx[d1];
+          double c2 = (Ec[d1][eidx(b, x2[0], x2[1], x2[2])] - Ec[d1][eidx(b, i, j, k)]) / b->dx[d2];
+          int64_t f = fidx(b, d, i, j, k);
+          b->bo[d][f] = a0 * b->bn[d][f] + a1 * b->bs[d][f] - bb * dt * (c1 - c2);
+          if (g_tscale_b && g_tscale_f) {
+            double s1 = (Ecs[d2][eidx(b, x1[0], x1[1], x1[2])] + Ecs[d2][eidx(b, i, j, k)]) / b->dx[d1];
+            double s2 = (Ecs[d1][eidx(b, x2[0], x2[1], x2[2])] + Ecs[d1][eidx(b, i, j, k)]) / b->dx[d2];
+            g_tscale_b[ib * 3 + d][f] = fabs(a0 * b->bn[d][f]) + fabs(a1 * b->bs[d][f]) +
+                                        fabs(bb) * dt * (s1 + s2);
+          }
+        }
+  }
+}
+
+static void alloc_emfs(const or_block *b, double *Ec[3], double *Ecs[3]) {
+  int64_t ne = nedge(b);
+  for (int a = 0; a < 3; ++a) {
+    Ec[a] = (double *)calloc((size_t)ne, sizeof(double));
+    Ecs[a] = g_tscale_b ? (double *)calloc((size_t)ne, sizeof(double)) : NULL;
+  }
+}
+static void free_emfs(double *Ec[3], double *Ecs[3]) {
+  for (int a = 0; a < 3; ++a) {
+    free(Ec[a]);
+    free(Ecs[a]);
+  }
+}
+
+int or_ct(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1, double bb,
+          double **Fall) {
+  (void)p;
+  for (int ib = 0; ib < nblk; ++ib) {
+    double *Ec[3], *Ecs[3];
+    alloc_emfs(&blks[ib], Ec, Ecs);
+    ct_emfs(blks, ib, Fall, Ec, Ecs);
+    ct_faces(blks, ib, dt, a0, a1, bb, Ec, Ecs);
+    free_emfs(Ec, Ecs);
   }
   return 0;
 }
@@ -1662,6 +2053,55 @@ int or_stage(or_block *blks, int nblk, const or_params *p, double dt, double a0,
     }
   }
   or_ct(blks, nblk, p, dt, a0, a1, bb, F);
+  or_update(blks, nblk, p, dt, a0, a1, bb, F);
+  or_stage_c2p(blks, nblk, p);
+  free_fluxes(F, nblk);
+  if (g_tscale_f) {
+    free_fluxes(g_tscale_f, nblk);
+    g_tscale_f = NULL;
+  }
+  return 0;
+}
+
+/* One stage on a refined mesh (leaves of several levels, amr): the steps of
+   or_stage, with the flag exchange across levels, and the flux correction
+   (after the FOFC refluxing) and EMF correction (between the corner EMFs and
+   the face update) at level boundaries. */
+int or_stage_amr(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1,
+                 double bb, const or_amr *amr) {
+  double **F = alloc_fluxes(blks, nblk);
+  if (g_tscale_u || g_tscale_b) g_tscale_f = alloc_fluxes(blks, nblk);
+  or_fluxes(blks, nblk, p, F);
+  if (p->fofc) {
+    or_fofc_flags(blks, nblk, p, dt, a0, a1, bb, F);
+    or_ghost_fill_amr(blks, nblk, GF_FLAGS, amr);
+    or_fofc_fix(blks, nblk, p, F);
+  } else {
+    for (int ib = 0; ib < nblk; ++ib) {
+      int64_t nc = ncell(&blks[ib]);
+      for (int64_t c = 0; c < nc; ++c) blks[ib].flags[c] = 0;
+    }
+  }
+  if (g_amr_flux_fix) {
+    amr_flux_correct(blks, nblk, amr, F);
+    if (g_tscale_f) amr_flux_correct(blks, nblk, amr, g_tscale_f);
+  }
+  double **E = (double **)calloc((size_t)nblk * 3, sizeof(double *));
+  double **Es = (double **)calloc((size_t)nblk * 3, sizeof(double *));
+  for (int ib = 0; ib < nblk; ++ib) {
+    alloc_emfs(&blks[ib], E + 3 * ib, Es + 3 * ib);
+    ct_emfs(blks, ib, F, E + 3 * ib, Es + 3 * ib);
+  }
+  if (g_amr_emf_fix) {
+    amr_emf_correct(blks, nblk, amr, E);
+    if (g_tscale_b) amr_emf_correct(blks, nblk, amr, Es);
+  }
+  for (int ib = 0; ib < nblk; ++ib) {
+    ct_faces(blks, ib, dt, a0, a1, bb, E + 3 * ib, Es + 3 * ib);
+    free_emfs(E + 3 * ib, Es + 3 * ib);
+  }
+  free(E);
+  free(Es);
   or_update(blks, nblk, p, dt, a0, a1, bb, F);
   or_stage_c2p(blks, nblk, p);
   free_fluxes(F, nblk);

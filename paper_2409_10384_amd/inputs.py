@@ -22,6 +22,14 @@ Workloads (seed = 2409_10384 + workload index):
                          A_phi ~ max(P - 0.04 P_max, 0), tiled into blocks
   refined_star_blocks    the same star sampled on ~1500 blocks of 16^3, 24^3
                          and 32^3 cells spread over 6 refinement levels
+                         (independent blocks with frozen ghosts)
+  leaf_mesh              a refined mesh: leaves of a 2:1-balanced octree of
+                         equal blocks (the structure only)
+  smooth_leaf_blocks     smooth periodic data on such a mesh, the face field
+                         the discrete curl of a vector potential whose
+                         components do not depend on their own coordinate
+                         (so coarse faces are the means of fine faces exactly)
+  star_leaf_blocks       the star on a leaf mesh refined towards its centre
   c2p_states             random primitive states over wide ranges of density,
                          specific energy, Lorentz factor and magnetisation in
                          random SPD 3-metrics near flat
@@ -541,3 +549,166 @@ def c2p_states_torch(n, seed_offset=3, gamma=5.0 / 3.0, log_rho=(-10.0, -2.0), l
     w = torch.stack([rho, W * v[:, 0], W * v[:, 1], W * v[:, 2], P]).contiguous()
     bt = (B * sqrtg[:, None]).T.contiguous()
     return {"w": w, "bt": bt, "gam": gam.contiguous(), "W": W, "eps": eps}
+
+
+# ---------------------------------------------------------------------------
+# refined meshes: leaves of a 2:1-balanced octree of equal blocks
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class LeafMesh:
+    """Leaves (level, (bi, bj, bk)) of an octree over nblocks0 level-0 blocks
+    of nb^3 cells; leaf l covers global cells [b nb, (b+1) nb) of its level
+    (cell size h0 / 2^level).  periodic: per axis, 1 periodic, 0 outflow."""
+    nblocks0: tuple
+    nb: int
+    periodic: tuple
+    leaves: list
+
+    @property
+    def n0(self):
+        return tuple(int(x) * self.nb for x in self.nblocks0)
+
+    def org(self, i):
+        return tuple(int(x) * self.nb for x in self.leaves[i][1])
+
+    @property
+    def levels(self):
+        return [lv for lv, _ in self.leaves]
+
+
+def leaf_mesh(nblocks0=(2, 2, 2), nb=8, refine=None, max_level=1, periodic=(1, 1, 1)):
+    """refine(level, (bi, bj, bk)) -> bool marks leaves to split (repeated up
+    to max_level); then leaves are split until every two leaves that touch
+    (across a face, an edge or a corner, periodic images included) differ by
+    at most one level.  Leaves are listed by level, then z, y, x."""
+    leaves = {(0, (i, j, k)) for k in range(nblocks0[2]) for j in range(nblocks0[1])
+              for i in range(nblocks0[0])}
+    for _ in range(max_level):
+        split = [lf for lf in leaves if lf[0] < max_level and refine is not None and refine(*lf)]
+        if not split:
+            break
+        for lv, b in split:
+            leaves.remove((lv, b))
+            for c in range(8):
+                leaves.add((lv + 1, (2 * b[0] + (c & 1), 2 * b[1] + ((c >> 1) & 1), 2 * b[2] + (c >> 2))))
+
+    def covering(lv, b):
+        for L in range(lv, -1, -1):
+            key = (L, tuple(x >> (lv - L) for x in b))
+            if key in leaves:
+                return key
+        return None
+
+    changed = True
+    while changed:
+        changed = False
+        for lv, b in sorted(leaves, key=lambda t: -t[0]):
+            if (lv, b) not in leaves or lv < 2:
+                continue
+            nbk = [n << lv for n in nblocks0]
+            for oz in (-1, 0, 1):
+                for oy in (-1, 0, 1):
+                    for ox in (-1, 0, 1):
+                        if ox == oy == oz == 0:
+                            continue
+                        q = [b[0] + ox, b[1] + oy, b[2] + oz]
+                        ok = True
+                        for a in range(3):
+                            if q[a] < 0 or q[a] >= nbk[a]:
+                                if periodic[a]:
+                                    q[a] %= nbk[a]
+                                else:
+                                    ok = False
+                        if not ok:
+                            continue
+                        cov = covering(lv, tuple(q))
+                        if cov is not None and cov[0] < lv - 1:
+                            leaves.remove(cov)
+                            L, cb = cov
+                            for c in range(8):
+                                leaves.add((L + 1, (2 * cb[0] + (c & 1), 2 * cb[1] + ((c >> 1) & 1),
+                                                    2 * cb[2] + (c >> 2))))
+                            changed = True
+    order = sorted(leaves, key=lambda t: (t[0], t[1][2], t[1][1], t[1][0]))
+    return LeafMesh(tuple(nblocks0), nb, tuple(int(x) for x in periodic), order)
+
+
+def _leaf_coords(mesh: LeafMesh, i, ng, h0):
+    lv, b = mesh.leaves[i]
+    h = h0 / 2 ** lv
+    o = [b[a] * mesh.nb for a in range(3)]
+    m = mesh.nb + 2 * ng
+    cc = [(o[a] - ng + np.arange(m) + 0.5) * h for a in range(3)]      # cell centres
+    fc = [(o[a] - ng + np.arange(m + 1)) * h for a in range(3)]        # faces / corners
+    return h, cc, fc
+
+
+def _waves_without(rng, axis, nwaves=3):
+    """random integer wave vectors with no component along `axis`"""
+    ks = []
+    while len(ks) < nwaves:
+        k = rng.integers(-2, 3, size=3)
+        k[axis] = 0
+        if np.any(k != 0):
+            ks.append(k)
+    return np.array(ks, dtype=np.float64), rng.uniform(0.0, 2.0 * np.pi, size=nwaves)
+
+
+def smooth_leaf_blocks(mesh: LeafMesh, ng=3, seed_offset=7, amp_rho=0.1, amp_p=0.01, amp_v=0.3,
+                       amp_a=0.05, flat=False, amp_lapse=0.05, amp_shift=0.01, amp_g=0.05,
+                       amp_k=0.01, uniform=None):
+    """Smooth periodic data on [0, 1)^3 sampled on every leaf of `mesh` (a
+    cubic domain: h0 = 1 / (nblocks0[0] nb)), ghosts included.  The fields are
+    those of smooth_periodic_block; the vector potential has A_x(y, z),
+    A_y(z, x), A_z(x, y) sampled at cell corners, so each edge value is the
+    exact line average and every face's B~ is the exact face average of the
+    curl.  flat: Minkowski metric (no sources).  uniform: (rho, u3, P, Bt3)
+    for a uniform state."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    waves = {}
+    for name in ("rho", "P", "u0", "u1", "u2", "alpha", "b0", "b1", "b2") + tuple(f"g{c}" for c in range(6)) \
+            + tuple(f"k{c}" for c in range(6)):
+        waves[name] = _random_waves(rng)
+    aw = [_waves_without(rng, a) for a in range(3)]
+    h0 = 1.0 / (mesh.nblocks0[0] * mesh.nb)
+    out = []
+    for i in range(len(mesh.leaves)):
+        lv, _ = mesh.leaves[i]
+        h, cc, fc = _leaf_coords(mesh, i, ng, h0)
+        Z, Y, X = np.meshgrid(cc[2], cc[1], cc[0], indexing="ij")
+        f = lambda nm: _wave_sum(*waves[nm], X, Y, Z)
+        rho = 1.0 + amp_rho * f("rho")
+        P = 0.1 + amp_p * f("P")
+        u = [amp_v * f(f"u{c}") / math.sqrt(3.0) for c in range(3)]
+        if flat:
+            alpha = np.ones_like(rho)
+            beta = [np.zeros_like(rho) for _ in range(3)]
+            gam = [np.full_like(rho, 1.0 if c in (0, 3, 5) else 0.0) for c in range(6)]
+            K = [np.zeros_like(rho) for _ in range(6)]
+        else:
+            alpha = 1.0 + amp_lapse * f("alpha")
+            beta = [amp_shift * f(f"b{c}") for c in range(3)]
+            gam = [(1.0 if c in (0, 3, 5) else 0.0) + amp_g * f(f"g{c}") for c in range(6)]
+            K = [amp_k * f(f"k{c}") for c in range(6)]
+        # A at corners (z, y, x lattices of m + 1 points); A_x depends on (y, z) ...
+        Zc, Yc, Xc = np.meshgrid(fc[2], fc[1], fc[0], indexing="ij")
+        Ax = amp_a * _wave_sum(*aw[0], Xc, Yc, Zc)
+        Ay = amp_a * _wave_sum(*aw[1], Xc, Yc, Zc)
+        Az = amp_a * _wave_sum(*aw[2], Xc, Yc, Zc)
+        # face averages of curl A from corner values (A_x constant along x, ...)
+        Bx = ((Az[:-1, 1:, :] - Az[:-1, :-1, :]) - (Ay[1:, :-1, :] - Ay[:-1, :-1, :])) / h
+        By = ((Ax[1:, :, :-1] - Ax[:-1, :, :-1]) - (Az[:-1, :, 1:] - Az[:-1, :, :-1])) / h
+        Bz = ((Ay[:, :-1, 1:] - Ay[:, :-1, :-1]) - (Ax[:, 1:, :-1] - Ax[:, :-1, :-1])) / h
+        if uniform is not None:
+            r0, u0, p0, b0 = uniform
+            rho = np.full_like(rho, r0)
+            P = np.full_like(rho, p0)
+            u = [np.full_like(rho, u0[c]) for c in range(3)]
+            Bx, By, Bz = (np.full_like(a, b0[c]) for c, a in enumerate((Bx, By, Bz)))
+        w = np.stack([rho, u[0], u[1], u[2], P])
+        adm = np.stack([alpha] + beta + gam + K)
+        org = mesh.org(i)
+        out.append(BlockInit(mesh.nb, mesh.nb, mesh.nb, ng, (h, h, h), np.ascontiguousarray(w),
+                             [np.ascontiguousarray(b) for b in (Bx, By, Bz)], np.ascontiguousarray(adm),
+                             [-1] * 27, 1, lv, tuple(org[a] * h for a in range(3))))
+    return out
