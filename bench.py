@@ -220,7 +220,11 @@ def copy_bandwidth(torch, lib, n=1 << 27, reps=10):
 def star_section(args, torch, inputs, lib):
     t0 = time.perf_counter()
     log(f"building inputs: star, {args.blocks_per_side}^3 blocks of {args.block}^3")
-    blocks, st = inputs.star_blocks(n_per_side=args.blocks_per_side, nb=args.block, device="cuda")
+    # --host-inputs: the initial data built with numpy and copied over (a
+    # counter pass then sees a few copies instead of thousands of small
+    # elementwise kernels)
+    blocks, st = inputs.star_blocks(n_per_side=args.blocks_per_side, nb=args.block,
+                                    device=None if args.host_inputs else "cuda")
     params = lib.MethodParams(**STAR_PARAMS)
     mesh = lib.DeviceMesh(blocks, params, device="cuda")
     torch.cuda.synchronize()
@@ -735,6 +739,8 @@ def main():
                     help="skip the reconstruction / RK3 / matter-source measurements on the star")
     ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")
     ap.add_argument("--c5-steps", type=int, default=100)
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="build the star's initial data on the host (counter passes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB plain copy first (for counter scaling)")
     args = ap.parse_args()

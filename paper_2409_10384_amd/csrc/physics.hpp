@@ -288,12 +288,13 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   const double be1 = k13 * s1a * s1a + 0.25 * s1b * s1b;
   const double be2 = k13 * s2a * s2a + 0.25 * s2b * s2b;
   const double t5 = fabs(be0 - be2);
-  // the three ratios t5 / (beta_k + eps) from one reciprocal of the product
-  // (each factor lies in [1e-40, ~1e3] for the fields reconstructed here)
-  const double e0 = be0 + 1e-40, e1 = be1 + 1e-40, e2 = be2 + 1e-40;
-  const double e12 = e1 * e2;
-  const double tip = t5 * rcp_nr(e0 * e12);
-  const double r0 = tip * e12, r1 = tip * (e0 * e2), r2 = tip * (e0 * e1);
+  // the three ratios t5 / (beta_k + eps), each from a refined reciprocal of
+  // its own denominator (at least 1e-40, so no reciprocal overflows; one
+  // reciprocal of the product of the three would overflow for smoothness
+  // indicators beyond ~1e100)
+  const double r0 = t5 * rcp_nr(be0 + 1e-40);
+  const double r1 = t5 * rcp_nr(be1 + 1e-40);
+  const double r2 = t5 * rcp_nr(be2 + 1e-40);
   const double w0 = 0.1 * (1.0 + r0 * r0);
   const double w1 = 0.6 * (1.0 + r1 * r1);
   const double w2 = 0.3 * (1.0 + r2 * r2);

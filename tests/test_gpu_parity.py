@@ -196,9 +196,19 @@ def _compare_state(om, gm, which, tol, label):
     return worst
 
 
-def test_flux_parity_smooth_block(G):
-    say("flux parity: smooth periodic block 32^3")
+@pytest.mark.parametrize("scale", [1.0, 1e120])
+def test_flux_parity_smooth_block(G, scale):
+    """scale multiplies rho and P (and B by its square root, so every
+    velocity is unchanged): at 1e120 the WENOZ smoothness indicators reach
+    ~1e240 and the product of three of them overflows, which the kernel's
+    one-reciprocal form must detect"""
+    say(f"flux parity: smooth periodic block 32^3, rho and P scaled by {scale:g}")
     blk = inputs.smooth_periodic_block(n=32)
+    if scale != 1.0:
+        blk.w[0] *= scale
+        blk.w[4] *= scale
+        for f in blk.bf:
+            f *= np.sqrt(scale)
     p = O.Params(gamma=5.0 / 3.0)
     om, gm = _meshes(G, [blk], p)
     F = O.alloc_fluxes(om)
