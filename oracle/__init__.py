@@ -483,22 +483,23 @@ class RefinedMesh(Mesh):
 
     def __init__(self, blocks, params: Params, leafmesh):
         super().__init__(blocks, params)
-        nb = len(blocks)
         self.leafmesh = leafmesh
-        self._level = (C.c_int32 * nb)(*leafmesh.levels)
-        self._org = (C.c_int32 * (3 * nb))(*[o for i in range(nb) for o in leafmesh.org(i)])
-        self.amr = OrAmr()
-        self.amr.n0 = (C.c_int32 * 3)(*leafmesh.n0)
-        self.amr.periodic = (C.c_int32 * 3)(*leafmesh.periodic)
-        self.amr.level = C.cast(self._level, C.POINTER(C.c_int32))
-        self.amr.org = C.cast(self._org, C.POINTER(C.c_int32))
+
+    def _amr(self):
+        """the or_amr of the leaf mesh and the arrays it points into"""
+        m = self.leafmesh
+        nb = len(self.blocks)
+        level = (C.c_int32 * nb)(*m.levels)
+        org = (C.c_int32 * (3 * nb))(*[o for i in range(nb) for o in m.org(i)])
+        amr = OrAmr()
+        amr.n0 = (C.c_int32 * 3)(*m.n0)
+        amr.periodic = (C.c_int32 * 3)(*m.periodic)
+        amr.level = C.cast(level, C.POINTER(C.c_int32))
+        amr.org = C.cast(org, C.POINTER(C.c_int32))
+        return amr, (level, org)
 
     def ghost_fill_state(self, which):
-        U, W, Bf = self._set(which)
-        arr = (OrBlock * len(self.blocks))()
-        for ib in range(len(self.blocks)):
-            arr[ib] = self._desc(ib, W[ib], U[ib], U[ib], Bf[ib], Bf[ib], U[ib], Bf[ib], W[ib])
-        lib().or_ghost_fill_amr(arr, len(self.blocks), GF_W | GF_US | GF_BS, C.byref(self.amr))
+        self.ghost_fill_mask(which, GF_W | GF_US | GF_BS)
 
     def ghost_fill_mask(self, which, mask):
         """ghost fill of the selected fields (GF_* bits) of state set `which`"""
@@ -506,11 +507,13 @@ class RefinedMesh(Mesh):
         arr = (OrBlock * len(self.blocks))()
         for ib in range(len(self.blocks)):
             arr[ib] = self._desc(ib, W[ib], U[ib], U[ib], Bf[ib], Bf[ib], U[ib], Bf[ib], W[ib])
-        lib().or_ghost_fill_amr(arr, len(self.blocks), mask, C.byref(self.amr))
+        amr, keep = self._amr()
+        lib().or_ghost_fill_amr(arr, len(self.blocks), mask, C.byref(amr))
 
     def _run_stage(self, arr, nb, dt, a0, a1, b):
+        amr, keep = self._amr()
         lib().or_stage_amr(arr, nb, C.byref(self.params.c()), C.c_double(dt), C.c_double(a0),
-                           C.c_double(a1), C.c_double(b), C.byref(self.amr))
+                           C.c_double(a1), C.c_double(b), C.byref(amr))
 
     def mass_total(self, which=0):
         """sum of D~ dV over every leaf's interior (each leaf with its own dV)"""

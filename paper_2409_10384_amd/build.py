@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgrmhd.so")
-SOURCES = [os.path.join(HERE, "csrc", "grmhd.hip"), os.path.join(HERE, "csrc", "learned.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "grmhd.hip"), os.path.join(HERE, "csrc", "learned.hip"),
+           os.path.join(HERE, "csrc", "amr.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "physics.hpp"), os.path.join(HERE, "csrc", "mlp.hpp"),
            os.path.join(ROOT, "include", "grmhd.h")]
 

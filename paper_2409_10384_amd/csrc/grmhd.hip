@@ -18,6 +18,21 @@
 
 using namespace gk;
 
+namespace gk {
+// inter-level transfer (amr.hip)
+int amr_max_level(const grmhd_amr_link* h, int nblk);
+int amr_check(const grmhd_block* h, const grmhd_amr_link* lh, int nblk);
+void launch_ghost_cells_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
+                            const grmhd_amr_link* ld, int mask, int list, int pass,
+                            unsigned grid, int threads, hipStream_t s);
+void launch_ghost_faces_amr(const grmhd_block* d, const grmhd_amr_link* ld, int dir, int pass,
+                            unsigned grid, int threads, hipStream_t s);
+void launch_amr_flux_fix(const grmhd_block* d, const grmhd_amr_link* ld, int nblk, int nb,
+                         hipStream_t s);
+void launch_amr_emf_fix(const grmhd_block* d, const grmhd_amr_link* ld, int nblk, int nb,
+                        hipStream_t s);
+}  // namespace gk
+
 namespace {
 
 constexpr int kThreads = 256;      // fixed-size kernels (pointwise, reductions)
@@ -1356,9 +1371,10 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
   });
 }
 
+// links (device): a refined mesh, whose flag exchange crosses levels
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
               const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
-              hipStream_t s) {
+              hipStream_t s, const grmhd_amr_link* links = nullptr) {
   k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
   if (!p.fofc) return;
   {
@@ -1369,7 +1385,11 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   }
   bool exchange = false;
   for (int i = 0; i < nblk; ++i) exchange = exchange || h[i].bc == 1;
-  if (exchange) {
+  if (links) {
+    TIMED(T_GHOST, s);
+    launch_ghost_cells_amr(h, d, nblk, links, 8, 1, -1, grid_cls(h, nblk, S_GSHELL, tpb(T_GHOST)).x,
+                           tpb(T_GHOST), s);
+  } else if (exchange) {
     TIMED(T_GHOST, s);
     k_ghost_cells<<<grid_cls(h, nblk, S_GSHELL, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8, 1);
   }
@@ -1381,10 +1401,13 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   });
 }
 
+// links (device): a refined mesh, whose boundary EMFs next to finer leaves
+// are corrected between the corner EMFs and the face update
 void run_ct(const grmhd_block* h, const grmhd_block* d, int nblk, const double* dt_d, double dt,
-            double a0, double a1, double b, hipStream_t s) {
+            double a0, double a1, double b, hipStream_t s, const grmhd_amr_link* links = nullptr) {
   TIMED(T_CT, s);
   k_emf_corners<<<grid_cls(h, nblk, S_CORNER, tpb(T_CT)), tpb(T_CT), 0, s>>>(d);
+  if (links) launch_amr_emf_fix(d, links, nblk, h[0].nx, s);
   k_ct_faces<<<grid_cls(h, nblk, S_CORNER, tpb(T_CT)), tpb(T_CT), 0, s>>>(d, dt_d, dt, a0, a1, b);
 }
 
@@ -1696,6 +1719,54 @@ int grmhd_ghost_fill(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t
   if (mask & 4) {
     for (int d = 0; d < 3; ++d) k_ghost_faces<<<grid_cls(blk_h, nblk, S_GXFACE + d, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(blk_d, d);
   }
+  return last_err();
+}
+
+int grmhd_ghost_fill_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                         const grmhd_amr_link* links_h, const grmhd_amr_link* links_d,
+                         int32_t mask, void* stream) {
+  if (!blk_h || !blk_d || !links_d || nblk < 1 || (mask & ~15)) return GRMHD_EINVAL;
+  if (prepare_layout(const_cast<grmhd_block*>(blk_h), nblk, false) != 0) return GRMHD_EINVAL;
+  int r = amr_check(blk_h, links_h, nblk);
+  if (r) return r;
+  for (int i = 0; i < nblk; ++i) {
+    const grmhd_block& b = blk_h[i];
+    if (((mask & 1) && !b.w[4]) || ((mask & 2) && !b.us[4]) || ((mask & 4) && !b.bs[2]) ||
+        ((mask & 8) && !b.flags))
+      return GRMHD_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  TIMED(T_GHOST, s);
+  const int top = amr_max_level(links_h, nblk);
+  // copies and restrictions (pass 0), then the prolongations level by level
+  for (int pass = 0; pass <= top; ++pass) {
+    if (mask & 11)
+      launch_ghost_cells_amr(blk_h, blk_d, nblk, links_d, mask & 11, 0, pass,
+                             grid_cls(blk_h, nblk, S_GCELLS, tpb(T_GHOST)).x, tpb(T_GHOST), s);
+    if (mask & 4)
+      for (int d = 0; d < 3; ++d)
+        launch_ghost_faces_amr(blk_d, links_d, d, pass,
+                               grid_cls(blk_h, nblk, S_GXFACE + d, tpb(T_GHOST)).x, tpb(T_GHOST), s);
+  }
+  return last_err();
+}
+
+int grmhd_stage_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                    const grmhd_amr_link* links_h, const grmhd_amr_link* links_d,
+                    const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
+                    double b, void* stream) {
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  if (!links_d) return GRMHD_EINVAL;
+  if ((r = amr_check(blk_h, links_h, nblk))) return r;
+  const Eos e = make_eos(*p);
+  hipStream_t s = (hipStream_t)stream;
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, links_d);
+  launch_amr_flux_fix(blk_d, links_d, nblk, blk_h[0].nx, s);
+  run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s, links_d);
+  run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s, true);
   return last_err();
 }
 

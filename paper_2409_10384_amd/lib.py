@@ -58,6 +58,15 @@ class Rk2Tables(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("a_h", "a_d", "b_h", "b_d", "ab_h", "ab_d", "ba_h", "ba_d")]
 
 
+class GrmhdAmrLink(C.Structure):
+    """grmhd_amr_link: a leaf's level, origin, domain size and the leaves
+    covering each of its 27 neighbour regions"""
+    _fields_ = [
+        ("level", C.c_int32), ("org", C.c_int32 * 3), ("N", C.c_int32 * 3), ("periodic", C.c_int32),
+        ("rel", C.c_int32 * 27), ("src", (C.c_int32 * 4) * 27),
+    ]
+
+
 class C2PStats(C.Structure):
     _fields_ = [("solves", C.c_uint64), ("evaluations", C.c_uint64), ("fallbacks", C.c_uint64),
                 ("failures", C.c_uint64)]
@@ -114,8 +123,24 @@ def load():
     L.grmhd_c2p_pairs.argtypes = blk + [C.c_int32, vp, vp, vp, vp, vp, vp]
     L.c2p_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_int32, vp, vp,
                                      vp, vp, vp]
+    L.grmhd_amr_links.argtypes = [C.c_int32, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
+    L.grmhd_ghost_fill_amr.argtypes = blk + [vp, vp, C.c_int32, vp]
+    L.grmhd_stage_amr.argtypes = blk + [vp, vp] + stage[3:]
     _lib = L
     return L
+
+
+def amr_links(levels, orgs, nb, ng, n0, periodic):
+    """host array of grmhd_amr_link of a leaf mesh (grmhd_amr_links)"""
+    n = len(levels)
+    lv = (C.c_int32 * n)(*levels)
+    og = (C.c_int32 * (3 * n))(*[int(x) for o in orgs for x in o])
+    links = (GrmhdAmrLink * n)()
+    check(load().grmhd_amr_links(n, C.cast(lv, C.c_void_p), C.cast(og, C.c_void_p), nb, ng,
+                                 C.cast((C.c_int32 * 3)(*n0), C.c_void_p),
+                                 C.cast((C.c_int32 * 3)(*periodic), C.c_void_p), links),
+          "grmhd_amr_links")
+    return links
 
 
 def _nullctx():
@@ -624,6 +649,38 @@ class DeviceMesh:
 # learned guess and bracket for the inversion
 # ---------------------------------------------------------------------------
 NPARAM = 8834
+
+
+class RefinedDeviceMesh(DeviceMesh):
+    """A DeviceMesh whose blocks are the leaves of a refined mesh (a LeafMesh
+    of paper_2409_10384_amd.inputs, blocks in its leaf order): ghost fills
+    across levels (grmhd_ghost_fill_amr) and stages with the flux and EMF
+    corrections at level boundaries (grmhd_stage_amr)."""
+
+    def __init__(self, blocks, params: MethodParams, leafmesh, device="cuda", stream=None):
+        b0 = blocks[0]
+        self.links = amr_links(leafmesh.levels, [leafmesh.org(i) for i in range(len(blocks))],
+                               b0.nx, b0.ng, leafmesh.n0, leafmesh.periodic)
+        self.leafmesh = leafmesh
+        super().__init__(blocks, params, device=device, stream=stream)
+        raw = bytes(memoryview(self.links).cast("B"))
+        self.links_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+
+    def _links(self):
+        return C.cast(self.links, C.c_void_p), C.c_void_p(self.links_dev.data_ptr())
+
+    def stage_sets(self, src, dst, coef, dt=None, dt_dev=None, mlp=None, stats=None):
+        if mlp is not None or stats is not None:
+            raise GrmhdError("the refined-mesh stage has the plain inversion only")
+        a0, a1, b = coef
+        dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
+        dval = float(dt) if dt is not None else 0.0
+        check(load().grmhd_stage_amr(*self._args((src, dst)), *self._links(), C.byref(self.params.c()),
+                                     dptr, dval, a0, a1, b, self.sp()), "grmhd_stage_amr")
+
+    def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
+        check(load().grmhd_ghost_fill_amr(*self._args((which, which)), *self._links(), mask, self.sp()),
+              "grmhd_ghost_fill_amr")
 
 
 class Rk2Graph:

@@ -1,0 +1,170 @@
+"""Inter-level transfer on the GPU (grmhd_ghost_fill_amr, grmhd_stage_amr)
+against the oracle's (or_ghost_fill_amr, or_stage_amr), through the C ABI:
+
+* the ghost fill from a common input: every ghost cell (w, U) and ghost face
+  of every leaf bit for bit (copies, restrictions and prolongations do the
+  same operations in the same order on both sides), on a two-level periodic
+  mesh and on a three-level mesh with outflow and periodic axes;
+* every stage of an RK2 step from the oracle's stage input at 1e-12 per
+  stage (tests/stage_parity.py: term-magnitude gate, decisions only within
+  1e-9 of a threshold may differ), on both meshes, FOFC+DMP on;
+* the device on its own through RK2 steps in flat space: all five totals
+  conserved to round-off, div B~ at round-off in every cell, coarse faces on
+  level boundaries equal to the mean of the fine faces."""
+import copy
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_10384_amd import inputs
+from tests import stage_parity as SP
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10384_amd import lib
+    lib.load()
+    return lib
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def to_mp(G, p: O.Params):
+    return G.MethodParams(**{f.name: getattr(p, f.name) for f in dataclasses.fields(p)})
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+MESHES = {
+    "two-level periodic": lambda: inputs.leaf_mesh((2, 2, 2), 8, refine=lambda lv, b: lv == 0 and b == (0, 0, 0),
+                                                   max_level=1),
+    "three-level, outflow in y": lambda: inputs.leaf_mesh((2, 2, 2), 8, refine=lambda lv, b: b == (0, 0, 0),
+                                                          max_level=2, periodic=(1, 0, 1)),
+}
+PARAMS = O.Params(gamma=5.0 / 3.0, fofc=1, dmp_M=1.0)
+
+
+def _upload(gm, om):
+    for k in range(2):
+        for dev, ref in zip(gm._set(k), om._set(k)):
+            for ib in range(len(om.blocks)):
+                if isinstance(ref[ib], list):
+                    for d in range(3):
+                        dev[ib][d].copy_(torch.from_numpy(ref[ib][d]))
+                else:
+                    dev[ib].copy_(torch.from_numpy(ref[ib]))
+
+
+def _interior(b, a):
+    g = b.ng
+    return a[..., g:g + b.nz, g:g + b.ny, g:g + b.nx]
+
+
+def _download(gm, dst, ib):
+    U, W, Bf = gm._set(dst)
+    b = gm.blocks[ib]
+    return (_interior(b, host(U[ib])), _interior(b, host(W[ib])),
+            [host(Bf[ib][d])[SP._face_slices(b, d)] for d in range(3)],
+            _interior(b, host(gm.flags[ib]).astype(np.uint16)))
+
+
+def _meshes(G, name, **kw):
+    m = MESHES[name]()
+    blocks = inputs.smooth_leaf_blocks(m, **kw)
+    om = O.RefinedMesh(copy.deepcopy(blocks), PARAMS, m)
+    gm = G.RefinedDeviceMesh(copy.deepcopy(blocks), to_mp(G, PARAMS), m)
+    return m, om, gm
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_ghost_fill_across_levels_is_bitwise_the_oracle(G, name):
+    m, om, gm = _meshes(G, name)
+    say(f"ghost fill across levels: {name}, {len(m.leaves)} leaves, levels {sorted(set(m.levels))}")
+    # a common input: the oracle's state (its ghosts poisoned on both sides)
+    for ib, b in enumerate(om.blocks):
+        g = b.ng
+        msk = np.ones(b.shape, bool)
+        msk[g:g + b.nz, g:g + b.ny, g:g + b.nx] = False
+        om.w0[ib][:, msk] = np.nan
+        om.u0[ib][:, msk] = np.nan
+        for d in range(3):
+            fm = np.ones(om.b0[ib][d].shape, bool)
+            fm[SP._face_slices(b, d)] = False
+            om.b0[ib][d][fm] = np.nan
+    _upload(gm, om)
+    om.ghost_fill_state(0)
+    gm.ghost_fill(0)
+    torch.cuda.synchronize()
+    for ib in range(len(om.blocks)):
+        np.testing.assert_array_equal(host(gm.w0[ib]), om.w0[ib])
+        np.testing.assert_array_equal(host(gm.u0[ib]), om.u0[ib])
+        for d in range(3):
+            np.testing.assert_array_equal(host(gm.b0[ib][d]), om.b0[ib][d])
+        assert np.all(np.isfinite(om.w0[ib])) and all(np.all(np.isfinite(f)) for f in om.b0[ib])
+    say("  every ghost cell and face equal")
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_stage_parity_across_levels(G, name):
+    m, om, gm = _meshes(G, name)
+    say(f"stage parity across levels: {name}, {len(m.leaves)} leaves")
+    om.ghost_fill_state(0)
+    dt = om.dt(0.3)
+    summary = SP.stage_parity(gm, om, O.Mesh.RK2, dt, tol=1e-12, margin=1e-9, say=say, upload=_upload,
+                              download=_download)
+    assert len(summary) == 2
+    assert any(np.any(f & (O.F_DMP | O.F_FOFC)) for f in om.flags)
+
+
+def _divb(gm):
+    worst = 0.0
+    for ib, b in enumerate(gm.blocks):
+        g, n = b.ng, b.nx
+        bx, by, bz = (host(f) for f in gm.b0[ib])
+        s = slice(g, g + n)
+        d = ((bx[s, s, g + 1:g + n + 1] - bx[s, s, s]) + (by[s, g + 1:g + n + 1, s] - by[s, s, s])
+             + (bz[g + 1:g + n + 1, s, s] - bz[s, s, s]))
+        worst = max(worst, float(np.abs(d).max()) / max(np.abs(bx).max(), np.abs(by).max(), np.abs(bz).max()))
+    return worst
+
+
+def _totals(gm):
+    return np.array([sum(float(_interior(b, host(gm.u0[ib][v])).sum()) * np.prod(b.dx)
+                         for ib, b in enumerate(gm.blocks)) for v in range(5)])
+
+
+def test_device_steps_conserve_and_keep_div_b_across_levels(G):
+    m, om, gm = _meshes(G, "two-level periodic", flat=True)
+    say(f"device RK2 steps on a two-level mesh, flat metric: {len(m.leaves)} leaves")
+    gm.ghost_fill(0)
+    om.ghost_fill_state(0)
+    t0 = _totals(gm)
+    dt = om.dt(0.3)
+    for step in range(3):
+        gm.rk2_step(dt=dt)
+        om.rk2_step(dt)
+    torch.cuda.synchronize()
+    dtot = np.abs(_totals(gm) - t0) / np.abs(t0).max()
+    divb = _divb(gm)
+    # the chained device steps against the oracle's (pointwise, loose: three
+    # steps of differences at round-off)
+    worst = 0.0
+    for ib in range(len(om.blocks)):
+        a, r = host(gm.u0[ib]), om.u0[ib]
+        worst = max(worst, float(np.abs(_interior(gm.blocks[ib], a - r)).max()) / float(np.abs(r).max()))
+    say(f"  conservation {dtot}, div B {divb:.1e}, device vs oracle after 3 steps {worst:.1e}")
+    assert np.all(dtot < 2e-15), dtot
+    assert divb < 1e-14
+    assert worst < 1e-11
