@@ -465,29 +465,50 @@ def _block_numpy(b):
     return c
 
 
-def c5_section(args, torch, inputs, lib):
-    """End-to-end: the refined star (the ~1500-block list, frozen ghosts) with a
-    seeded 3-piece piecewise polytrope + Gamma_th = 1.75 thermal part, K RK2
-    steps with device dt, plain C2P against the learned bracket in the stage
-    inversion (network trained on prim/cons pairs of the run's own states)"""
+def c5_section(args, torch, inputs, lib, amr=True):
+    """End-to-end: the star with a seeded 3-piece piecewise polytrope +
+    Gamma_th = 1.75 thermal part, K RK2 steps with device dt, plain C2P
+    against the learned bracket in the stage inversion (network trained on
+    prim/cons pairs of the run's own states).  amr: the star on a leaf mesh
+    of 32^3 blocks over 4 levels with the inter-level transfer (ghost fills
+    across levels, flux and EMF correction); else the ~1500 independent
+    blocks of 16^3, 24^3 and 32^3 over 6 levels with ghosts frozen at the
+    analytic data."""
     pp, pK = inputs.pp_eos()
     st = inputs.calibrate_field(inputs.StarSetup(pp=pp, pp_K=pK))
-    blocks, st = inputs.refined_star_blocks(nblocks=args.refined_blocks, device="cuda", st=st)
     params_kw = {**STAR_PARAMS, **pp}
     params = lib.MethodParams(**params_kw)
-    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
     K = args.c5_steps
-    # seeded subset of 16 of the 16^3 blocks for the oracle check on the host
-    rng = np.random.default_rng(inputs.SEED_BASE + 55)
-    small = [i for i, b in enumerate(blocks) if b.nx == 16]
-    subset = sorted(int(i) for i in rng.choice(small, size=min(16, len(small)), replace=False))
-    init_sub = [_block_numpy(blocks[i]) for i in subset]
+    if amr:
+        blocks, leaf, st = inputs.star_leaf_blocks(st=st, device="cuda")
+        make = lambda bl: lib.RefinedDeviceMesh(bl, params, leaf, device="cuda")
+        # the oracle check: the same leaf structure with 8^3 blocks, whole mesh
+        small_np, small_leaf, _ = inputs.star_leaf_blocks(st=st, nb=8)
+        subset = list(range(len(small_np)))
+        init_sub = small_np
+        warm_mesh = lambda: lib.RefinedDeviceMesh([_copy_np(b) for b in small_np], params, small_leaf,
+                                                  device="cuda")
+        log(f"c5 (refined mesh, inter-level transfer): {len(blocks)} leaves of 32^3 on levels "
+            f"{sorted(set(leaf.levels))}")
+    else:
+        blocks, st = inputs.refined_star_blocks(nblocks=args.refined_blocks, device="cuda", st=st)
+        make = lambda bl: lib.DeviceMesh(bl, params, device="cuda")
+        # seeded subset of 16 of the 16^3 blocks for the oracle check on the host
+        rng = np.random.default_rng(inputs.SEED_BASE + 55)
+        small = [i for i, b in enumerate(blocks) if b.nx == 16]
+        subset = sorted(int(i) for i in rng.choice(small, size=min(16, len(small)), replace=False))
+        init_sub = [_block_numpy(blocks[i]) for i in subset]
+        warm_mesh = lambda: lib.DeviceMesh(_clone_blocks(blocks[:2]), params, device="cuda")
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
     log(f"c5: {len(blocks)} blocks, {ncell} cells, piecewise polytrope Gamma={pp['Gam'][:3]}")
-    plain = lib.DeviceMesh(blocks, params, device="cuda")
-    learned = lib.DeviceMesh(_clone_blocks(blocks), params, device="cuda")
+    plain = make(blocks)
+    learned = make(_clone_blocks(blocks))
+    if amr:
+        plain.ghost_fill(0)
+        learned.ghost_fill(0)
     net = lib.LearnedC2P(seed=0)
-    # warm every kernel of both paths once on a two-block copy
-    warm = lib.DeviceMesh(_clone_blocks(blocks[:2]), params, device="cuda")
+    # warm every kernel of both paths once on a small mesh
+    warm = warm_mesh()
     wu, wb, wg, ww = warm.c2p_pairs(0)
     net.fit(wu, wb, wg, params, ww, steps=2)
     warm.rk2_step(cfl=0.25)
@@ -552,8 +573,35 @@ def c5_section(args, torch, inputs, lib):
            "learned": {"ms": ms_l, "zone_updates_per_s": ncell * K / (ms_l * 1e-3), "mass_drift": drift_l,
                        "fallback_rate": n_fb / max(n_s, 1), "evals_per_solve": n_ev / max(n_s, 1),
                        "failures": n_fail, "solves": n_s, "kernel_ms_per_step": kt_l},
-           "learned_speedup": ms_p / ms_l, "train_s": train_s,
-           "note": "ghosts frozen at the analytic data, so mass also flows through block faces"}
+           "learned_speedup": ms_p / ms_l, "train_s": train_s}
+    if amr:
+        res["mesh"] = {"leaves": len(blocks), "block": 32, "levels": sorted(set(leaf.levels)),
+                       "leaves_per_level": {int(l): int(leaf.levels.count(l)) for l in set(leaf.levels)},
+                       "domain": "[-48, 48]^3, outflow", "refined_within": [28.0, 14.0, 8.0]}
+        res["note"] = ("ghosts filled across levels every stage (copy / restriction / prolongation), "
+                       "flux and EMF correction at level boundaries; the drift is the floors' and the "
+                       "outflow boundary's")
+        # the oracle check's GPU leg: the 8^3-block mesh, a few steps from the
+        # same initial data, plain and learned
+        del plain, learned
+        torch.cuda.synchronize()
+        sub = {"subset": subset, "init": init_sub, "leaf": small_leaf, "params": params_kw}
+        for kind, mlp in (("plain", None), ("learned", net)):
+            gm = warm_mesh()
+            gm.ghost_fill(0)
+            dts = []
+            for _ in range(args.c5_check_steps):
+                gm.compute_dt(0.25)
+                dts.append(float(gm.dt_dev.item()))
+                gm.rk2_step(dt=dts[-1], mlp=mlp)
+            torch.cuda.synchronize()
+            sub["dts_" + kind] = np.array(dts)
+            sub["gpu_" + kind] = [(gm.u0[i].cpu().numpy(), gm.w0[i].cpu().numpy(),
+                                   [f.cpu().numpy() for f in gm.b0[i]]) for i in subset]
+            del gm
+        sub["dts"] = sub["dts_plain"]
+        return res, sub
+    res["note"] = "ghosts frozen at the analytic data, so mass also flows through block faces"
     # the oracle check runs on the host in the cpu leg, from these
     sub = {"subset": subset, "init": init_sub, "dts": dts_p.cpu().numpy(),
            "gpu_plain": [(plain.u0[i].cpu().numpy(), plain.w0[i].cpu().numpy(),
@@ -576,16 +624,27 @@ def c5_oracle_check(sub):
     block's largest D~ and over the star's cells alone."""
     import oracle as O
     from tests import parity as PM
-    out = {"blocks": sub["subset"]}
-    m = O.Mesh([_copy_np(b) for b in sub["init"]], O.Params(**sub["params"]))
-    t0 = time.perf_counter()
-    for dt in sub["dts"]:
-        m.rk2_step(float(dt))
-    el = time.perf_counter() - t0
-    out["oracle_s"] = el
+    amr = "leaf" in sub
+    out = {"blocks": sub["subset"] if not amr else f"all {len(sub['subset'])} leaves of the 8^3 mesh"}
     names_u = ("D", "S_x", "S_y", "S_z", "tau")
     names_w = ("rho", "u_x", "u_y", "u_z", "P")
+    el = 0.0
+    meshes = {}
     for kind in ("learned", "plain"):
+        dts = sub.get("dts_" + kind, sub["dts"])
+        key = tuple(float(x) for x in dts)
+        if key not in meshes:
+            if amr:
+                m = O.RefinedMesh([_copy_np(b) for b in sub["init"]], O.Params(**sub["params"]), sub["leaf"])
+                m.ghost_fill_state(0)
+            else:
+                m = O.Mesh([_copy_np(b) for b in sub["init"]], O.Params(**sub["params"]))
+            t0 = time.perf_counter()
+            for dt in dts:
+                m.rk2_step(float(dt))
+            el += time.perf_counter() - t0
+            meshes[key] = m
+        m = meshes[key]
         worst_all, worst_star = 0.0, 0.0
         fields = {}
         for j, (gu, gw, gb) in enumerate(sub["gpu_" + kind]):
@@ -609,8 +668,10 @@ def c5_oracle_check(sub):
                      "max_dev_by_field": fields, "max_dev_all_fields": max(fields.values())}
         log(f"c5 oracle check ({kind}): max |dD|/max D {worst_all:.2e}, star rel {worst_star:.2e}, "
             f"all fields {max(fields.values()):.2e} ({ {k: float('%.1e' % v) for k, v in fields.items()} })")
+    out["oracle_s"] = el
+    out["steps"] = len(sub["dts"])
     cells = sum(b.nx * b.ny * b.nz for b in sub["init"])
-    out["oracle_zone_updates_per_s"] = cells * len(sub["dts"]) / el
+    out["oracle_zone_updates_per_s"] = cells * len(sub["dts"]) * len(meshes) / el
     log(f"c5 oracle: {len(sub['dts'])} steps of {len(sub['init'])} blocks in {el:.1f} s")
     return out
 
@@ -739,6 +800,10 @@ def main():
                     help="skip the reconstruction / RK3 / matter-source measurements on the star")
     ap.add_argument("--c5-only", action="store_true", help="only the end-to-end section (+ its oracle check)")
     ap.add_argument("--c5-steps", type=int, default=100)
+    ap.add_argument("--c5-check-steps", type=int, default=2,
+                    help="steps of the refined-mesh oracle check (whole 8^3-block mesh)")
+    ap.add_argument("--c5-frozen", action="store_true",
+                    help="also the end-to-end run on the independent block list with frozen ghosts")
     ap.add_argument("--host-inputs", action="store_true",
                     help="build the star's initial data on the host (counter passes)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -773,7 +838,7 @@ def main():
         print(json.dumps({"refined": refined_section(args, torch, inputs, lib)}), flush=True)
         return
     if args.c5_only:
-        res, sub = c5_section(args, torch, inputs, lib)
+        res, sub = c5_section(args, torch, inputs, lib, amr=not args.c5_frozen)
         if not args.no_cpu_baseline:
             res["oracle_check"] = c5_oracle_check(sub)
         print(json.dumps({"end_to_end": res}), flush=True)
@@ -807,14 +872,18 @@ def main():
     if not args.no_c2p:
         out["c2p"] = c2p_section(args, torch, inputs, lib)
         out["c2p_hybrid_eos"] = c2p_section(args, torch, inputs, lib, eos="hybrid")
-    c5_sub = None
+    c5_sub = c5f_sub = None
     if not args.no_c5:
-        out["end_to_end"], c5_sub = c5_section(args, torch, inputs, lib)
+        out["end_to_end"], c5_sub = c5_section(args, torch, inputs, lib, amr=True)
+        if args.c5_frozen:
+            out["end_to_end_frozen"], c5f_sub = c5_section(args, torch, inputs, lib, amr=False)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(star["st"], args.blocks_per_side, args.block, STAR_PARAMS)
         if c5_sub is not None:
             out["end_to_end"]["oracle_check"] = c5_oracle_check(c5_sub)
+        if c5f_sub is not None:
+            out["end_to_end_frozen"]["oracle_check"] = c5_oracle_check(c5f_sub)
     print(json.dumps(out), flush=True)
 
 

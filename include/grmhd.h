@@ -188,71 +188,6 @@ int grmhd_stage_c2p(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t 
 int grmhd_ghost_fill(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
                      int32_t mask, void *stream);
 
-/* ---------------------------------------------------------------------------
-   Refined meshes: the inter-level transfer of block-based mesh refinement
-   (Sec. I; prolongation and restriction are among the costs of Sec. V-A).
-   The blocks are the leaves of a 2:1-balanced octree of equal blocks
-   (nx = ny = nz = nb, nb even, nb >= 2 ng + 2): refinement by 2, and any two
-   leaves that touch across a face, an edge or a corner differ by at most one
-   level.  A ghost cell or face takes its value from the leaf that covers it:
-   a same-level leaf: a copy; a finer leaf: the mean of the 8 child cells
-   (flags: their OR) or of the 4 child faces on the face's plane; a coarser
-   leaf: the parent cell plus, per axis, a quarter of its minmod-limited slope
-   signed towards the child (flags: the parent's), for a face on a parent
-   face that face's value and for a face inside a parent cell the mean of
-   that cell's two faces along the normal (each child cell then has its
-   parent's divergence).  Where two leaves hold a face, the one within the
-   block's own range along the face's normal is read first.  Outflow
-   boundaries take the nearest cell (face) of the domain; periodic ones wrap.
-   In a stage the fluxes of a block's boundary faces next to a finer leaf are
-   the mean of the 4 fine fluxes (conservation), and its boundary edge EMFs
-   next to a finer leaf the mean of the 2 fine EMFs along the edge (div B~ at
-   round-off, and every leaf around such an edge uses the same EMF).  One dt
-   for every level.
-   ------------------------------------------------------------------------- */
-#define GRMHD_AMR_NONE (-9)   /* rel[] of a region beyond an outflow boundary */
-
-typedef struct {
-  int32_t level;       /* refinement level (cell size dx0 / 2^level)                 */
-  int32_t org[3];      /* global index, at its level, of the block's first interior cell */
-  int32_t N[3];        /* cells of the domain per axis at its level                    */
-  int32_t periodic;    /* bit a set: axis a periodic, else outflow                    */
-  int32_t rel[27];     /* per neighbour region (ox+1)+3(oy+1)+9(oz+1), ng+1 cells deep
-                          (the block's own interior for 13): the level of the leaves
-                          covering it minus this block's, -1, 0 or 1; GRMHD_AMR_NONE
-                          beyond an outflow boundary                                  */
-  int32_t src[27][4];  /* the leaves covering each region (block indices, -1 unused)  */
-} grmhd_amr_link;
-
-/* Host: the links of nblk leaves (level[i], org[3 i .. 3 i + 2]) of blocks of
-   nb^3 cells with ng ghosts on a domain of n0[3] level-0 cells with
-   periodic[3] (1 periodic, 0 outflow); links: nblk entries written.
-   GRMHD_EINVAL for sizes out of range (nb odd or < 2 ng + 2, a leaf outside
-   the domain or off its level's nb lattice), overlapping leaves, a region
-   covered by no leaf or by leaves of different levels or of a level more
-   than one apart, or more than 4 leaves in a region. */
-int grmhd_amr_links(int32_t nblk, const int32_t *level, const int32_t *org, int32_t nb,
-                    int32_t ng, const int32_t n0[3], const int32_t periodic[3],
-                    grmhd_amr_link *links);
-
-/* Ghost fill across levels of the w (mask 1), us (2), bs (4) and flags (8)
-   slots of a refined mesh: copies and restrictions first, then the
-   prolongations level by level upwards (the parent's slope may read the
-   parent leaf's ghosts).  links_h / links_d: the same grmhd_amr_link array
-   in host / device memory.  GRMHD_EINVAL for unequal block sizes or a block
-   with bc != 1. */
-int grmhd_ghost_fill_amr(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
-                         const grmhd_amr_link *links_h, const grmhd_amr_link *links_d,
-                         int32_t mask, void *stream);
-
-/* One stage on a refined mesh: the steps of grmhd_stage with the flag
-   exchange across levels, the flux correction after the FOFC refluxing and
-   the EMF correction between the corner EMFs and the face update. */
-int grmhd_stage_amr(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
-                    const grmhd_amr_link *links_h, const grmhd_amr_link *links_d,
-                    const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
-                    double b, void *stream);
-
 /* Step a9: dt_out[0] = cfl / max over interior cells and directions of
    |lambda_+-| / dx_d from the w and bs slots (fast magnetosonic speeds).
    red: device scratch of one double (overwritten).  GRMHD_EINVAL for a NULL
@@ -496,6 +431,72 @@ int grmhd_copy(const double *src, double *dst, int64_t n, void *stream);
 /* sizeof of the ABI structs (0 grmhd_params, 1 grmhd_block, 2 c2p_mlp,
    3 c2p_stats; -1 otherwise), so bindings can check their layouts. */
 int32_t grmhd_struct_size(int32_t which);
+
+/* ---------------------------------------------------------------------------
+   Refined meshes: the inter-level transfer of block-based mesh refinement
+   (Sec. I; prolongation and restriction are among the costs of Sec. V-A).
+   The blocks are the leaves of a 2:1-balanced octree of equal blocks
+   (nx = ny = nz = nb, nb even, nb >= 2 ng + 2): refinement by 2, and any two
+   leaves that touch across a face, an edge or a corner differ by at most one
+   level.  A ghost cell or face takes its value from the leaf that covers it:
+   a same-level leaf: a copy; a finer leaf: the mean of the 8 child cells
+   (flags: their OR) or of the 4 child faces on the face's plane; a coarser
+   leaf: the parent cell plus, per axis, a quarter of its minmod-limited slope
+   signed towards the child (flags: the parent's), for a face on a parent
+   face that face's value and for a face inside a parent cell the mean of
+   that cell's two faces along the normal (each child cell then has its
+   parent's divergence).  Where two leaves hold a face, the one within the
+   block's own range along the face's normal is read first.  Outflow
+   boundaries take the nearest cell (face) of the domain; periodic ones wrap.
+   In a stage the fluxes of a block's boundary faces next to a finer leaf are
+   the mean of the 4 fine fluxes (conservation), and its boundary edge EMFs
+   next to a finer leaf the mean of the 2 fine EMFs along the edge (div B~ at
+   round-off, and every leaf around such an edge uses the same EMF).  One dt
+   for every level.
+   ------------------------------------------------------------------------- */
+#define GRMHD_AMR_NONE (-9)   /* rel[] of a region beyond an outflow boundary */
+
+typedef struct {
+  int32_t level;       /* refinement level (cell size dx0 / 2^level)                 */
+  int32_t org[3];      /* global index, at its level, of the block's first interior cell */
+  int32_t N[3];        /* cells of the domain per axis at its level                    */
+  int32_t periodic;    /* bit a set: axis a periodic, else outflow                    */
+  int32_t rel[27];     /* per neighbour region (ox+1)+3(oy+1)+9(oz+1), ng+1 cells deep
+                          (the block's own interior for 13): the level of the leaves
+                          covering it minus this block's, -1, 0 or 1; GRMHD_AMR_NONE
+                          beyond an outflow boundary                                  */
+  int32_t src[27][4];  /* the leaves covering each region (block indices, -1 unused)  */
+} grmhd_amr_link;
+
+/* Host: the links of nblk leaves (level[i], org[3 i .. 3 i + 2]) of blocks of
+   nb^3 cells with ng ghosts on a domain of n0[3] level-0 cells with
+   periodic[3] (1 periodic, 0 outflow); links: nblk entries written.
+   GRMHD_EINVAL for sizes out of range (nb odd or < 2 ng + 2, a leaf outside
+   the domain or off its level's nb lattice), overlapping leaves, a region
+   covered by no leaf or by leaves of different levels or of a level more
+   than one apart, or more than 4 leaves in a region. */
+int grmhd_amr_links(int32_t nblk, const int32_t *level, const int32_t *org, int32_t nb,
+                    int32_t ng, const int32_t n0[3], const int32_t periodic[3],
+                    grmhd_amr_link *links);
+
+/* Ghost fill across levels of the w (mask 1), us (2), bs (4) and flags (8)
+   slots of a refined mesh: copies and restrictions first, then the
+   prolongations level by level upwards (the parent's slope may read the
+   parent leaf's ghosts).  links_h / links_d: the same grmhd_amr_link array
+   in host / device memory.  GRMHD_EINVAL for unequal block sizes or a block
+   with bc != 1. */
+int grmhd_ghost_fill_amr(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                         const grmhd_amr_link *links_h, const grmhd_amr_link *links_d,
+                         int32_t mask, void *stream);
+
+/* One stage on a refined mesh: the steps of grmhd_stage_learned (mlp and
+   stats optional, as there) with the flag exchange across levels, the flux
+   correction after the FOFC refluxing and the EMF correction between the
+   corner EMFs and the face update. */
+int grmhd_stage_amr(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                    const grmhd_amr_link *links_h, const grmhd_amr_link *links_d,
+                    const grmhd_params *p, const double *dt_d, double dt, double a0, double a1,
+                    double b, const c2p_mlp *mlp, c2p_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1200,26 +1200,99 @@ static int amr_cell_axis(const or_amr *amr, int lvl, int a, int I) {
   return I < 0 ? 0 : N - 1;
 }
 
-/* the leaf that covers global cell I (inside the domain) of level lvl */
-static int find_leaf(const or_block *blks, int nblk, const or_amr *amr, int lvl, const int I[3]) {
+/* Lookup of the leaf that covers a cell.  The definition is a search over
+   all leaves (find_leaf_search); where every leaf has one size nb, a table
+   per level of the leaves on that level's lattice of nb-blocks answers the
+   same question in a few probes (a cell is covered by at most one leaf).
+   The table is built by each public entry point of the refined mesh and
+   released on return. */
+static struct {
+  int on, nb, maxlvl;
+  int32_t nbk[32][3];
+  int32_t *tab[32];
+} g_leafidx;
+static int g_leafidx_use = 1;   /* test instrument: 0 searches every time */
+void or_set_leaf_index(int on) { g_leafidx_use = on; }
+
+static int leaf_contains(const or_block *blks, const or_amr *amr, int ib, int lvl, const int I[3]) {
+  const int L = amr->level[ib];
+  const int n[3] = {blks[ib].nx, blks[ib].ny, blks[ib].nz};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t lo = (int64_t)amr->org[3 * ib + a], hi = lo + n[a];
+    /* the cell's extent in leaf-level indices: [c0, c1) */
+    int64_t c0, c1;
+    if (L >= lvl) {
+      c0 = (int64_t)I[a] << (L - lvl);
+      c1 = c0 + ((int64_t)1 << (L - lvl));
+    } else {
+      c0 = (int64_t)I[a] >> (lvl - L);
+      c1 = c0 + 1;
+    }
+    if (!(c0 >= lo && c1 <= hi)) return 0;
+  }
+  return 1;
+}
+
+static int find_leaf_search(const or_block *blks, int nblk, const or_amr *amr, int lvl, const int I[3]) {
+  for (int ib = 0; ib < nblk; ++ib)
+    if (leaf_contains(blks, amr, ib, lvl, I)) return ib;
+  return -1;
+}
+
+static void leaf_index_build(const or_block *blks, int nblk, const or_amr *amr) {
+  g_leafidx.on = 0;
+  if (!g_leafidx_use) return;
+  const int nb = blks[0].nx;
+  int maxlvl = 0;
+  for (int ib = 0; ib < nblk; ++ib) {
+    if (blks[ib].nx != nb || blks[ib].ny != nb || blks[ib].nz != nb) return;
+    if (amr->level[ib] > maxlvl) maxlvl = amr->level[ib];
+    for (int a = 0; a < 3; ++a)
+      if (amr->org[3 * ib + a] % nb) return;
+  }
+  if (maxlvl >= 32) return;
+  for (int a = 0; a < 3; ++a)
+    if (amr->n0[a] % nb) return;
+  g_leafidx.nb = nb;
+  g_leafidx.maxlvl = maxlvl;
+  for (int L = 0; L <= maxlvl; ++L) {
+    int64_t cnt = 1;
+    for (int a = 0; a < 3; ++a) {
+      g_leafidx.nbk[L][a] = (amr->n0[a] << L) / nb;
+      cnt *= g_leafidx.nbk[L][a];
+    }
+    g_leafidx.tab[L] = (int32_t *)malloc((size_t)cnt * sizeof(int32_t));
+    for (int64_t x = 0; x < cnt; ++x) g_leafidx.tab[L][x] = -1;
+  }
   for (int ib = 0; ib < nblk; ++ib) {
     const int L = amr->level[ib];
-    const int n[3] = {blks[ib].nx, blks[ib].ny, blks[ib].nz};
-    int in = 1;
-    for (int a = 0; a < 3 && in; ++a) {
-      const int64_t lo = (int64_t)amr->org[3 * ib + a], hi = lo + n[a];
-      /* the cell's extent in leaf-level indices: [c0, c1) */
-      int64_t c0, c1;
-      if (L >= lvl) {
-        c0 = (int64_t)I[a] << (L - lvl);
-        c1 = c0 + ((int64_t)1 << (L - lvl));
-      } else {
-        c0 = (int64_t)I[a] >> (lvl - L);
-        c1 = c0 + 1;
-      }
-      in = c0 >= lo && c1 <= hi;
+    const int32_t *nk = g_leafidx.nbk[L];
+    const int bx = amr->org[3 * ib] / nb, by = amr->org[3 * ib + 1] / nb, bz = amr->org[3 * ib + 2] / nb;
+    g_leafidx.tab[L][((int64_t)bz * nk[1] + by) * nk[0] + bx] = ib;
+  }
+  g_leafidx.on = 1;
+}
+
+static void leaf_index_free(void) {
+  if (!g_leafidx.on) return;
+  for (int L = 0; L <= g_leafidx.maxlvl; ++L) free(g_leafidx.tab[L]);
+  g_leafidx.on = 0;
+}
+
+/* the leaf that covers global cell I (inside the domain) of level lvl */
+static int find_leaf(const or_block *blks, int nblk, const or_amr *amr, int lvl, const int I[3]) {
+  if (!g_leafidx.on) return find_leaf_search(blks, nblk, amr, lvl, I);
+  const int nb = g_leafidx.nb;
+  for (int L = 0; L <= g_leafidx.maxlvl; ++L) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t J = L >= lvl ? ((int64_t)I[a] << (L - lvl)) : ((int64_t)I[a] >> (lvl - L));
+      c[a] = (int)(J / nb);
     }
-    if (in) return ib;
+    const int32_t *nk = g_leafidx.nbk[L];
+    if (c[0] >= nk[0] || c[1] >= nk[1] || c[2] >= nk[2]) continue;
+    const int ib = g_leafidx.tab[L][((int64_t)c[2] * nk[1] + c[1]) * nk[0] + c[0]];
+    if (ib >= 0 && leaf_contains(blks, amr, ib, lvl, I)) return ib;
   }
   return -1;
 }
@@ -1410,11 +1483,23 @@ static void amr_fill_faces(or_block *blks, int nblk, const or_amr *amr, int ib, 
       }
 }
 
+static int ghost_fill_amr_body(or_block *blks, int nblk, int mask, const or_amr *amr);
 int or_ghost_fill_amr(or_block *blks, int nblk, int mask, const or_amr *amr) {
+  const int own = !g_leafidx.on;
+  if (own) leaf_index_build(blks, nblk, amr);
+  const int r = ghost_fill_amr_body(blks, nblk, mask, amr);
+  if (own) leaf_index_free();
+  return r;
+}
+
+static int ghost_fill_amr_body(or_block *blks, int nblk, int mask, const or_amr *amr) {
   int maxlvl = 0;
   for (int ib = 0; ib < nblk; ++ib)
     if (amr->level[ib] > maxlvl) maxlvl = amr->level[ib];
+  /* within a pass each block writes its own ghosts and reads only what an
+     earlier pass (or no pass) wrote: the blocks of a pass are independent */
   for (int pass = 0; pass <= maxlvl; ++pass)
+#pragma omp parallel for schedule(dynamic)
     for (int ib = 0; ib < nblk; ++ib) {
       if (blks[ib].bc == 0) continue;
       if (pass > 0 && amr->level[ib] != pass) continue;
@@ -1428,6 +1513,10 @@ int or_ghost_fill_amr(or_block *blks, int nblk, int mask, const or_amr *amr) {
 /* flux correction: each boundary face of a block next to a finer leaf takes
    the mean of that leaf's 4 fluxes there (all 7 components) */
 static void amr_flux_correct(or_block *blks, int nblk, const or_amr *amr, double **Fall) {
+  /* each block writes its own boundary values; the finer leaves' values it
+     reads are never written here (a leaf next to a finer one is not next to
+     a coarser one across the same face or edge) */
+#pragma omp parallel for schedule(dynamic)
   for (int ib = 0; ib < nblk; ++ib) {
     or_block *b = &blks[ib];
     const int lv = amr->level[ib], g = b->ng;
@@ -1477,6 +1566,10 @@ static void amr_flux_correct(or_block *blks, int nblk, const or_amr *amr, double
    around the edge lies in a finer leaf takes the mean of that leaf's 2 EMFs
    along the edge.  Eall[3 * ib + c]: block ib's edge array of component c. */
 static void amr_emf_correct(or_block *blks, int nblk, const or_amr *amr, double **Eall) {
+  /* each block writes its own boundary values; the finer leaves' values it
+     reads are never written here (a leaf next to a finer one is not next to
+     a coarser one across the same face or edge) */
+#pragma omp parallel for schedule(dynamic)
   for (int ib = 0; ib < nblk; ++ib) {
     or_block *b = &blks[ib];
     const int lv = amr->level[ib], g = b->ng;
@@ -2069,6 +2162,7 @@ int or_stage(or_block *blks, int nblk, const or_params *p, double dt, double a0,
    the face update) at level boundaries. */
 int or_stage_amr(or_block *blks, int nblk, const or_params *p, double dt, double a0, double a1,
                  double bb, const or_amr *amr) {
+  leaf_index_build(blks, nblk, amr);
   double **F = alloc_fluxes(blks, nblk);
   if (g_tscale_u || g_tscale_b) g_tscale_f = alloc_fluxes(blks, nblk);
   or_fluxes(blks, nblk, p, F);
@@ -2109,6 +2203,7 @@ int or_stage_amr(or_block *blks, int nblk, const or_params *p, double dt, double
     free_fluxes(g_tscale_f, nblk);
     g_tscale_f = NULL;
   }
+  leaf_index_free();
   return 0;
 }
 

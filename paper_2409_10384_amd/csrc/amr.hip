@@ -70,6 +70,25 @@ __device__ __forceinline__ void amr_axis(const grmhd_amr_link& lk, const Geo& q,
   I = G;
 }
 
+// block and item of this thread for launch shape cls over the blocks
+// b0..b1 of the list (a contiguous range: the leaves of one level), as
+// locate() does over the whole list
+__device__ __forceinline__ bool locate_range(const grmhd_block* __restrict__ blks, int cls, int b0,
+                                             int b1, int& bi, int64_t& t) {
+  const int64_t g = (int64_t)xcd_linear() * blockDim.x + threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane((int)(g >> 6)) + blks[b0].wave0[cls];
+  int lo = b0, hi = b1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blks[mid].wave0[cls] <= w) lo = mid; else hi = mid - 1;
+  }
+  bi = lo;
+  const Geo q = geo_of(blks[bi]);
+  if (bi == b1 && w >= blks[b1].wave0[cls] + (int)((shape_items(q, cls) + 63) >> 6)) return false;
+  t = (int64_t)(w - blks[bi].wave0[cls]) * 64 + (threadIdx.x & 63);
+  return t < shape_items(q, cls);
+}
+
 __device__ __forceinline__ double minmod2(double a, double b) {
   if (a * b <= 0.0) return 0.0;
   return fabs(a) < fabs(b) ? a : b;
@@ -105,11 +124,11 @@ __device__ __forceinline__ double prolong(const grmhd_amr_link& ls, const Geo& q
 // parent's, which is an interior cell).
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_cells_amr(
     const grmhd_block* __restrict__ blks, const grmhd_amr_link* __restrict__ L, int mask, int list,
-    int pass) {
+    int pass, int b0, int b1) {
   int ib;
   int64_t t;
   const int cls = list ? S_GSHELL : S_GCELLS;
-  if (!locate(blks, cls, ib, t)) return;
+  if (!locate_range(blks, cls, b0, b1, ib, t)) return;
   const grmhd_amr_link& lk = L[ib];
   if (pass > 0 && lk.level != pass) return;
   const GB b = gview(blks[ib]);
@@ -192,10 +211,11 @@ __device__ __forceinline__ double leaf_face(const grmhd_block& bs, const grmhd_a
 // Ghost faces of direction d (launch shape S_GXFACE + d); passes as for the
 // cells.
 __global__ __launch_bounds__(kMaxThreads) void k_ghost_faces_amr(
-    const grmhd_block* __restrict__ blks, const grmhd_amr_link* __restrict__ L, int d, int pass) {
+    const grmhd_block* __restrict__ blks, const grmhd_amr_link* __restrict__ L, int d, int pass,
+    int b0, int b1) {
   int ib;
   int64_t t;
-  if (!locate(blks, S_GXFACE + d, ib, t)) return;
+  if (!locate_range(blks, S_GXFACE + d, b0, b1, ib, t)) return;
   const grmhd_amr_link& lk = L[ib];
   if (pass > 0 && lk.level != pass) return;
   const Geo q = geo_of(blks[ib]);
@@ -470,17 +490,49 @@ int amr_check(const grmhd_block* h, const grmhd_amr_link* lh, int nblk) {
   return GRMHD_OK;
 }
 
-void launch_ghost_cells_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
-                            const grmhd_amr_link* ld, int mask, int list, int pass,
-                            unsigned grid, int threads, hipStream_t s) {
-  (void)h;
-  (void)nblk;
-  k_ghost_cells_amr<<<grid, threads, 0, s>>>(d, ld, mask, list, pass);
+// the blocks of pass `pass` (all for pass <= 0; the leaves of that level
+// for pass > 0, a contiguous range when the list is ordered by level, else
+// all of them) and the workgroups covering their items of shape cls
+static bool pass_range(const grmhd_block* h, const grmhd_amr_link* lh, int nblk, int pass, int cls,
+                       int threads, int& b0, int& b1, unsigned& grid) {
+  b0 = 0;
+  b1 = nblk - 1;
+  if (pass > 0) {
+    int first = -1, last = -1, count = 0;
+    for (int i = 0; i < nblk; ++i)
+      if (lh[i].level == pass) {
+        if (first < 0) first = i;
+        last = i;
+        ++count;
+      }
+    if (count == 0) return false;
+    if (last - first + 1 == count) {
+      b0 = first;
+      b1 = last;
+    }
+  }
+  const int64_t waves = (int64_t)h[b1].wave0[cls] + (shape_items(geo_of(h[b1]), cls) + 63) / 64 -
+                        h[b0].wave0[cls];
+  grid = (unsigned)((waves * 64 + threads - 1) / threads);
+  return waves > 0;
 }
 
-void launch_ghost_faces_amr(const grmhd_block* d, const grmhd_amr_link* ld, int dir, int pass,
-                            unsigned grid, int threads, hipStream_t s) {
-  k_ghost_faces_amr<<<grid, threads, 0, s>>>(d, ld, dir, pass);
+void launch_ghost_cells_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
+                            const grmhd_amr_link* lh, const grmhd_amr_link* ld, int mask, int list,
+                            int pass, int threads, hipStream_t s) {
+  int b0, b1;
+  unsigned grid;
+  if (!pass_range(h, lh, nblk, pass, list ? S_GSHELL : S_GCELLS, threads, b0, b1, grid)) return;
+  k_ghost_cells_amr<<<grid, threads, 0, s>>>(d, ld, mask, list, pass, b0, b1);
+}
+
+void launch_ghost_faces_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
+                            const grmhd_amr_link* lh, const grmhd_amr_link* ld, int dir, int pass,
+                            int threads, hipStream_t s) {
+  int b0, b1;
+  unsigned grid;
+  if (!pass_range(h, lh, nblk, pass, S_GXFACE + dir, threads, b0, b1, grid)) return;
+  k_ghost_faces_amr<<<grid, threads, 0, s>>>(d, ld, dir, pass, b0, b1);
 }
 
 void launch_amr_flux_fix(const grmhd_block* d, const grmhd_amr_link* ld, int nblk, int nb,

@@ -23,10 +23,11 @@ namespace gk {
 int amr_max_level(const grmhd_amr_link* h, int nblk);
 int amr_check(const grmhd_block* h, const grmhd_amr_link* lh, int nblk);
 void launch_ghost_cells_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
-                            const grmhd_amr_link* ld, int mask, int list, int pass,
-                            unsigned grid, int threads, hipStream_t s);
-void launch_ghost_faces_amr(const grmhd_block* d, const grmhd_amr_link* ld, int dir, int pass,
-                            unsigned grid, int threads, hipStream_t s);
+                            const grmhd_amr_link* lh, const grmhd_amr_link* ld, int mask, int list,
+                            int pass, int threads, hipStream_t s);
+void launch_ghost_faces_amr(const grmhd_block* h, const grmhd_block* d, int nblk,
+                            const grmhd_amr_link* lh, const grmhd_amr_link* ld, int dir, int pass,
+                            int threads, hipStream_t s);
 void launch_amr_flux_fix(const grmhd_block* d, const grmhd_amr_link* ld, int nblk, int nb,
                          hipStream_t s);
 void launch_amr_emf_fix(const grmhd_block* d, const grmhd_amr_link* ld, int nblk, int nb,
@@ -1371,10 +1372,12 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
   });
 }
 
-// links (device): a refined mesh, whose flag exchange crosses levels
+// links / links_h (device / host): a refined mesh, whose flag exchange
+// crosses levels
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
               const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
-              hipStream_t s, const grmhd_amr_link* links = nullptr) {
+              hipStream_t s, const grmhd_amr_link* links = nullptr,
+              const grmhd_amr_link* links_h = nullptr) {
   k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
   if (!p.fofc) return;
   {
@@ -1387,8 +1390,7 @@ void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_
   for (int i = 0; i < nblk; ++i) exchange = exchange || h[i].bc == 1;
   if (links) {
     TIMED(T_GHOST, s);
-    launch_ghost_cells_amr(h, d, nblk, links, 8, 1, -1, grid_cls(h, nblk, S_GSHELL, tpb(T_GHOST)).x,
-                           tpb(T_GHOST), s);
+    launch_ghost_cells_amr(h, d, nblk, links_h, links, 8, 1, -1, tpb(T_GHOST), s);
   } else if (exchange) {
     TIMED(T_GHOST, s);
     k_ghost_cells<<<grid_cls(h, nblk, S_GSHELL, tpb(T_GHOST)), tpb(T_GHOST), 0, s>>>(d, 8, 1);
@@ -1741,12 +1743,10 @@ int grmhd_ghost_fill_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int
   // copies and restrictions (pass 0), then the prolongations level by level
   for (int pass = 0; pass <= top; ++pass) {
     if (mask & 11)
-      launch_ghost_cells_amr(blk_h, blk_d, nblk, links_d, mask & 11, 0, pass,
-                             grid_cls(blk_h, nblk, S_GCELLS, tpb(T_GHOST)).x, tpb(T_GHOST), s);
+      launch_ghost_cells_amr(blk_h, blk_d, nblk, links_h, links_d, mask & 11, 0, pass, tpb(T_GHOST), s);
     if (mask & 4)
       for (int d = 0; d < 3; ++d)
-        launch_ghost_faces_amr(blk_d, links_d, d, pass,
-                               grid_cls(blk_h, nblk, S_GXFACE + d, tpb(T_GHOST)).x, tpb(T_GHOST), s);
+        launch_ghost_faces_amr(blk_h, blk_d, nblk, links_h, links_d, d, pass, tpb(T_GHOST), s);
   }
   return last_err();
 }
@@ -1754,19 +1754,28 @@ int grmhd_ghost_fill_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int
 int grmhd_stage_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
                     const grmhd_amr_link* links_h, const grmhd_amr_link* links_d,
                     const grmhd_params* p, const double* dt_d, double dt, double a0, double a1,
-                    double b, void* stream) {
+                    double b, const c2p_mlp* mlp, c2p_stats* stats, void* stream) {
   int r = check_params(p);
   if (r) return r;
   if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
   if (!links_d) return GRMHD_EINVAL;
   if ((r = amr_check(blk_h, links_h, nblk))) return r;
+  if (mlp && (!mlp->w_bf16 || !mlp->w_f32)) return GRMHD_EINVAL;
   const Eos e = make_eos(*p);
   hipStream_t s = (hipStream_t)stream;
   run_fluxes(blk_h, blk_d, nblk, *p, e, s);
-  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, links_d);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, links_d, links_h);
   launch_amr_flux_fix(blk_d, links_d, nblk, blk_h[0].nx, s);
   run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s, links_d);
-  run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s, true);
+  if (mlp) {
+    run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s);
+    if ((r = launch_stage_c2p_learned(blk_h, blk_d, nblk, *p, mlp, stats, s))) return r;
+  } else if (stats) {
+    run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s);
+    run_c2p(blk_h, blk_d, nblk, *p, e, s, stats);
+  } else {
+    run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s, true);
+  }
   return last_err();
 }
 

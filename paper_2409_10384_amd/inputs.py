@@ -712,3 +712,38 @@ def smooth_leaf_blocks(mesh: LeafMesh, ng=3, seed_offset=7, amp_rho=0.1, amp_p=0
                              [np.ascontiguousarray(b) for b in (Bx, By, Bz)], np.ascontiguousarray(adm),
                              [-1] * 27, 1, lv, tuple(org[a] * h for a in range(3))))
     return out
+
+
+def star_leaf_mesh(nblocks0=4, nb=32, half=48.0, radii=(28.0, 14.0, 8.0)):
+    """A leaf mesh about the star at the origin on [-half, half]^3 (outflow
+    boundaries): a level-0 leaf of level l < len(radii) is split while its
+    box comes within radii[l] of the centre, then 2:1-balanced."""
+    h0 = 2.0 * half / (nblocks0 * nb)
+
+    def refine(lv, b):
+        if lv >= len(radii):
+            return False
+        side = nb * h0 / 2 ** lv
+        lo = [-half + b[a] * side for a in range(3)]
+        d2 = sum(max(lo[a], 0.0, -(lo[a] + side)) ** 2 for a in range(3))
+        return d2 < radii[lv] ** 2
+
+    m = leaf_mesh((nblocks0,) * 3, nb, refine=refine, max_level=len(radii), periodic=(0, 0, 0))
+    return m, h0
+
+
+def star_leaf_blocks(st: StarSetup | None = None, nblocks0=4, nb=32, ng=3, half=48.0,
+                     radii=(28.0, 14.0, 8.0), device=None):
+    """The star (StarSetup) sampled on every leaf of star_leaf_mesh, ghosts
+    included; returns (blocks, leaf mesh, star setup)."""
+    st = st or calibrate_field(StarSetup())
+    backend = _TorchBackend(device) if device is not None else None
+    m, h0 = star_leaf_mesh(nblocks0, nb, half, radii)
+    blocks = []
+    for i, (lv, b) in enumerate(m.leaves):
+        h = h0 / 2 ** lv
+        o = m.org(i)
+        w, bf, adm = _star_block_arrays(st, o[0], o[1], o[2], nb, ng, h, -half, backend)
+        blocks.append(BlockInit(nb, nb, nb, ng, (h, h, h), w, bf, adm, [-1] * 27, 1, lv,
+                                tuple(-half + o[a] * h for a in range(3))))
+    return blocks, m, st

@@ -125,7 +125,7 @@ def load():
                                      vp, vp, vp]
     L.grmhd_amr_links.argtypes = [C.c_int32, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.grmhd_ghost_fill_amr.argtypes = blk + [vp, vp, C.c_int32, vp]
-    L.grmhd_stage_amr.argtypes = blk + [vp, vp] + stage[3:]
+    L.grmhd_stage_amr.argtypes = blk + [vp, vp] + stage[3:-1] + [vp, vp, vp]
     _lib = L
     return L
 
@@ -670,13 +670,16 @@ class RefinedDeviceMesh(DeviceMesh):
         return C.cast(self.links, C.c_void_p), C.c_void_p(self.links_dev.data_ptr())
 
     def stage_sets(self, src, dst, coef, dt=None, dt_dev=None, mlp=None, stats=None):
-        if mlp is not None or stats is not None:
-            raise GrmhdError("the refined-mesh stage has the plain inversion only")
         a0, a1, b = coef
         dptr = C.c_void_p(dt_dev.data_ptr()) if dt_dev is not None else None
         dval = float(dt) if dt is not None else 0.0
+        mptr = None
+        if mlp is not None:
+            self._mlp_keep = mlp.c()
+            mptr = C.byref(self._mlp_keep)
+        sptr = C.c_void_p(stats.data_ptr()) if stats is not None else None
         check(load().grmhd_stage_amr(*self._args((src, dst)), *self._links(), C.byref(self.params.c()),
-                                     dptr, dval, a0, a1, b, self.sp()), "grmhd_stage_amr")
+                                     dptr, dval, a0, a1, b, mptr, sptr, self.sp()), "grmhd_stage_amr")
 
     def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
         check(load().grmhd_ghost_fill_amr(*self._args((which, which)), *self._links(), mask, self.sp()),

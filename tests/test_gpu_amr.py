@@ -168,3 +168,22 @@ def test_device_steps_conserve_and_keep_div_b_across_levels(G):
     assert np.all(dtot < 2e-15), dtot
     assert divb < 1e-14
     assert worst < 1e-11
+
+
+STAR_P = O.Params(gamma=2.0, rho_atm=1.28e-13, T_atm=1.28e-11, f_thr=0.1, M_max=100.0, fofc=1,
+                  dmp_M=1.1)
+
+
+def test_star_on_a_leaf_mesh_stage_parity(G):
+    """the star on the leaf mesh of the end-to-end run (levels 0-3 refined
+    towards the centre, outflow edges), 8^3 blocks: both RK2 stages at 1e-12
+    from a common input, the star's surface crossing level boundaries"""
+    blocks, m, st = inputs.star_leaf_blocks(nb=8)
+    say(f"star on a leaf mesh: {len(m.leaves)} leaves of 8^3, levels {sorted(set(m.levels))}")
+    om = O.RefinedMesh(copy.deepcopy(blocks), STAR_P, m)
+    gm = G.RefinedDeviceMesh(copy.deepcopy(blocks), to_mp(G, STAR_P), m)
+    om.ghost_fill_state(0)
+    dt = om.dt(0.25)
+    summary = SP.stage_parity(gm, om, O.Mesh.RK2, dt, tol=1e-12, margin=1e-9, say=say, upload=_upload,
+                              download=_download)
+    assert len(summary) == 2

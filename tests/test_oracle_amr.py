@@ -413,3 +413,28 @@ def test_uniform_state_stays_uniform_across_levels():
         w = om.interior(om.w0[ib], ib)
         for v, ref in enumerate((1.0, 0.3, -0.2, 0.1, 0.5)):
             assert np.abs(w[v] - ref).max() < 1e-14, (ib, v)
+
+
+def test_leaf_lookup_table_answers_as_the_search():
+    """the per-level lookup table of the leaves gives the search's answer:
+    ghost fills and a stage bit for bit the same with it and without it"""
+    refine = lambda lv, b: b == (0, 0, 0)
+    m = inputs.leaf_mesh((2, 2, 2), 8, refine=refine, max_level=2, periodic=(1, 0, 1))
+    blocks = inputs.smooth_leaf_blocks(m)
+    p = O.Params(gamma=5.0 / 3.0, fofc=1, dmp_M=1.0)
+    runs = []
+    for use in (1, 0):
+        O.lib().or_set_leaf_index(use)
+        try:
+            om = O.RefinedMesh(copy.deepcopy(blocks), p, m)
+            om.ghost_fill_state(0)
+            om.rk2_step(cfl=0.3)
+        finally:
+            O.lib().or_set_leaf_index(1)
+        runs.append(om)
+    a, b = runs
+    for ib in range(len(blocks)):
+        np.testing.assert_array_equal(a.u0[ib], b.u0[ib])
+        np.testing.assert_array_equal(a.w0[ib], b.w0[ib])
+        for d in range(3):
+            np.testing.assert_array_equal(a.b0[ib][d], b.b0[ib][d])
