@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-A 5-64-64-64-2 multilayer perceptron with SiLU activations maps five
+A 5-64-64-64-2 multilayer perceptron with hard-swish activations maps five
 invariants of a conserved state to an initial guess and a bracket half-width
 for the root mu = 1/(hW) of the Kastaun master function.  The root solve
 itself is unchanged and always finishes, so the network only decides where
@@ -33,13 +33,14 @@ SIZES = [(64, 5), (64, 64), (64, 64), (2, 64)]
 LOG_ERR_C = 1e-4
 
 
-def silu(z):
-    return z / (1.0 + np.exp(-z))
+def act(z):
+    """hard-swish (Howard et al. 2019): z clamp(z / 6 + 1/2, 0, 1)"""
+    return z * np.clip(z / 6.0 + 0.5, 0.0, 1.0)
 
 
-def dsilu(z):
-    s = 1.0 / (1.0 + np.exp(-z))
-    return s * (1.0 + z * (1.0 - s))
+def dact(z):
+    """its derivative: 0 below -3, 1 above 3, z / 3 + 1/2 between"""
+    return np.where(z <= -3.0, 0.0, np.where(z >= 3.0, 1.0, z / 3.0 + 0.5))
 
 
 def features(D, q, r2, b2, s):
@@ -71,7 +72,7 @@ def forward(params, x):
         z = h @ W.T + b
         pre.append(z)
         if li < len(params) - 1:
-            h = silu(z)
+            h = act(z)
             acts.append(h)
         else:
             h = z
@@ -97,7 +98,7 @@ def backward(params, cache, dy):
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]
         if li < len(params) - 1:
-            g = g * dsilu(pre[li])
+            g = g * dact(pre[li])
         dW = g.T @ acts[li]
         db = g.sum(axis=0)
         grads[li] = [dW, db]

@@ -375,7 +375,7 @@ struct TrainLds {
   MlpLds w;
   uint16_t x0[64 * kLdIn];
   uint16_t h[3][64 * kLdH];     // h1, h2, h3 (bf16)
-  float d[3][64 * 64];          // SiLU'(z_l), then the fp32 gradient g_l in place
+  float d[3][64 * 64];          // act'(z_l), then the fp32 gradient g_l in place
   uint16_t ga[64 * kLdH];       // bf16 copies of g_l for the MFMA (ping-pong)
   uint16_t gb[64 * kLdH];
   float y[64 * 2];
@@ -408,7 +408,7 @@ __device__ __forceinline__ void grad_w(const uint16_t* G, const uint16_t* X, int
     }
 }
 
-// dX[r][i] = sum_o G[r][o] W[o][i] (M = r, N = i, K = o), times SiLU'(z) in
+// dX[r][i] = sum_o G[r][o] W[o][i] (M = r, N = i, K = o), times act'(z) in
 // place into d (fp32), bf16 copy into gnext
 __device__ __forceinline__ void grad_x(const uint16_t* G, const uint16_t* W, float* d,
                                        uint16_t* gnext) {
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t nbatch, const float* f
 #pragma unroll
   for (int c = 0; c < 16; ++c) s.x0[l * kLdIn + c] = c < 5 ? f2bf(feats[c * nbatch + t]) : (uint16_t)0;
   __syncthreads();
-  // forward, keeping SiLU'(z) for each hidden layer
+  // forward, keeping act'(z) for each hidden layer
 #pragma unroll 1
   for (int mt = 0; mt < 4; ++mt) {
     mlp_hidden<1>(s.x0 + mt * 16 * kLdIn, kLdIn, s.w.W1, kLdIn, s.w.b1, s.h[0] + mt * 16 * kLdH,
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t nbatch, const float* f
     if (l == 0 && loss_part) loss_part[blockIdx.x] = ls;
   }
   __syncthreads();
-  // output layer in fp32 (two outputs): dW4, db4 and dh3 = dy0 W4[0], g3 = dh3 * SiLU'(z3)
+  // output layer in fp32 (two outputs): dW4, db4 and dh3 = dy0 W4[0], g3 = dh3 * act'(z3)
   {
     // dW4[o][i] = sum_r dy[r][o] h3[r][i]; lane l owns column i = l
     float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(64) void k_mlp_train(int64_t nbatch, const float* f
     }
   }
   __syncthreads();
-  // layer 3: dW3 = g3^T h2, db3, g2 = (g3 W3) * SiLU'(z2)
+  // layer 3: dW3 = g3^T h2, db3, g2 = (g3 W3) * act'(z2)
   grad_w<4>(s.ga, s.h[1], kLdH, pg + kOffW3, 64);
   grad_b(s.d[2], pg + kOffB3);
   grad_x(s.ga, s.w.W3, s.d[1], s.gb);

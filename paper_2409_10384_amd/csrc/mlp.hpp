@@ -1,5 +1,5 @@
 // mlp.hpp -- device pieces of the learned C2P guess network (not in the paper):
-// a 5-64-64-64-2 perceptron with SiLU, bf16 operands on the MFMA units with
+// a 5-64-64-64-2 perceptron with hard-swish activations, bf16 operands on the MFMA units with
 // fp32 accumulation.
 //
 // Parameter vector (fp32 master copy and bf16 copy share this layout):
@@ -32,15 +32,15 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// logistic function with the hardware exp and reciprocal (relative error a
-// few ulp of fp32, far below the bf16 rounding of the activations)
-__device__ __forceinline__ float sigmoid_f(float z) {
-  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+// hard-swish activation (Howard et al. 2019), z clamp(z / 6 + 1/2, 0, 1):
+// one fused multiply-add with a clamp to [0, 1] and one multiply, where a
+// logistic-based activation needs an exponential and a reciprocal (quarter
+// rate) per neuron, which would cost several times the matrix products
+__device__ __forceinline__ float act_f(float z) {
+  return z * __builtin_amdgcn_fmed3f(fmaf(z, 1.0f / 6.0f, 0.5f), 0.0f, 1.0f);
 }
-__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
-__device__ __forceinline__ float dsilu_f(float z) {
-  const float s = sigmoid_f(z);
-  return s * (1.0f + z * (1.0f - s));
+__device__ __forceinline__ float dact_f(float z) {
+  return z <= -3.0f ? 0.0f : (z >= 3.0f ? 1.0f : fmaf(z, 1.0f / 3.0f, 0.5f));
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -94,9 +94,9 @@ __device__ __forceinline__ void mlp_load(MlpLds& s, const uint16_t* wh, const fl
   if (threadIdx.x < 2) s.b4[threadIdx.x] = wf[kOffB4 + threadIdx.x];
 }
 
-// One hidden layer on a 16-row tile: out = SiLU(in W^T + b), in [16][ld_in]
+// One hidden layer on a 16-row tile: out = act(in W^T + b), in [16][ld_in]
 // with KT k-steps of 16, out [16][kLdH] (64 columns).  Optionally keeps the
-// pre-activation derivative SiLU'(z) (fp32 [16][64]) for the backward pass.
+// pre-activation derivative act'(z) (fp32 [16][64]) for the backward pass.
 template <int KT>
 __device__ __forceinline__ void mlp_hidden(const uint16_t* in, int ld_in, const uint16_t* W, int ldw,
                                            const float* bias, uint16_t* out, float* dz) {
@@ -116,8 +116,8 @@ __device__ __forceinline__ void mlp_hidden(const uint16_t* in, int ld_in, const 
     for (int e = 0; e < 4; ++e) {
       const int row = 4 * q + e;
       const float z = acc[e] + bias[col];
-      out[row * kLdH + col] = f2bf(silu_f(z));
-      if (dz) dz[row * 64 + col] = dsilu_f(z);
+      out[row * kLdH + col] = f2bf(act_f(z));
+      if (dz) dz[row * 64 + col] = dact_f(z);
     }
   }
 }
@@ -153,12 +153,12 @@ __device__ __forceinline__ void mlp_out(const uint16_t* in, const uint16_t* W4, 
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 
-// SiLU of an MFMA output fragment (bias already in the accumulator), packed
-// to bf16 two values per conversion
-__device__ __forceinline__ bf16x4 silu_frag(f32x4 acc) {
+// activation of an MFMA output fragment (bias already in the accumulator),
+// packed to bf16 two values per conversion
+__device__ __forceinline__ bf16x4 act_frag(f32x4 acc) {
   f32x4 h;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) h[e] = silu_f(acc[e]);
+  for (int e = 0; e < 4; ++e) h[e] = act_f(acc[e]);
   return __builtin_bit_cast(bf16x4, __builtin_convertvector(h, bf16x4v));
 }
 
@@ -192,7 +192,7 @@ __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], floa
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = bias_frag(w.b1 + nt * 16 + 4 * q);
       acc = mfma16(ld4(w.W1 + (nt * 16 + r) * kLdIn + 4 * q), xb, acc);
-      h1[nt] = silu_frag(acc);
+      h1[nt] = act_frag(acc);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -200,7 +200,7 @@ __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], floa
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = mfma16(ld4(w.W2 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h1[ks], acc);
-      h2[nt] = silu_frag(acc);
+      h2[nt] = act_frag(acc);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -208,7 +208,7 @@ __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], floa
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
         acc = mfma16(ld4(w.W3 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h2[ks], acc);
-      h1[nt] = silu_frag(acc);
+      h1[nt] = act_frag(acc);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll

@@ -59,9 +59,16 @@ def family(kname):
     return FAMILY_OF_BASE.get(base)
 
 
+# the sources the kernels of the plain RK step are compiled from (the
+# learned inversion, the network and the refined-mesh transfer are not in it)
+STEP_SOURCES = ("grmhd.hip", "physics.hpp", "blocks.hpp", "timing.hpp")
+
+
 def source_hash():
+    """hash of the step kernels' sources: counter summaries taken on other
+    sources are stale"""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+    for f in STEP_SOURCES:
         h.update(open(os.path.join(HERE, "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -1,17 +1,25 @@
 """Pins of the FP64 MLP oracle: backward against central finite differences,
-SiLU derivative closed form, Adam's bias-corrected first step, and the
+the hard-swish activation and its derivative, Adam's bias-corrected first step, and the
 bracket map."""
 import numpy as np
 
 from oracle import mlp as M
 
 
-def test_silu_derivative_closed_form():
-    z = np.linspace(-8, 8, 101)
+def test_hard_swish_and_its_derivative():
+    """z clamp(z/6 + 1/2, 0, 1): 0 below -3, the identity above 3, the
+    parabola z (z + 3) / 6 between; the derivative against central
+    differences away from the two kinks"""
+    z = np.linspace(-8, 8, 1601)
+    z = z[(np.abs(z - 3) > 1e-3) & (np.abs(z + 3) > 1e-3)]
     h = 1e-6
-    fd = (M.silu(z + h) - M.silu(z - h)) / (2 * h)
-    np.testing.assert_allclose(M.dsilu(z), fd, rtol=1e-8, atol=1e-10)
-    assert M.silu(0.0) == 0.0
+    fd = (M.act(z + h) - M.act(z - h)) / (2 * h)
+    np.testing.assert_allclose(M.dact(z), fd, rtol=1e-8, atol=1e-9)
+    assert M.act(0.0) == 0.0 and M.act(3.0) == 3.0 and M.act(-3.0) == 0.0
+    mid = z[np.abs(z) < 3]
+    np.testing.assert_allclose(M.act(mid), mid * (mid + 3.0) / 6.0, rtol=1e-15, atol=1e-16)
+    np.testing.assert_array_equal(M.act(z[z > 3]), z[z > 3])
+    np.testing.assert_array_equal(M.act(z[z < -3]), 0.0 * z[z < -3])
 
 
 def test_backward_matches_finite_differences():
