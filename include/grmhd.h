@@ -261,6 +261,16 @@ int c2p_batch(int64_t n, double *u[5], double *const bt[3], double *const gam[6]
               uint16_t *flags, const grmhd_params *p, const c2p_mlp *mlp, c2p_stats *stats,
               double *mu_out, int32_t *nev_out, void *stream);
 
+/* grmhd_stage whose dt is the CFL time step of its input (step a9 folded
+   into the stage's first kernel, which reads that state anyway): dt_out[0] =
+   cfl / max over interior cells and directions of |lambda_+-| / dx_d, the
+   value grmhd_dt gives, bit for bit; the stage then runs with it.  red: device
+   scratch of one double.  For the first stage of a step (its input is the
+   step's state).  GRMHD_EINVAL as for grmhd_dt and grmhd_stage. */
+int grmhd_stage_cfl(const grmhd_block *blk_h, const grmhd_block *blk_d, int32_t nblk,
+                    const grmhd_params *p, double cfl, double *red, double *dt_out, double a0,
+                    double a1, double b, void *stream);
+
 /* grmhd_stage with the stage's final inversion (step a8) started from the
    learned bracket (mlp != NULL; NULL = the plain inversion of grmhd_stage).
    Same outputs and atmosphere rules; a bracket that holds no sign change is
@@ -375,10 +385,10 @@ typedef struct grmhd_rk2_tables {
   const grmhd_block *ba_h, *ba_d;
 } grmhd_rk2_tables;
 
-/* One step: dt_out = CFL dt of set A (grmhd_dt, red its scratch double),
-   stage 1 (0, 1, 1) with that device dt, ghost fill of set B, stage 2
-   (1/2, 1/2, 1/2), ghost fill of set A (w, U, faces).  Asynchronous; errors
-   as for the calls it makes. */
+/* One step: stage 1 (0, 1, 1) with dt_out = the CFL dt of set A computed in
+   that stage (grmhd_stage_cfl, red its scratch double), ghost fill of set B,
+   stage 2 (1/2, 1/2, 1/2) with the device dt, ghost fill of set A (w, U,
+   faces).  Asynchronous; errors as for the calls it makes. */
 int grmhd_rk2_step(const grmhd_rk2_tables *t, int32_t nblk, const grmhd_params *p, double cfl,
                    double *red, double *dt_out, void *stream);
 

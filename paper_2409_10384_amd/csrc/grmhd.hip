@@ -41,14 +41,86 @@ constexpr int kMaxThreads = 512;   // stage kernels: runtime workgroup size up t
 
 
 // ---------------------------------------------------------------------------
+// a9 pieces: the CFL speed of one interior cell (the largest |lambda_+-|/dx
+// over the three directions, Eq. 7-9 fast speeds of the slot w and the face
+// average of bs), the wave maximum, and the workgroup maximum folded into
+// *red (non-negative doubles order like their bit patterns: exact, order-
+// independent)
+// ---------------------------------------------------------------------------
+__global__ void k_zero1(double* x) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = 0.0;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double cfl_speed(const Eos& e, const GB& b, const Geo& q, int i, int j,
+                                            int k) {
+  const int64_t c = cell(q, i, j, k);
+  M3 m;
+  cell_metric(b, c, m);
+  const double beta[3] = {b.adm[1][c], b.adm[2][c], b.adm[3][c]};
+  double w[5], Bt[3];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[v] = b.w[v][c];
+  cell_bt(q, b.bs, i, j, k, Bt);
+  const double is = 1.0 / m.sg;
+  const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+  const double al = b.adm[0][c];
+  Side sd;
+  double s = 0.0;
+  side_state<0>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[0]);
+  side_state<1>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[1]);
+  side_state<2>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[2]);
+  return s;
+}
+
+// every thread of the workgroup calls this (it holds a barrier)
+__device__ __forceinline__ void workgroup_max_into(double s, double* red) {
+  s = wave_max(s);
+  __shared__ double part[kMaxThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = part[0];
+    for (int x = 1; x < (int)(blockDim.x >> 6); ++x) r = fmax(r, part[x]);
+    atomicMax((unsigned long long*)red, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a1: cell-centred un-densitized field B^i = B~_cc / sqrt(gamma), all cells
 // ---------------------------------------------------------------------------
 // and, on cells [g-1, g+n]^3, the cell-centre EMF E = -alpha (vhat x B~) of
 // the stage input (the reference value of the upwind corner EMFs of a5)
-__global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restrict__ blks) {
+// With DT (the first stage of a step with device dt), the same pass also
+// folds the CFL speed of every interior cell into *red (a9): the stage input
+// it reads is the state the step's dt is taken from.
+template <int ET, bool DT>
+__global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restrict__ blks, Eos e_in,
+                                                    double* red) {
   int bi;
   int64_t t;
-  if (!locate(blks, S_CELLS, bi, t)) return;
+  const bool live = locate(blks, S_CELLS, bi, t);
+  if (DT) {
+    // no early return before the workgroup reduction
+    double sp = 0.0;
+    if (live) {
+      const GB b = gview(blks[bi]);
+      const Geo q = geo_of(b);
+      const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
+      if (i >= q.g && j >= q.g && k >= q.g && i < q.g + q.nx && j < q.g + q.ny && k < q.g + q.nz)
+        sp = cfl_speed(eos_fixed<ET>(e_in), b, q, i, j, k);
+    }
+    workgroup_max_into(sp, red);
+  }
+  if (!live) return;
   const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
@@ -985,17 +1057,8 @@ __global__ __launch_bounds__(kThreads) void k_c2p_pairs(const grmhd_block* __res
 }
 
 // ---------------------------------------------------------------------------
-// a9: dt reduction (max of |lambda|/dx; order-independent, exact)
+// a9: dt reduction (max of |lambda|/dx; order-independent, exact), alone
 // ---------------------------------------------------------------------------
-__global__ void k_zero1(double* x) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = 0.0;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <int ET>
 __global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restrict__ blks, Eos e_in,
@@ -1011,35 +1074,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_dt(const grmhd_block* __restric
     const Box bx = interior_box(q);
     int i, j, k;
     bx.at(t, i, j, k);
-    const int64_t c = cell(q, i, j, k);
-    M3 m;
-    cell_metric(b, c, m);
-    const double beta[3] = {b.adm[1][c], b.adm[2][c], b.adm[3][c]};
-    double w[5], Bt[3];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) w[v] = b.w[v][c];
-    cell_bt(q, b.bs, i, j, k, Bt);
-    const double is = 1.0 / m.sg;
-    const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
-    const double al = b.adm[0][c];
-    Side sd;
-    side_state<0>(e, m, al, beta, w, B, sd);
-    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[0]);
-    side_state<1>(e, m, al, beta, w, B, sd);
-    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[1]);
-    side_state<2>(e, m, al, beta, w, B, sd);
-    s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[2]);
+    s = cfl_speed(e, b, q, i, j, k);
   }
-  s = wave_max(s);
-  __shared__ double part[kMaxThreads / 64];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = part[0];
-    for (int x = 1; x < (int)(blockDim.x >> 6); ++x) r = fmax(r, part[x]);
-    // non-negative doubles order like their bit patterns
-    atomicMax((unsigned long long*)red, (unsigned long long)__double_as_longlong(r));
-  }
+  workgroup_max_into(s, red);
 }
 
 __global__ void k_dt_final(const double* red, double cfl, double* dt_out) {
@@ -1339,12 +1376,23 @@ unsigned batch_grid(int64_t n) {
 }
 
 // the steps; validation is done by the public entry points
+// red, dt_out (device): the first stage of a step with device dt, whose CFL
+// reduction rides on the field kernel; dt_out = cfl / max speed before the
+// fluxes (the stage reads it from the FOFC trial state on)
 void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
-                const Eos& e, hipStream_t s) {
-  {
+                const Eos& e, hipStream_t s, double* red = nullptr, double cfl = 0.0,
+                double* dt_out = nullptr) {
+  if (red) {
+    k_zero1<<<1, 64, 0, s>>>(red);
     TIMED(T_BCC, s);
-    k_bcc<<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d);
+    eos_dispatch(e.type, [&](auto et) {
+      k_bcc<decltype(et)::value, true><<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d, e, red);
+    });
+  } else {
+    TIMED(T_BCC, s);
+    k_bcc<0, false><<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d, e, nullptr);
   }
+  if (red) k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
   {
     TIMED(T_FLUX_X, s);
     eos_dispatch(e.type, [&](auto et) {
@@ -1655,6 +1703,22 @@ int grmhd_stage(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk
   return grmhd_stage_learned(blk_h, blk_d, nblk, p, dt_d, dt, a0, a1, b, nullptr, nullptr, stream);
 }
 
+int grmhd_stage_cfl(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
+                    const grmhd_params* p, double cfl, double* red, double* dt_out, double a0,
+                    double a1, double b, void* stream) {
+  if (!red || !dt_out || !(cfl > 0.0)) return GRMHD_EINVAL;
+  int r = check_params(p);
+  if (r) return r;
+  if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
+  const Eos e = make_eos(*p);
+  hipStream_t s = (hipStream_t)stream;
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s, red, cfl, dt_out);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_out, 0.0, a0, a1, b, s);
+  run_ct(blk_h, blk_d, nblk, dt_out, 0.0, a0, a1, b, s);
+  run_update(blk_h, blk_d, nblk, e, *p, dt_out, 0.0, a0, a1, b, s, true);
+  return last_err();
+}
+
 int grmhd_stage_learned(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t nblk,
                         const grmhd_params* p, const double* dt_d, double dt, double a0,
                         double a1, double b, const c2p_mlp* mlp, c2p_stats* stats, void* stream) {
@@ -1946,9 +2010,10 @@ int grmhd_c2p_pairs(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t 
 int grmhd_rk2_step(const grmhd_rk2_tables* t, int32_t nblk, const grmhd_params* p, double cfl,
                    double* red, double* dt_out, void* stream) {
   if (!t) return GRMHD_EINVAL;
-  int r = grmhd_dt(t->a_h, t->a_d, nblk, p, cfl, red, dt_out, stream);
-  if (r) return r;
-  if ((r = grmhd_stage(t->ab_h, t->ab_d, nblk, p, dt_out, 0.0, 0.0, 1.0, 1.0, stream))) return r;
+  int r;
+  // the CFL dt of set A, reduced in the first stage's field kernel
+  if ((r = grmhd_stage_cfl(t->ab_h, t->ab_d, nblk, p, cfl, red, dt_out, 0.0, 1.0, 1.0, stream)))
+    return r;
   if ((r = grmhd_ghost_fill(t->b_h, t->b_d, nblk, 7, stream))) return r;
   if ((r = grmhd_stage(t->ba_h, t->ba_d, nblk, p, dt_out, 0.0, 0.5, 0.5, 0.5, stream))) return r;
   return grmhd_ghost_fill(t->a_h, t->a_d, nblk, 7, stream);

@@ -92,6 +92,8 @@ def load():
         getattr(L, name).argtypes = stage
     L.grmhd_fluxes.argtypes = blk + [C.c_void_p, C.c_void_p]
     L.grmhd_stage_c2p.argtypes = blk + [C.c_void_p, C.c_void_p]
+    L.grmhd_stage_cfl.argtypes = blk + [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_double,
+                                        C.c_double, C.c_double, C.c_void_p]
     L.grmhd_stage_learned.argtypes = stage[:-1] + [C.c_void_p, C.c_void_p, C.c_void_p]
     L.grmhd_stage_c2p_learned.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.grmhd_matter_sources.argtypes = blk + [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -442,6 +444,19 @@ class DeviceMesh:
                                        a1, b, C.byref(self._mlp_keep), sptr, self.sp())
         check(rc, "grmhd_stage")
 
+    def stage_cfl(self, src, dst, coef, cfl):
+        """one stage whose dt is the CFL dt of its input, reduced in the
+        stage's first kernel (grmhd_stage_cfl); dt left in self.dt_dev"""
+        a0, a1, b = coef
+        check(load().grmhd_stage_cfl(*self._args((src, dst)), C.byref(self.params.c()), float(cfl),
+                                     C.c_void_p(self.red.data_ptr()), C.c_void_p(self.dt_dev.data_ptr()),
+                                     a0, a1, b, self.sp()), "grmhd_stage_cfl")
+        return self.dt_dev
+
+    # the first stage of a device-dt step takes its dt from grmhd_stage_cfl
+    # (plain inversion, one-level mesh); else from grmhd_dt before it
+    fused_dt = True
+
     def ghost_fill(self, which, mask=GF_W | GF_US | GF_BS):
         """ghosts of state set which (0 A, 1 B, 2 C)"""
         check(load().grmhd_ghost_fill(*self._args((which, which)), mask, self.sp()),
@@ -459,13 +474,18 @@ class DeviceMesh:
         """One step of `scheme` (RK2 or RK3); dt from the device CFL reduction
         when dt is None; the ghosts of each stage's output are filled before
         the next stage; mlp/stats as for stage()."""
+        fused = dt is None and self.fused_dt and mlp is None and stats is None
         if dt is None:
-            self.compute_dt(cfl)
+            if not fused:
+                self.compute_dt(cfl)
             kw = dict(dt_dev=self.dt_dev)
         else:
             kw = dict(dt=dt)
-        for src, dst, coef in scheme:
-            self.stage_sets(src, dst, coef, mlp=mlp, stats=stats, **kw)
+        for k, (src, dst, coef) in enumerate(scheme):
+            if fused and k == 0:
+                self.stage_cfl(src, dst, coef, cfl)
+            else:
+                self.stage_sets(src, dst, coef, mlp=mlp, stats=stats, **kw)
             if self.alpha_excise > 0.0:
                 self.excise(dst, self.alpha_excise)
             self.ghost_fill(dst)
@@ -656,6 +676,8 @@ class RefinedDeviceMesh(DeviceMesh):
     of paper_2409_10384_amd.inputs, blocks in its leaf order): ghost fills
     across levels (grmhd_ghost_fill_amr) and stages with the flux and EMF
     corrections at level boundaries (grmhd_stage_amr)."""
+
+    fused_dt = False
 
     def __init__(self, blocks, params: MethodParams, leafmesh, device="cuda", stream=None):
         b0 = blocks[0]
