@@ -101,8 +101,9 @@ __device__ __forceinline__ void workgroup_max_into(double s, double* red) {
 // the stage input (the reference value of the upwind corner EMFs of a5)
 // With DT (the first stage of a step with device dt), the same pass also
 // folds the CFL speed of every interior cell into *red (a9): the stage input
-// it reads is the state the step's dt is taken from.
-template <int ET, bool DT>
+// it reads is the state the step's dt is taken from.  With CLR (a whole
+// stage) it also clears the cell flags and the FOFC list of the stage.
+template <int ET, bool DT, bool CLR>
 __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restrict__ blks, Eos e_in,
                                                     double* red) {
   int bi;
@@ -123,6 +124,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
   if (!live) return;
   const GB b = gview(blks[bi]);
   const Geo q = geo_of(b);
+  if (CLR) {
+    b.flags[t] = 0;
+    if (t == 0) *fofc_count(b, q) = 0u;
+  }
   const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
   // face i+1 exists for every cell of the padded block
   M3 m;
@@ -1379,18 +1384,27 @@ unsigned batch_grid(int64_t n) {
 // red, dt_out (device): the first stage of a step with device dt, whose CFL
 // reduction rides on the field kernel; dt_out = cfl / max speed before the
 // fluxes (the stage reads it from the FOFC trial state on)
+// clear: a whole stage (the field kernel also clears the flags and the FOFC
+// list; run_fofc is then told so)
 void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
                 const Eos& e, hipStream_t s, double* red = nullptr, double cfl = 0.0,
-                double* dt_out = nullptr) {
+                double* dt_out = nullptr, bool clear = false) {
+  const dim3 gb = grid_cls(h, nblk, S_CELLS, tpb(T_BCC));
   if (red) {
     k_zero1<<<1, 64, 0, s>>>(red);
     TIMED(T_BCC, s);
     eos_dispatch(e.type, [&](auto et) {
-      k_bcc<decltype(et)::value, true><<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d, e, red);
+      if (clear)
+        k_bcc<decltype(et)::value, true, true><<<gb, tpb(T_BCC), 0, s>>>(d, e, red);
+      else
+        k_bcc<decltype(et)::value, true, false><<<gb, tpb(T_BCC), 0, s>>>(d, e, red);
     });
   } else {
     TIMED(T_BCC, s);
-    k_bcc<0, false><<<grid_cls(h, nblk, S_CELLS, tpb(T_BCC)), tpb(T_BCC), 0, s>>>(d, e, nullptr);
+    if (clear)
+      k_bcc<0, false, true><<<gb, tpb(T_BCC), 0, s>>>(d, e, nullptr);
+    else
+      k_bcc<0, false, false><<<gb, tpb(T_BCC), 0, s>>>(d, e, nullptr);
   }
   if (red) k_dt_final<<<1, 64, 0, s>>>(red, cfl, dt_out);
   {
@@ -1422,11 +1436,13 @@ void run_fluxes(const grmhd_block* h, const grmhd_block* d, int nblk, const grmh
 
 // links / links_h (device / host): a refined mesh, whose flag exchange
 // crosses levels
+// cleared: the flags and the FOFC list were cleared by the field kernel
 void run_fofc(const grmhd_block* h, const grmhd_block* d, int nblk, const grmhd_params& p,
               const Eos& e, const double* dt_d, double dt, double a0, double a1, double b,
               hipStream_t s, const grmhd_amr_link* links = nullptr,
-              const grmhd_amr_link* links_h = nullptr) {
-  k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
+              const grmhd_amr_link* links_h = nullptr, bool cleared = false) {
+  if (!cleared)
+    k_clear_flags<<<grid_cls(h, nblk, S_CELLS, tpb(T_FOFC_FLAGS)), tpb(T_FOFC_FLAGS), 0, s>>>(d);
   if (!p.fofc) return;
   {
     TIMED(T_FOFC_FLAGS, s);
@@ -1712,8 +1728,8 @@ int grmhd_stage_cfl(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t 
   if ((r = check_blocks(blk_h, blk_d, nblk))) return r;
   const Eos e = make_eos(*p);
   hipStream_t s = (hipStream_t)stream;
-  run_fluxes(blk_h, blk_d, nblk, *p, e, s, red, cfl, dt_out);
-  run_fofc(blk_h, blk_d, nblk, *p, e, dt_out, 0.0, a0, a1, b, s);
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s, red, cfl, dt_out, true);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_out, 0.0, a0, a1, b, s, nullptr, nullptr, true);
   run_ct(blk_h, blk_d, nblk, dt_out, 0.0, a0, a1, b, s);
   run_update(blk_h, blk_d, nblk, e, *p, dt_out, 0.0, a0, a1, b, s, true);
   return last_err();
@@ -1728,8 +1744,8 @@ int grmhd_stage_learned(const grmhd_block* blk_h, const grmhd_block* blk_d, int3
   if (mlp && (!mlp->w_bf16 || !mlp->w_f32)) return GRMHD_EINVAL;
   const Eos e = make_eos(*p);
   hipStream_t s = (hipStream_t)stream;
-  run_fluxes(blk_h, blk_d, nblk, *p, e, s);
-  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s);
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s, nullptr, 0.0, nullptr, true);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, nullptr, nullptr, true);
   run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s);
   if (mlp) {
     run_update(blk_h, blk_d, nblk, e, *p, dt_d, dt, a0, a1, b, s);
@@ -1827,8 +1843,8 @@ int grmhd_stage_amr(const grmhd_block* blk_h, const grmhd_block* blk_d, int32_t 
   if (mlp && (!mlp->w_bf16 || !mlp->w_f32)) return GRMHD_EINVAL;
   const Eos e = make_eos(*p);
   hipStream_t s = (hipStream_t)stream;
-  run_fluxes(blk_h, blk_d, nblk, *p, e, s);
-  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, links_d, links_h);
+  run_fluxes(blk_h, blk_d, nblk, *p, e, s, nullptr, 0.0, nullptr, true);
+  run_fofc(blk_h, blk_d, nblk, *p, e, dt_d, dt, a0, a1, b, s, links_d, links_h, true);
   launch_amr_flux_fix(blk_d, links_d, nblk, blk_h[0].nx, s);
   run_ct(blk_h, blk_d, nblk, dt_d, dt, a0, a1, b, s, links_d);
   if (mlp) {
