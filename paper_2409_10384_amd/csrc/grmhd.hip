@@ -57,6 +57,20 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+__device__ __forceinline__ double cfl_speed_of(const Eos& e, const M3& m, double al,
+                                               const double beta[3], const double w[5],
+                                               const double B[3], const double dx[3]) {
+  Side sd;
+  double s = 0.0;
+  side_state<0>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / dx[0]);
+  side_state<1>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / dx[1]);
+  side_state<2>(e, m, al, beta, w, B, sd);
+  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / dx[2]);
+  return s;
+}
+
 __device__ __forceinline__ double cfl_speed(const Eos& e, const GB& b, const Geo& q, int i, int j,
                                             int k) {
   const int64_t c = cell(q, i, j, k);
@@ -69,16 +83,7 @@ __device__ __forceinline__ double cfl_speed(const Eos& e, const GB& b, const Geo
   cell_bt(q, b.bs, i, j, k, Bt);
   const double is = 1.0 / m.sg;
   const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
-  const double al = b.adm[0][c];
-  Side sd;
-  double s = 0.0;
-  side_state<0>(e, m, al, beta, w, B, sd);
-  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[0]);
-  side_state<1>(e, m, al, beta, w, B, sd);
-  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[1]);
-  side_state<2>(e, m, al, beta, w, B, sd);
-  s = fmax(s, fmax(fabs(sd.lm), fabs(sd.lp)) / b.dx[2]);
-  return s;
+  return cfl_speed_of(e, m, b.adm[0][c], beta, w, B, b.dx);
 }
 
 // every thread of the workgroup calls this (it holds a barrier)
@@ -108,53 +113,53 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
                                                     double* red) {
   int bi;
   int64_t t;
+  // no early return before the workgroup reduction of DT
   const bool live = locate(blks, S_CELLS, bi, t);
-  if (DT) {
-    // no early return before the workgroup reduction
-    double sp = 0.0;
-    if (live) {
-      const GB b = gview(blks[bi]);
-      const Geo q = geo_of(b);
-      const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
-      if (i >= q.g && j >= q.g && k >= q.g && i < q.g + q.nx && j < q.g + q.ny && k < q.g + q.nz)
-        sp = cfl_speed(eos_fixed<ET>(e_in), b, q, i, j, k);
+  double sp = 0.0;
+  if (live) {
+    const GB b = gview(blks[bi]);
+    const Geo q = geo_of(b);
+    if (CLR) {
+      b.flags[t] = 0;
+      if (t == 0) *fofc_count(b, q) = 0u;
     }
-    workgroup_max_into(sp, red);
+    const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
+    // face i+1 exists for every cell of the padded block
+    M3 m;
+    cell_metric(b, t, m);
+    double Bt[3];
+    cell_bt(q, b.bs, i, j, k, Bt);
+    gptr<double> out = b.scratch + off_bcc(q);
+    const int64_t nc = n_cells(q);
+    const double is = 1.0 / m.sg;
+    out[t] = Bt[0] * is;
+    out[nc + t] = Bt[1] * is;
+    out[2 * nc + t] = Bt[2] * is;
+    const int g1 = q.g - 1;
+    if (i >= g1 && j >= g1 && k >= g1 && i <= q.g + q.nx && j <= q.g + q.ny && k <= q.g + q.nz) {
+      const double al = b.adm[0][t];
+      const double beta[3] = {b.adm[1][t], b.adm[2][t], b.adm[3][t]};
+      const double ux = b.w[1][t], uy = b.w[2][t], uz = b.w[3][t];
+      double lx, ly, lz;
+      lower(m.g, ux, uy, uz, lx, ly, lz);
+      const double iW = 1.0 / sqrt(1.0 + ux * lx + uy * ly + uz * lz);
+      const double ia = 1.0 / al;
+      const double vx = ux * iW - beta[0] * ia;
+      const double vy = uy * iW - beta[1] * ia;
+      const double vz = uz * iW - beta[2] * ia;
+      gptr<double> E = b.scratch + off_ecc(q);
+      E[t] = -al * (vy * Bt[2] - vz * Bt[1]);
+      E[nc + t] = -al * (vz * Bt[0] - vx * Bt[2]);
+      E[2 * nc + t] = -al * (vx * Bt[1] - vy * Bt[0]);
+      if (DT && i >= q.g && j >= q.g && k >= q.g && i < q.g + q.nx && j < q.g + q.ny &&
+          k < q.g + q.nz) {
+        const double w[5] = {b.w[0][t], ux, uy, uz, b.w[4][t]};
+        const double B[3] = {Bt[0] * is, Bt[1] * is, Bt[2] * is};
+        sp = cfl_speed_of(eos_fixed<ET>(e_in), m, al, beta, w, B, b.dx);
+      }
+    }
   }
-  if (!live) return;
-  const GB b = gview(blks[bi]);
-  const Geo q = geo_of(b);
-  if (CLR) {
-    b.flags[t] = 0;
-    if (t == 0) *fofc_count(b, q) = 0u;
-  }
-  const int i = (int)(t % q.sx), j = (int)((t / q.sx) % q.sy), k = (int)(t / ((int64_t)q.sx * q.sy));
-  // face i+1 exists for every cell of the padded block
-  M3 m;
-  cell_metric(b, t, m);
-  double Bt[3];
-  cell_bt(q, b.bs, i, j, k, Bt);
-  gptr<double> out = b.scratch + off_bcc(q);
-  const int64_t nc = n_cells(q);
-  const double is = 1.0 / m.sg;
-  out[t] = Bt[0] * is;
-  out[nc + t] = Bt[1] * is;
-  out[2 * nc + t] = Bt[2] * is;
-  const int g1 = q.g - 1;
-  if (i < g1 || j < g1 || k < g1 || i > q.g + q.nx || j > q.g + q.ny || k > q.g + q.nz) return;
-  const double al = b.adm[0][t];
-  const double ux = b.w[1][t], uy = b.w[2][t], uz = b.w[3][t];
-  double lx, ly, lz;
-  lower(m.g, ux, uy, uz, lx, ly, lz);
-  const double iW = 1.0 / sqrt(1.0 + ux * lx + uy * ly + uz * lz);
-  const double ia = 1.0 / al;
-  const double vx = ux * iW - b.adm[1][t] * ia;
-  const double vy = uy * iW - b.adm[2][t] * ia;
-  const double vz = uz * iW - b.adm[3][t] * ia;
-  gptr<double> E = b.scratch + off_ecc(q);
-  E[t] = -al * (vy * Bt[2] - vz * Bt[1]);
-  E[nc + t] = -al * (vz * Bt[0] - vx * Bt[2]);
-  E[2 * nc + t] = -al * (vx * Bt[1] - vy * Bt[0]);
+  if (DT) workgroup_max_into(sp, red);
 }
 
 // ---------------------------------------------------------------------------
