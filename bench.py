@@ -64,8 +64,10 @@ def kernel_bytes(family, blocks):
             # per face: normal field in, 7 flux components out
             tot += 8 * (17 * box + 8 * faces)
         elif family == "update":
-            # U^n 5, U^(s) 5, w 5, B~ 3, ADM 16, flux divergence 15 in; U 5 out
-            tot += 8 * 54 * cells_in
+            # the stage's update with the inversion in its tail: U^n 5,
+            # U^(s) 5, w 5, B~ of the stage input 3, ADM 16, flux divergence
+            # 15, B~ of the updated faces 3 in; U 5, w 5 out; flag in/out
+            tot += 8 * 62 * cells_in + 4 * cells_in
         elif family == "fofc_flags":
             # U^n 5, U^(s) 5, B~ 3, metric 6, fluxes 15 in; flag out
             tot += 8 * 34 * cells_in + 2 * cells_in

@@ -227,8 +227,9 @@ int prim2con(int64_t n, double *const w[5], double *const bt[3], double *const g
              double *u[5], const grmhd_params *p, void *stream);
 
 /* Learned guess and bracket for the inversion (not in the paper): a
-   5-64-64-64-2 perceptron with SiLU on standardised invariants of the scaled
-   state (log10 D, log10(1+q), r/(1+q), b^2/(1+q), s^2/(r^2 b^2)).  Output y0
+   5-64-64-64-2 perceptron with hard-swish activations, z clamp(z/6 + 1/2, 0, 1),
+   on standardised invariants of the scaled state (log10 D, log10(1+q),
+   r/(1+q), b^2/(1+q), s^2/(r^2 b^2)).  Output y0
    estimates logit(mu), y1 the log of the expected |logit error|; the bracket
    is logistic(y0 -+ (width_k exp(y1) + width_min)).  Parameters are one flat
    vector of C2P_MLP_NPARAM values, row-major [out][in] per layer:
