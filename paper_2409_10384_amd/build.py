@@ -15,13 +15,14 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # every product and sum rounded on its own, as written (no contraction to
-    # fused multiply-adds; explicit fma() calls stay): mirror-image states
-    # then give mirror-image results bit for bit (with contraction only the
-    # Riemann flux kept from fusing, the blast wave's y mirror still broke),
-    # and the rounding follows the oracle's operation by operation where the
-    # two write an expression alike.  About 3% of the step time on the star.
-    "-ffp-contract=off",
+    # contraction to fused multiply-adds only within one expression (FP_CONTRACT
+    # on; HIP's default "fast" mode fuses across statements and ignores the
+    # pragma below).  Where mirrored states exchange the roles of two terms --
+    # the Riemann flux of the two sides, the corner EMFs, the CT face update --
+    # the code switches contraction off with `#pragma clang fp contract(off)`,
+    # so a mirror-image state still gives mirror-image results bit for bit;
+    # everywhere else a fused product is one instruction instead of two.
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -165,13 +165,16 @@ __global__ __launch_bounds__(kMaxThreads) void k_bcc(const grmhd_block* __restri
 // ---------------------------------------------------------------------------
 // a2 + a3: flux through one face of direction D
 // ---------------------------------------------------------------------------
-template <int D, int RC>
-__device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
-                                          const GB& b, const Geo& q, int i, int j, int k,
-                                          double F[7]) {
+// a3 at the face of direction D below cell c0 (face index fi) from the
+// reconstructed states qL, qR (rho, W v^i, P, B^{t1}, B^{t2}; floored here,
+// so the caller's copies may be reused): face metric, Eq. 7-9 on both sides,
+// Riemann flux
+template <int D>
+__device__ __forceinline__ void face_solve(const Eos& e, const grmhd_params& p, const GB& b,
+                                           const Geo& q, int64_t c0, int64_t fi, double qL[7],
+                                           double qR[7], double F[7]) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
-  const int64_t c0 = cell(q, i, j, k);
   // metric at the face: 4th-order Lagrange (-1, 9, 9, -1)/16
   double gf[10];
 #pragma unroll
@@ -181,35 +184,9 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   }
   M3 m;
   metric_build(m, gf[4], gf[5], gf[6], gf[7], gf[8], gf[9]);
-  gptr<const double> bcc = b.scratch + off_bcc(q);
-  const int64_t nc = n_cells(q);
-  const gptr<const double> bt1 = bcc + T1 * nc;
-  const gptr<const double> bt2 = bcc + T2 * nc;
-  double qL[7], qR[7];
-  // Donor cell is also reached at run time in the high-order variants (where
-  // p.recon == RC, so it is never taken): with the reconstruction loop in a
-  // branch of its own the compiler keeps WENOZ at 152 VGPRs (3 waves per
-  // SIMD) instead of 244 (2 waves), and the flux kernels run ~12% faster.
-  if (RC == 0 || p.recon == 0) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      qL[v] = b.w[v][c0 - st];
-      qR[v] = b.w[v][c0];
-    }
-    qL[5] = bt1[c0 - st]; qR[5] = bt1[c0];
-    qL[6] = bt2[c0 - st]; qR[6] = bt2[c0];
-  } else {
-    gptr<const double> src[7] = {b.w[0], b.w[1], b.w[2], b.w[3], b.w[4], bt1, bt2};
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const gptr<const double> a = src[v];
-      recon_face<RC>(a[c0 - 3 * st], a[c0 - 2 * st], a[c0 - st], a[c0], a[c0 + st],
-                     a[c0 + 2 * st], qL[v], qR[v]);
-    }
-  }
   floor_face(e, p, qL);
   floor_face(e, p, qR);
-  const double Bn = b.bs[D][face<D>(q, i, j, k)] / m.sg;
+  const double Bn = b.bs[D][fi] / m.sg;
   double BL[3], BR[3];
   BL[D] = Bn; BR[D] = Bn;
   BL[T1] = qL[5]; BL[T2] = qL[6];
@@ -219,6 +196,51 @@ __device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
   side_state<D>(e, m, gf[0], beta, qL, BL, L);
   side_state<D>(e, m, gf[0], beta, qR, BR, R);
   riemann(p.riemann, L, R, F);
+}
+
+// the seven reconstructed fields of direction D: rho, W v^i, P, and the
+// cell-centred B^{t1}, B^{t2} of the field kernel
+template <int D>
+__device__ __forceinline__ void recon_sources(const GB& b, const Geo& q,
+                                              gptr<const double> src[7]) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  gptr<const double> bcc = b.scratch + off_bcc(q);
+  const int64_t nc = n_cells(q);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) src[v] = b.w[v];
+  src[5] = bcc + T1 * nc;
+  src[6] = bcc + T2 * nc;
+}
+
+template <int D, int RC>
+__device__ __forceinline__ void face_flux(const Eos& e, const grmhd_params& p,
+                                          const GB& b, const Geo& q, int i, int j, int k,
+                                          double F[7]) {
+  const int64_t st = D == 0 ? 1 : D == 1 ? (int64_t)q.sx : (int64_t)q.sx * q.sy;
+  const int64_t c0 = cell(q, i, j, k);
+  gptr<const double> src[7];
+  recon_sources<D>(b, q, src);
+  double qL[7], qR[7];
+  // Donor cell is also reached at run time in the high-order variants (where
+  // p.recon == RC, so it is never taken): with the reconstruction in a basic
+  // block of its own, ahead of the face metric's loads, the compiler keeps
+  // every ideal-gas variant at 122-124 VGPRs (4 waves per SIMD); scheduled
+  // in one block with the face solve it holds both at once (240 VGPRs).
+  if (RC == 0 || p.recon == 0) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      qL[v] = src[v][c0 - st];
+      qR[v] = src[v][c0];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const gptr<const double> a = src[v];
+      recon_face<RC>(a[c0 - 3 * st], a[c0 - 2 * st], a[c0 - st], a[c0], a[c0 + st],
+                     a[c0 + 2 * st], qL[v], qR[v]);
+    }
+  }
+  face_solve<D>(e, p, b, q, c0, face<D>(q, i, j, k), qL, qR, F);
 }
 
 template <int D, int ET, int RC>
@@ -410,6 +432,10 @@ __device__ __forceinline__ double face_emf(gptr<const double> sc, const Geo& q, 
 // cells x, x - e_A, x - e_Bx, x - e_A - e_Bx)
 template <int C>
 __device__ __forceinline__ double corner_emf(const GB& b, const Geo& q, const int x[3]) {
+  // no contraction to FMA: mirrored neighbourhoods exchange the roles of the
+  // terms, and every product and sum rounded as written keeps the corner
+  // EMF of a mirrored state the mirrored EMF bit for bit
+#pragma clang fp contract(off)
   constexpr int A = (C + 1) % 3, BX = (C + 2) % 3;
   gptr<const double> sc = b.scratch;
   // cells (a,b), (a-1,b), (a,b-1), (a-1,b-1)
@@ -470,6 +496,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_emf_corners(const grmhd_block* 
 template <int D>
 __device__ __forceinline__ void ct_face(const GB& b, const Geo& q, const int x[3], double dt,
                                         double a0, double a1, double bb) {
+#pragma clang fp contract(off)
   constexpr int D1 = (D + 1) % 3, D2 = (D + 2) % 3;
   gptr<const double> Ee = b.scratch + off_edge(q);
   const int64_t ne = n_edges(q);

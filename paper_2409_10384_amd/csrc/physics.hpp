@@ -243,8 +243,8 @@ __device__ __forceinline__ void side_state(const Eos& e, const M3& m, double alp
 // following the noise's sign.
 constexpr double kMassFluxZero = 1e-12;
 
-// No contraction to FMA (the whole library is built without it; this
-// function says so on its own): the two sides enter the flux formula as
+// No contraction to FMA in this function (elsewhere the library fuses
+// products within an expression): the two sides enter the flux formula as
 // mirror images (L <-> R with the normal components negated), and a fused
 // product keeps one side's product exact while the other's is rounded, so a
 // mirror-symmetric state would get fluxes that are not mirror images bit for
@@ -278,23 +278,32 @@ __device__ __forceinline__ void riemann(int kind, const Side& L, const Side& R, 
   if (fabs(F[0]) <= kMassFluxZero * scale) F[0] = 0.0;
 }
 
-// WENOZ value at the upper interface of cell c from cells c-2..c+2
-__device__ __forceinline__ double wenoz(double a, double b, double c, double d, double f) {
-  const double s0a = a - 2.0 * b + c, s0b = a - 4.0 * b + 3.0 * c;
-  const double s1a = b - 2.0 * c + d, s1b = b - d;
-  const double s2a = c - 2.0 * d + f, s2b = 3.0 * c - 4.0 * d + f;
-  const double k13 = 13.0 / 12.0;
-  const double be0 = k13 * s0a * s0a + 0.25 * s0b * s0b;
-  const double be1 = k13 * s1a * s1a + 0.25 * s1b * s1b;
-  const double be2 = k13 * s2a * s2a + 0.25 * s2b * s2b;
-  const double t5 = fabs(be0 - be2);
-  // the three ratios t5 / (beta_k + eps), each from a refined reciprocal of
-  // its own denominator (at least 1e-40, so no reciprocal overflows; one
-  // reciprocal of the product of the three would overflow for smoothness
-  // indicators beyond ~1e100)
-  const double r0 = t5 * rcp_nr(be0 + 1e-40);
-  const double r1 = t5 * rcp_nr(be1 + 1e-40);
-  const double r2 = t5 * rcp_nr(be2 + 1e-40);
+// WENOZ (reading R3).  The smoothness indicators are written so that the
+// mirror image of a stencil gives the same bits: the side stencils as
+// (near + far) - 2 mid and (3 near - 4 mid) + far, the centre one from the
+// sum and the difference of its outer cells.  (The value at the lower edge
+// of a cell is then the value at the upper edge of its mirror image.)
+
+// indicator of a side stencil: the cell itself (near), its neighbour (mid)
+// and the next cell (far)
+__device__ __forceinline__ double wz_beta_side(double near, double mid, double far) {
+  const double sa = (near + far) - 2.0 * mid;
+  const double sb = (3.0 * near - 4.0 * mid) + far;
+  return (13.0 / 12.0) * sa * sa + 0.25 * sb * sb;
+}
+
+// indicator of the centre stencil (l, c, r)
+__device__ __forceinline__ double wz_beta_mid(double l, double c, double r) {
+  const double sa = (l + r) - 2.0 * c;
+  const double sb = l - r;
+  return (13.0 / 12.0) * sa * sa + 0.25 * sb * sb;
+}
+
+// value at the edge of cell c on the side of f, from the cells a, b, c, d, f
+// in that order and the ratios r_k = tau5 / (beta_k + eps) of the stencils
+// (a, b, c), (b, c, d), (c, d, f)
+__device__ __forceinline__ double wz_edge(double r0, double r1, double r2, double a, double b,
+                                          double c, double d, double f) {
   const double w0 = 0.1 * (1.0 + r0 * r0);
   const double w1 = 0.6 * (1.0 + r1 * r1);
   const double w2 = 0.3 * (1.0 + r2 * r2);
@@ -302,6 +311,27 @@ __device__ __forceinline__ double wenoz(double a, double b, double c, double d, 
   const double p1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
   const double p2 = (2.0 * c + 5.0 * d - f) * (1.0 / 6.0);
   return (w0 * p0 + w1 * p1 + w2 * p2) * rcp_nr(w0 + w1 + w2);
+}
+
+// the ratios t5 / (beta_k + eps), each from a refined reciprocal of its own
+// denominator (at least 1e-40, so no reciprocal overflows; one reciprocal of
+// the product of the three would overflow for indicators beyond ~1e100)
+__device__ __forceinline__ void wz_ratios(double a, double b, double c, double d, double f,
+                                          double& r0, double& r1, double& r2) {
+  const double be0 = wz_beta_side(c, b, a);
+  const double be1 = wz_beta_mid(b, c, d);
+  const double be2 = wz_beta_side(c, d, f);
+  const double t5 = fabs(be0 - be2);
+  r0 = t5 * rcp_nr(be0 + 1e-40);
+  r1 = t5 * rcp_nr(be1 + 1e-40);
+  r2 = t5 * rcp_nr(be2 + 1e-40);
+}
+
+// value at the upper edge of cell c from cells c-2..c+2
+__device__ __forceinline__ double wenoz(double a, double b, double c, double d, double f) {
+  double r0, r1, r2;
+  wz_ratios(a, b, c, d, f, r0, r1, r2);
+  return wz_edge(r0, r1, r2, a, b, c, d, f);
 }
 
 // ---------------------------------------------------------------------------
