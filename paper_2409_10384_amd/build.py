@@ -21,7 +21,8 @@ HIPCC_FLAGS = [
     # the Riemann flux of the two sides, the corner EMFs, the CT face update --
     # the code switches contraction off with `#pragma clang fp contract(off)`,
     # so a mirror-image state still gives mirror-image results bit for bit;
-    # everywhere else a fused product is one instruction instead of two.
+    # everywhere else a fused product is one instruction instead of two
+    # (learned.hip opts out as a whole; its header says why).
     "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]

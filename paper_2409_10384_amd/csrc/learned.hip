@@ -5,6 +5,11 @@
 // The FP64 bracketed root solve of the paper's inversion always finishes:
 // the network only chooses the starting bracket; when that bracket holds no
 // sign change the full bracket is used (flag GRMHD_F_BRACKET_FALLBACK).
+// Built without contraction to fused multiply-adds (the rest of the library
+// fuses within expressions): with it the fused network + root-solve kernel
+// of the piecewise polytrope needs 258 registers (VGPRs + AGPRs) and drops
+// to one wave per SIMD.
+#pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
