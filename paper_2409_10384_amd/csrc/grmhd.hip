@@ -1943,8 +1943,10 @@ int prim2con(int64_t n, double* const w[5], double* const bt[3], double* const g
              const grmhd_params* p, void* stream) {
   int r = check_params(p);
   if (r) return r;
-  if (n < 0 || !w || !bt || !gam || !u) return GRMHD_EINVAL;
+  // an empty batch is valid whatever its (possibly NULL) pointers
+  if (n < 0) return GRMHD_EINVAL;
   if (n == 0) return GRMHD_OK;
+  if (!w || !bt || !gam || !u) return GRMHD_EINVAL;
   Ptrs5 pw, pu;
   Ptrs3 pb;
   Ptrs6 pg;
@@ -1964,9 +1966,11 @@ int c2p_batch(int64_t n, double* u[5], double* const bt[3], double* const gam[6]
               double* mu_out, int32_t* nev_out, void* stream) {
   int r = check_params(p);
   if (r) return r;
-  if (n < 0 || !u || !bt || !gam || !w || !flags) return GRMHD_EINVAL;
-  if (mlp) return c2p_batch_learned(n, u, bt, gam, w, flags, p, mlp, stats, mu_out, nev_out, stream);
+  // an empty batch is valid whatever its (possibly NULL) pointers
+  if (n < 0) return GRMHD_EINVAL;
   if (n == 0) return GRMHD_OK;
+  if (!u || !bt || !gam || !w || !flags) return GRMHD_EINVAL;
+  if (mlp) return c2p_batch_learned(n, u, bt, gam, w, flags, p, mlp, stats, mu_out, nev_out, stream);
   for (int v = 0; v < 5; ++v) if (!w[v] || !u[v]) return GRMHD_EINVAL;
   for (int v = 0; v < 3; ++v) if (!bt[v]) return GRMHD_EINVAL;
   for (int v = 0; v < 6; ++v) if (!gam[v]) return GRMHD_EINVAL;
@@ -2022,8 +2026,9 @@ int grmhd_timing_read(int32_t family, double* ms, int64_t* launches) {
 }
 
 int grmhd_copy(const double* src, double* dst, int64_t n, void* stream) {
-  if (!src || !dst || n < 0) return GRMHD_EINVAL;
+  if (n < 0) return GRMHD_EINVAL;
   if (n == 0) return GRMHD_OK;
+  if (!src || !dst) return GRMHD_EINVAL;
   k_copy<<<4096, kThreads, 0, (hipStream_t)stream>>>(src, dst, n);
   return last_err();
 }

@@ -622,8 +622,10 @@ int c2p_batch_learned(int64_t n, double* u[5], double* const bt[3], double* cons
                       c2p_stats* stats, double* mu_out, int32_t* nev_out, void* stream) {
   int r = check_params_host(p);
   if (r) return r;
-  if (n < 0 || !flags || !mlp || !mlp->w_bf16 || !mlp->w_f32) return GRMHD_EINVAL;
+  // an empty batch is valid whatever its (possibly NULL) pointers
+  if (n < 0) return GRMHD_EINVAL;
   if (n == 0) return GRMHD_OK;
+  if (!flags || !mlp || !mlp->w_bf16 || !mlp->w_f32) return GRMHD_EINVAL;
   P5 pu, pw;
   P3 pb;
   P6 pg;

@@ -64,6 +64,25 @@ def test_host_side_argument_checks_reject_bad_input():
     assert L.grmhd_scratch_doubles(n, n, n, g) == expect
 
 
+def test_empty_batches_are_valid_calls():
+    """n = 0 returns GRMHD_OK before anything else is looked at (an empty
+    tensor's pointers may be NULL); n < 0 is GRMHD_EINVAL.  Nothing is
+    launched either way, so no GPU is needed"""
+    from paper_2409_10384_amd import lib
+    L = lib.load()
+    p = lib.MethodParams().c()
+    N = None
+    assert L.c2p_batch(0, N, N, N, N, N, ctypes.byref(p), N, N, N, N, N) == 0
+    assert L.prim2con(0, N, N, N, N, ctypes.byref(p), N) == 0
+    assert L.grmhd_copy(N, N, 0, N) == 0
+    assert L.c2p_batch(-1, N, N, N, N, N, ctypes.byref(p), N, N, N, N, N) == -1
+    assert L.prim2con(-1, N, N, N, N, ctypes.byref(p), N) == -1
+    assert L.grmhd_copy(N, N, -1, N) == -1
+    # with n > 0 the missing arrays are refused
+    assert L.c2p_batch(4, N, N, N, N, N, ctypes.byref(p), N, N, N, N, N) == -1
+    assert L.grmhd_copy(N, N, 4, N) == -1
+
+
 def test_pointwise_block_calls_reject_missing_arrays():
     """grmhd_mass, grmhd_dt and grmhd_prim2con_blocks check the arrays their
     kernels read before launching anything (no GPU is touched)"""

@@ -286,3 +286,51 @@ def test_learned_stage_matches_plain_stage(G):
                 e = np.max(np.abs(ga[c][ok] - pa[c][ok])) / max(scale, 1e-300) if ok.any() else 0.0
                 assert e < 1e-10, (ib, name, c, e)
     say("  learned and plain stages agree on the star")
+
+
+@pytest.mark.parametrize("n", [1, 15, 17, 63, 65, 1000])
+def test_learned_c2p_on_ragged_lengths(G, n):
+    """lengths that leave the network's 16-state tiles and the 64-state waves
+    partly filled: the fused and the split learned paths return the exact
+    label's mu (1e-10, as the plain solve) with no unrecovered failure, and
+    the flags other than the bracket-fallback bit equal the plain solve's"""
+    say(f"learned C2P on {n} states (ragged tile and wave)")
+    net = _trained(G)
+    p = G.MethodParams(**C4P)
+    st, w, bt, gam, u = _c4_device(G, n, 310 + n)
+    eps = st["w"][4] / (2.0 / 3.0 * st["w"][0])
+    mus = 1.0 / ((1 + eps + st["w"][4] / st["w"][0]) * st["W"])
+    plain = G.c2p_batch(u.clone(), bt, gam, p, want_mu=True)
+    fp = plain["flags"].cpu().numpy().astype(np.uint16)
+    for split in (False, True):
+        out = G.c2p_batch_learned(u.clone(), bt, gam, p, net, want_mu=True, stats=True, split=split)
+        mu = out["mu"].cpu().numpy()
+        assert mu.shape == (n,)
+        assert np.max(np.abs(mu - mus) / mus) < 1e-10, split
+        fl = out["flags"].cpu().numpy().astype(np.uint16)
+        assert not np.any(fl & O.F_C2P_FAIL)
+        np.testing.assert_array_equal(fl & ~np.uint16(O.F_BRACKET_FALLBACK), fp)
+        stl = out["stats"].cpu().numpy()
+        assert stl[0] == n and stl[3] == 0
+
+
+def test_c2p_on_zero_states(G):
+    """an empty batch is a valid call: nothing launched, nothing returned"""
+    net = _trained(G)
+    p = G.MethodParams(**C4P)
+    e = lambda k: torch.empty((k, 0), dtype=torch.float64, device="cuda")
+    for out in (G.c2p_batch(e(5), e(3), e(6), p, want_mu=True),
+                G.c2p_batch_learned(e(5), e(3), e(6), p, net, want_mu=True),
+                G.c2p_batch_learned(e(5), e(3), e(6), p, net, want_mu=True, split=True)):
+        torch.cuda.synchronize()
+        assert out["w"].shape == (5, 0) and out["mu"].shape == (0,)
+
+
+_NET = {}
+
+
+def _trained(G):
+    """one trained network for the tests that only use it (trained once)"""
+    if "net" not in _NET:
+        _NET["net"], _ = train_network(G, steps=600)
+    return _NET["net"]

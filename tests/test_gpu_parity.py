@@ -99,6 +99,22 @@ def test_c2p_batch_parity_wide_ranges(G):
     assert e_r.max() < 1e-12 and e_u.max() < 1e-12 and e_p.max() < 1e-12
 
 
+@pytest.mark.parametrize("n", [1, 63, 65, 4097])
+def test_c2p_batch_parity_ragged_lengths(G, n):
+    """batches that end inside a wave: the same flags as the oracle and mu
+    to 2e-12 in every state, the last one included"""
+    say(f"c2p_batch parity: {n} states")
+    st = inputs.c2p_states(n, seed_offset=400 + n)
+    p = O.Params(gamma=5.0 / 3.0, rho_atm=1e-20, T_atm=1e-30, M_max=1e30, c2p_tol=1e-12)
+    u = O.prim2con(st["w"], st["bt"], st["gam"], p)
+    _, wref, fref, nref, muref = O.c2p(u, st["bt"], st["gam"], p)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    out = G.c2p_batch(d(u), d(st["bt"]), d(st["gam"]), to_mp(G, p), want_mu=True)
+    np.testing.assert_array_equal(host(out["flags"]).astype(np.uint16), fref)
+    mu = host(out["mu"])
+    assert mu.shape == (n,) and np.max(np.abs(mu - muref) / muref) < 2e-12
+
+
 def test_c2p_batch_parity_hybrid_eos(G):
     """piecewise polytrope + thermal part: same flags, mu to 2e-12, the
     primitives within the conditioning of the root.  Densities up to
