@@ -778,7 +778,8 @@ def c2p_section(args, torch, inputs, lib, eos="ideal"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    # the star workload is 20 RK2 steps (after the warm-up steps)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--blocks-per-side", type=int, default=4)
     ap.add_argument("--block", type=int, default=64)
