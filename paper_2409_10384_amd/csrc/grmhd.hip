@@ -254,7 +254,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_flux(const grmhd_block* __restr
   const Geo q = geo_of(b);
   const Box bx = face_box<D>(q);
   int i, j, k;
-  bx.at(t, i, j, k);
+  if (D == 2) {
+    // z faces run x fastest, then z, then y: a face's z stencil (three
+    // planes each way) then lies in the waves just before and after it,
+    // whose loads are still in L2, instead of planes apart
+    i = bx.lo[0] + (int)(t % bx.cnt[0]);
+    const int64_t r = t / bx.cnt[0];
+    k = bx.lo[2] + (int)(r % bx.cnt[2]);
+    j = bx.lo[1] + (int)(r / bx.cnt[2]);
+  } else {
+    bx.at(t, i, j, k);
+  }
   double F[7];
   face_flux<D, RC>(e, p, b, q, i, j, k, F);
   const int64_t f = face<D>(q, i, j, k);
