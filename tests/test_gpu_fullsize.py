@@ -7,7 +7,8 @@ interior cell of every block is compared, gated on the FOFC and floor
 decisions as in the small star tests.  A second test shows that the step does
 not depend on the launch configuration: the row layout at workgroup size 256,
 the brick layout of the update, and the benchmark's sizes give bitwise equal
-states."""
+states.  A third checks the batched-stage workload at its full size (1500
+blocks of three sizes on six levels) on a seeded sample of its blocks."""
 import numpy as np
 import pytest
 
@@ -112,3 +113,75 @@ def test_brick_update_on_uneven_blocks(G):
         for d in range(3):
             assert torch.equal(gm.b0[i][d], gb.b0[i][d]), (i, d)
     _compare_state(om, gb, 0, 2e-12, "brick step")
+
+
+# workgroup sizes the autotuner picks for the 1500-block list on MI355X
+REFINED_SIZES = {"flux_x": 64, "flux_y": 64, "flux_z": 64, "fofc_flags": 64, "fofc_fix": 64,
+                 "ct": 256, "update": 512, "stage_c2p": 256}
+
+
+def test_refined_full_list_sampled_parity(G):
+    """the batched-stage workload at its full size: 1500 independent blocks
+    of 16^3, 24^3 and 32^3 on six levels (ghosts frozen at the analytic
+    data), every kernel launched once over the whole list at the autotuner's
+    workgroup sizes, one RK2 step.  A seeded sample of 24 blocks (every size
+    and level present) against the oracle stepping those blocks alone: each
+    block reads only its own frozen ghosts, so the oracle's answer is the one
+    the full list must give.  Gate as for the chained step of the star tests
+    (1e-11 of the oracle's term magnitudes; a block whose decisions went the
+    other way at a threshold is reported and left out)."""
+    import copy
+
+    import bench
+    import oracle as O
+    from paper_2409_10384_amd import autotune, inputs
+    from tests import stage_parity as SP
+    from tests.test_gpu_parity import _download, to_mp
+    blocks, _ = inputs.refined_star_blocks(device="cuda")
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    say(f"refined star at full size: {len(blocks)} blocks, {ncell} cells, 1 RK2 step; 24 sampled blocks")
+    rng = np.random.default_rng(4242)
+    by = {}
+    for i, b in enumerate(blocks):
+        by.setdefault((b.nx, b.level), []).append(i)
+    picks = {int(rng.choice(v)) for v in by.values()}
+    rest = [i for i in range(len(blocks)) if i not in picks]
+    picks = sorted(picks | {int(i) for i in rng.choice(rest, size=24 - len(picks), replace=False)})
+    sub = [bench._block_numpy(blocks[i]) for i in picks]
+    om = O.Mesh(copy.deepcopy(sub), STAR_P)
+    dt = om.dt(0.25)
+    _set_sizes(REFINED_SIZES)
+    try:
+        gm = G.DeviceMesh(blocks, to_mp(G, STAR_P), device="cuda")
+        for src, dst, (a0, a1, b) in O.Mesh.RK2:
+            gm.stage_sets(src, dst, (a0, a1, b), dt=dt)
+            gm.ghost_fill(dst)
+        torch.cuda.synchronize()
+    finally:
+        autotune.reset()
+    tu = tb = None
+    for src, dst, (a0, a1, b) in O.Mesh.RK2:
+        tu, tb = om.stage_sets(src, dst, dt, a0, a1, b, term_scales=True)
+        om.ghost_fill_state(dst)
+    worst = {}
+
+    def note(key, e):
+        worst[key] = max(worst.get(key, 0.0), e)
+
+    compared = nflag = 0
+    for k, ib in enumerate(picks):
+        blk = om.blocks[k]
+        ref = SP._outputs(om, 0, k)
+        dev = _download(gm, 0, ib)
+        nflag += int(np.sum(ref[3] != 0))
+        if np.any(dev[3] != ref[3]):
+            say(f"  block {ib}: decisions differ in {int(np.sum(dev[3] != ref[3]))} cells")
+            continue
+        TU = np.array(om.interior(tu[k], k))
+        TB = [tb[k][d][SP._face_slices(blk, d)] for d in range(3)]
+        SP.compare_block(om, k, ref, dev, TU, TB, np.ones(ref[3].shape, bool),
+                         [np.ones(f.shape, bool) for f in ref[2]], note)
+        compared += 1
+    w = max(worst.values())
+    say(f"  {compared} of {len(picks)} sampled blocks compared, gated {w:.1e}; flagged cells {nflag}")
+    assert compared >= 20 and w < 1e-11, worst
