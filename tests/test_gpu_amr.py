@@ -10,7 +10,10 @@ against the oracle's (or_ghost_fill_amr, or_stage_amr), through the C ABI:
   1e-9 of a threshold may differ), on both meshes, FOFC+DMP on;
 * the device on its own through RK2 steps in flat space: all five totals
   conserved to round-off, div B~ at round-off in every cell, coarse faces on
-  level boundaries equal to the mean of the fine faces."""
+  level boundaries equal to the mean of the fine faces;
+* the star on its leaf meshes: both stages from a common input at 8^3
+  blocks, and one RK2 step of the end-to-end workload's full mesh (736
+  leaves of 32^3, piecewise polytrope) against the oracle's."""
 import copy
 import dataclasses
 
@@ -187,3 +190,53 @@ def test_star_on_a_leaf_mesh_stage_parity(G):
     summary = SP.stage_parity(gm, om, O.Mesh.RK2, dt, tol=1e-12, margin=1e-9, say=say, upload=_upload,
                               download=_download)
     assert len(summary) == 2
+
+
+def test_star_leaf_mesh_full_size_step(G):
+    """the end-to-end workload's mesh at its full size: the star with the
+    seeded piecewise polytrope on 736 leaves of 32^3 over four levels, one
+    RK2 step on the device (ghost fills across levels between the stages,
+    flux and EMF correction) against the oracle's step of the whole mesh,
+    every leaf, gated at 1e-11 of the oracle's term magnitudes (as the
+    chained step of the star tests; a leaf whose decisions went the other way
+    at a threshold is reported and left out)"""
+    pp, K = inputs.pp_eos()
+    st = inputs.calibrate_field(inputs.StarSetup(pp=pp, pp_K=K))
+    blocks, m, st = inputs.star_leaf_blocks(st=st)
+    p = dataclasses.replace(STAR_P, **pp)
+    ncell = sum(b.nx * b.ny * b.nz for b in blocks)
+    say(f"star leaf mesh at full size: {len(blocks)} leaves of 32^3, {ncell} cells, 1 RK2 step")
+    gm = G.RefinedDeviceMesh(blocks, to_mp(G, p), m)
+    om = O.RefinedMesh(blocks, p, m)
+    om.ghost_fill_state(0)
+    gm.ghost_fill(0)
+    dt = om.dt(0.25)
+    for src, dst, (a0, a1, b) in O.Mesh.RK2:
+        gm.stage_sets(src, dst, (a0, a1, b), dt=dt)
+        gm.ghost_fill(dst)
+    torch.cuda.synchronize()
+    tu = tb = None
+    for src, dst, (a0, a1, b) in O.Mesh.RK2:
+        tu, tb = om.stage_sets(src, dst, dt, a0, a1, b, term_scales=True)
+        om.ghost_fill_state(dst)
+    worst = {}
+
+    def note(key, e):
+        worst[key] = max(worst.get(key, 0.0), e)
+
+    compared = nflag = 0
+    for ib, blk in enumerate(om.blocks):
+        ref = SP._outputs(om, 0, ib)
+        dev = _download(gm, 0, ib)
+        nflag += int(np.sum(ref[3] != 0))
+        if np.any(dev[3] != ref[3]):
+            say(f"  leaf {ib}: decisions differ in {int(np.sum(dev[3] != ref[3]))} cells")
+            continue
+        TU = np.array(om.interior(tu[ib], ib))
+        TB = [tb[ib][d][SP._face_slices(blk, d)] for d in range(3)]
+        SP.compare_block(om, ib, ref, dev, TU, TB, np.ones(ref[3].shape, bool),
+                         [np.ones(f.shape, bool) for f in ref[2]], note)
+        compared += 1
+    w = max(worst.values())
+    say(f"  {compared} of {len(om.blocks)} leaves compared, gated {w:.1e}; flagged cells {nflag}")
+    assert compared >= len(om.blocks) - 8 and w < 1e-11, worst
