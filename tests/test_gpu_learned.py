@@ -334,3 +334,37 @@ def _trained(G):
     if "net" not in _NET:
         _NET["net"], _ = train_network(G, steps=600)
     return _NET["net"]
+
+
+def test_c2p_full_size_sampled_parity(G):
+    """the learned-inversion workload at its full size: 2^24 states (the
+    benchmark's states), plain and learned (fused) inversions over all of
+    them in one launch each; a seeded sample of 65536 states against the
+    oracle's inversion of the same states: the plain solve's flags equal and
+    mu to 2e-12, the learned solve's flags equal but for the bracket-fallback
+    bit and its mu to 2e-12 of the oracle's, no unrecovered failure"""
+    n = 1 << 24
+    say(f"C2P at full size: {n} states, plain and learned; 65536 sampled against the oracle")
+    net = _trained(G)
+    p = G.MethodParams(**C4P)
+    s = inputs.c2p_states_torch(n, seed_offset=3, device="cuda")
+    u = G.prim2con(s["w"], s["bt"], s["gam"], p)
+    plain = G.c2p_batch(u.clone(), s["bt"], s["gam"], p, want_mu=True)
+    learned = G.c2p_batch_learned(u.clone(), s["bt"], s["gam"], p, net, want_mu=True, stats=True)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(np.sort(np.random.default_rng(777).choice(n, size=1 << 16, replace=False)),
+                          device="cuda")
+    h = lambda t: np.ascontiguousarray(t[:, idx].cpu().numpy())
+    po = O.Params(**C4P)
+    _, wref, fref, nref, muref = O.c2p(h(u), h(s["bt"]), h(s["gam"]), po)
+    fp = plain["flags"][idx].cpu().numpy().astype(np.uint16)
+    fl = learned["flags"][idx].cpu().numpy().astype(np.uint16)
+    mp = plain["mu"][idx].cpu().numpy()
+    ml = learned["mu"][idx].cpu().numpy()
+    np.testing.assert_array_equal(fp, fref)
+    np.testing.assert_array_equal(fl & ~np.uint16(O.F_BRACKET_FALLBACK), fref)
+    ep = np.max(np.abs(mp - muref) / muref)
+    el = np.max(np.abs(ml - muref) / muref)
+    say(f"  sampled mu against the oracle: plain {ep:.1e}, learned {el:.1e}")
+    assert ep < 2e-12 and el < 2e-12
+    assert int(learned["stats"][3].item()) == 0
