@@ -216,8 +216,8 @@ def _compare_state(om, gm, which, tol, label):
 def test_flux_parity_smooth_block(G, scale):
     """scale multiplies rho and P (and B by its square root, so every
     velocity is unchanged): at 1e120 the WENOZ smoothness indicators reach
-    ~1e240 and the product of three of them overflows, which the kernel's
-    one-reciprocal form must detect"""
+    ~1e240, where the product of three of them would overflow; the kernel
+    takes one refined reciprocal per indicator and must stay exact there"""
     say(f"flux parity: smooth periodic block 32^3, rho and P scaled by {scale:g}")
     blk = inputs.smooth_periodic_block(n=32)
     if scale != 1.0:
