@@ -24,6 +24,10 @@ HIPCC_FLAGS = [
     # everywhere else a fused product is one instruction instead of two
     # (learned.hip opts out as a whole; its header says why).
     "-ffp-contract=on",
+    # matrix-core results in ordinary VGPRs: the network's activations then
+    # read them directly instead of one v_accvgpr_read per value (only
+    # learned.hip has MFMA code)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -1209,15 +1209,19 @@ __global__ __launch_bounds__(kThreads) void k_prim2con(int64_t n, Ptrs5 w, Ptrs3
 template <int ET>
 __global__ __launch_bounds__(kThreads) void k_c2p_batch(int64_t n, Ptrs5 u, Ptrs3 bt, Ptrs6 gm,
                                                         Ptrs5 w, uint16_t* flags, Eos e_in,
-                                                        grmhd_params p, const double* blo,
+                                                        grmhd_params p_in, const double* blo,
                                                         const double* bhi, double* mu_out,
                                                         int32_t* nev_out, c2p_stats* stats) {
-  const Eos e = eos_fixed<ET>(e_in);
+  const Eos e0 = eos_fixed<ET>(e_in);
+  const grmhd_params p0 = p_in;
   unsigned long long c_n = 0, c_ev = 0, c_fb = 0, c_fail = 0;
   // grid-stride loop: each lane keeps its statistics until the end, so the
   // atomics are per wave of a bounded grid, not per 64 states
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x) {
+    Eos e = e0;
+    grmhd_params p = p0;
+    consts_per_pass(e, p);
     C2PWork cw;
     double ww[5];
     {

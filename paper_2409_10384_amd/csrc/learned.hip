@@ -97,11 +97,12 @@ struct WaveLoop {
 // ---------------------------------------------------------------------------
 template <int ET>
 __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 gm, P5 wout,
-                                                    uint16_t* flags, Eos e_in, grmhd_params p,
+                                                    uint16_t* flags, Eos e_in, grmhd_params p_in,
                                                     const uint16_t* wh, const float* wf, Feat ft,
                                                     float width_k, float width_min, double* mu_out,
                                                     int32_t* nev_out, c2p_stats* stats) {
-  const Eos e = eos_fixed<ET>(e_in);
+  const Eos e0 = eos_fixed<ET>(e_in);
+  const grmhd_params p0 = p_in;
   __shared__ MlpLds s;
   mlp_load(s, wh, wf);
   __syncthreads();
@@ -111,6 +112,9 @@ __global__ __launch_bounds__(kT) void k_c2p_learned(int64_t n, P5 u, P3 bt, P6 g
   for (int64_t base = wl.first; base < n; base += wl.stride) {
     const int64_t t = base + l;
     const bool live = t < n;
+    Eos e = e0;
+    grmhd_params p = p0;
+    consts_per_pass(e, p);
     double w[5];
     C2PWork cw;
     float x[5] = {0.f, 0.f, 0.f, 0.f, 0.f};

@@ -10,6 +10,10 @@
 //   A (16x16, rows x k):  A[l % 16][4 (l / 16) + e]
 //   B (16x16, k x cols):  B[4 (l / 16) + e][l % 16]
 //   D (16x16, rows x cols): D[4 (l / 16) + e][l % 16]
+// The inference pass takes its 64-deep layers in 32-deep steps of
+// v_mfma_f32_16x16x32_bf16 (8 bf16 of A and of B per lane, same D fragment):
+// a lane's 8 k-slots are the same in A and B, so which neuron sits in which
+// slot is free as long as both operands agree.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -148,23 +152,45 @@ __device__ __forceinline__ void mlp_out(const uint16_t* in, const uint16_t* W4, 
 // activations the B operand (k = input neuron, column = state).  The MFMA
 // result D[4 (l / 16) + e][l % 16] (neuron, state) is then exactly the B
 // fragment of the next layer's k-step, so activations never leave the
-// registers.  Lane l contributes its own state's 5 features x and receives
-// (y0, y1) of its own state.  All 64 lanes must call this together.
+// registers.  A 32-deep step joins two such fragments: slots 0..3 of lane
+// group q hold neurons 32 s + 4 q + e, slots 4..7 neurons 32 s + 16 + 4 q + e,
+// and the weight fragment reads the same two column groups.  Lane l
+// contributes its own state's 5 features x and receives (y0, y1) of its own
+// state.  All 64 lanes must call this together.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 
 // activation of an MFMA output fragment (bias already in the accumulator),
-// packed to bf16 two values per conversion
+// packed to bf16 two values per conversion (one v_cvt_pk_bf16_f32 per pair;
+// a 4-wide conversion is split by the compiler into one per value plus
+// byte permutes)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  const f32x2 h = {act_f(a), act_f(b)};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(h, bf16x2v));
+}
 __device__ __forceinline__ bf16x4 act_frag(f32x4 acc) {
-  f32x4 h;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) h[e] = act_f(acc[e]);
-  return __builtin_bit_cast(bf16x4, __builtin_convertvector(h, bf16x4v));
+  const u32x2 r = {bf16_pair(acc[0], acc[1]), bf16_pair(acc[2], acc[3])};
+  return __builtin_bit_cast(bf16x4, r);
 }
 
 // accumulator start: the biases of this lane's 4 fragment rows (neurons)
 __device__ __forceinline__ f32x4 bias_frag(const float* bias) {
   return *(const f32x4*)bias;
+}
+
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+// two 4-wide fragments as the 8 k-slots of one 32-deep step
+__device__ __forceinline__ bf16x8v cat8(bf16x4 a, bf16x4 b) {
+  const s16x8 r = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  return __builtin_bit_cast(bf16x8v, r);
+}
+// weight columns c + 0..3 and c + 16..19 of one row: the neurons of cat8
+__device__ __forceinline__ bf16x8v ld8(const uint16_t* p) { return cat8(ld4(p), ld4(p + 16)); }
+__device__ __forceinline__ f32x4 mfma32(bf16x8v a, bf16x8v b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], float& y0, float& y1) {
@@ -198,21 +224,24 @@ __device__ __forceinline__ void mlp_wave(const MlpLds& w, const float x[5], floa
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = bias_frag(w.b2 + nt * 16 + 4 * q);
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        acc = mfma16(ld4(w.W2 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h1[ks], acc);
+      for (int ks = 0; ks < 2; ++ks)
+        acc = mfma32(ld8(w.W2 + (nt * 16 + r) * kLdH + ks * 32 + 4 * q),
+                     cat8(h1[2 * ks], h1[2 * ks + 1]), acc);
       h2[nt] = act_frag(acc);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = bias_frag(w.b3 + nt * 16 + 4 * q);
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        acc = mfma16(ld4(w.W3 + (nt * 16 + r) * kLdH + ks * 16 + 4 * q), h2[ks], acc);
+      for (int ks = 0; ks < 2; ++ks)
+        acc = mfma32(ld8(w.W3 + (nt * 16 + r) * kLdH + ks * 32 + 4 * q),
+                     cat8(h2[2 * ks], h2[2 * ks + 1]), acc);
       h1[nt] = act_frag(acc);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) acc = mfma16(ld4(w.W4 + r * kLdH + ks * 16 + 4 * q), h1[ks], acc);
+    for (int ks = 0; ks < 2; ++ks)
+      acc = mfma32(ld8(w.W4 + r * kLdH + ks * 32 + 4 * q), cat8(h1[2 * ks], h1[2 * ks + 1]), acc);
     // rows 0 and 1 (lanes 0..15, e = 0, 1) hold the two outputs of state 16 t + r
     const float o0 = __shfl(acc[0], r, 64), o1 = __shfl(acc[1], r, 64);
     if (q == t) {

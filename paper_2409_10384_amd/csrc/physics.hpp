@@ -676,6 +676,8 @@ __device__ __forceinline__ C2PWork c2p_prepare(const Eos& e, const grmhd_params&
     cw.fl = finite ? GRMHD_F_DFLOOR : GRMHD_F_C2P_FAIL;
     cw.done = true;
     cw.k.D = 1.0; cw.k.q = 0.0; cw.k.r2 = 0.0; cw.k.b2 = 0.0; cw.k.s = 0.0; cw.k.v0sq = 0.0;
+    cw.ru[0] = cw.ru[1] = cw.ru[2] = 0.0;   // defined on every path: in a loop over
+    cw.bu[0] = cw.bu[1] = cw.bu[2] = 0.0;   // states, undefined ones get carried across passes
     return cw;
   }
   if (B2 / D > p.M_max) {
@@ -703,6 +705,16 @@ __device__ __forceinline__ C2PWork c2p_prepare(const Eos& e, const grmhd_params&
   const double z2 = k.r2;      // z0 = r/h0 with h0 = 1
   k.v0sq = z2 / (1.0 + z2);
   return cw;
+}
+
+// For a loop over states: the EOS and parameter fields that the ideal-gas
+// inversion reads, marked as redefined at the top of every pass (an empty
+// asm on their scalar registers).  Otherwise the compiler hoists the FP64
+// constants derived from them out of the loop into vector registers that
+// stay live across the root solve (about 24 VGPRs: one wave per SIMD less).
+__device__ __forceinline__ void consts_per_pass(Eos& e, grmhd_params& p) {
+  __asm__ volatile("" : "+s"(e.gam), "+s"(e.gth), "+s"(p.rho_atm), "+s"(p.T_atm), "+s"(p.f_thr),
+                   "+s"(p.M_max), "+s"(p.c2p_tol), "+s"(p.c2p_maxit));
 }
 
 // Root solve, recovery, primitive floors and the failure policy.  With
